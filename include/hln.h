@@ -1,0 +1,138 @@
+/*
+ * hln.h -- C ABI of the MI355X (gfx950) library for exact closeness
+ * centrality on homogeneous multilayer networks (HoMLNs).
+ *
+ * Paper: "Closeness Centrality Detection in Homogeneous Multilayer
+ * Networks" (arXiv 2207.11662).  Problem Statement (Sec. 1): given layers
+ * G_1(V,E_1) ... G_l(V,E_l) over one vertex set, find the closeness
+ * centrality (CC) nodes of the Boolean AND aggregate of any r <= l layers;
+ * each layer is analysed once (the Psi step) and partial results are
+ * composed (the Theta step).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers marked [dev] are device pointers on the current HIP device;
+ *    [host] pointers are host memory.  The caller owns every buffer.  No
+ *    entry point allocates device memory: scratch comes from a caller
+ *    workspace whose size the matching *_workspace_size query returns
+ *    (256-byte aligned base required).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls are asynchronous and stream-ordered; results are valid after the
+ *    stream is synchronised.  Results are deterministic.
+ *  - Graphs are CSR over int32 vertex ids: row_ptr[n+1], col_idx[nnz],
+ *    nnz = 2 * (undirected edges).  Layers must be symmetric, rows sorted
+ *    ascending, no self-loops, no duplicate arcs (Sec. 1: simple undirected
+ *    graphs); hln_csr_from_edges produces this form, hln_csr_validate checks
+ *    it.
+ *  - Every call returns an hln_status.  On an error nothing has been
+ *    enqueued and no output has been written; hln_last_error() returns a
+ *    thread-local message.  Argument checks that need no device data run on
+ *    the host before anything is enqueued.  Faults detected by a kernel
+ *    (e.g. a bounded wait that ran out) are reported as HLN_EDEVICE by the
+ *    next call that synchronises (hln_device_status).
+ */
+#ifndef HLN_H
+#define HLN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HLN_OK = 0,
+    HLN_EINVAL = 1,        /* bad argument (null pointer, size, id range, mode) */
+    HLN_ENOMEM = 2,        /* workspace or output capacity too small */
+    HLN_EDEVICE = 3,       /* HIP runtime error or device-side fault */
+    HLN_EUNSUPPORTED = 4   /* valid request outside what this build supports */
+} hln_status;
+
+/* A graph in device memory (see conventions).  n and nnz are host values. */
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    const int32_t* row_ptr;   /* [dev] n+1 */
+    const int32_t* col_idx;   /* [dev] nnz */
+} hln_csr;
+
+/* Source-batch width and traversal direction of the bit-parallel BFS. */
+typedef struct {
+    int32_t width_bits;   /* sources per batch: 64, 128, 256, 512, 1024 or 2048; 0 = library default (512) */
+    int32_t direction;    /* 0 = automatic per level, 1 = top-down only, 2 = bottom-up only */
+    int32_t flags;        /* reserved, must be 0 */
+} hln_opts;
+
+/* Thread-local text of the last error of this thread ("" if none). */
+const char* hln_last_error(void);
+
+/* Library version, e.g. 0x000100 for 0.1.0. */
+int32_t hln_version(void);
+
+/* Number of compute units of the current device (0 on error). */
+int32_t hln_device_cu_count(void);
+
+/* Synchronises `stream` and reports a device-side fault recorded by the
+ * library's kernels since the last call (HLN_EDEVICE), else HLN_OK. */
+hln_status hln_device_status(void* stream);
+
+/* ------------------------------------------------------------------------
+ * Layer ingest (Sec. 1, Problem Statement; Sec. 4: undirected layers).
+ * ------------------------------------------------------------------------
+ * hln_csr_from_edges: normalised symmetric CSR from an arbitrary edge list
+ * eu[i]--ev[i], i < m (either orientation, duplicates and self-loops
+ * allowed: self-loops are dropped, duplicates merged, both arcs of every
+ * edge emitted, rows sorted).  row_ptr [dev] n+1 and col_idx [dev] with room
+ * for 2*m entries are outputs; the arc count is row_ptr[n].  Ids outside
+ * [0, n) are a device-side fault (HLN_EDEVICE at hln_device_status) and
+ * leave the outputs unspecified.  n >= 1, 0 <= m <= 2^30. */
+size_t hln_csr_from_edges_workspace_size(int32_t n, int64_t m);
+hln_status hln_csr_from_edges(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev,
+                              int32_t* row_ptr, int32_t* col_idx,
+                              void* workspace, size_t workspace_bytes, void* stream);
+
+/* hln_csr_validate: checks the CSR conventions on the device and writes a
+ * bit mask to *result [dev] (0 = valid): 1 row_ptr not monotone or
+ * row_ptr[0] != 0 or row_ptr[n] != nnz, 2 id out of range, 4 row not
+ * strictly ascending (duplicate or unsorted), 8 self-loop, 16 asymmetric
+ * (arc u->v without v->u). */
+hln_status hln_csr_validate(const hln_csr* g, int32_t* result, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Boolean aggregation of r layers (Sec. 3.1; ground truth, Sec. 4).
+ * ------------------------------------------------------------------------
+ * AND keeps an edge present in every layer, OR one present in at least one
+ * layer.  layers [host] array of r graphs with equal n; out_row_ptr [dev]
+ * n+1, out_col_idx [dev] with `capacity` entries; the arc count is
+ * out_row_ptr[n].  capacity must be >= min nnz (AND) or >= sum nnz (OR),
+ * else HLN_ENOMEM.  1 <= r <= 64. */
+size_t hln_compose_workspace_size(int32_t n, int32_t r);
+hln_status hln_compose_and(const hln_csr* layers, int32_t r, int32_t* out_row_ptr, int32_t* out_col_idx,
+                           int64_t capacity, void* workspace, size_t workspace_bytes, void* stream);
+hln_status hln_compose_or(const hln_csr* layers, int32_t r, int32_t* out_row_ptr, int32_t* out_col_idx,
+                          int64_t capacity, void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Exact closeness of one graph (Sec. 4, Eq. 1 with the Wasserman-Faust
+ * normalisation used for disconnected graphs; one BFS per source).
+ * ------------------------------------------------------------------------
+ * sources [dev] NULL: every vertex is a source and the outputs are indexed
+ *   by vertex (n_src must equal n).  Otherwise n_src distinct vertex ids and
+ *   the outputs are indexed by position in `sources`.
+ * S  [dev] int64: sum of hop distances to the reachable vertices.
+ * R  [dev] int32: number of reachable vertices, the source included.
+ * cc [dev] double, nullable: ((R-1)/S) * ((R-1)/(n-1)) rounded in that
+ *   order (IEEE division), 0 when R <= 1 or n <= 1.
+ * h2 [dev] int32, nullable: vertices at distance exactly 2.
+ * opts [host] nullable (defaults).  0 <= n_src; n >= 1. */
+size_t hln_closeness_workspace_size(int32_t n, int64_t nnz, int32_t n_src, const hln_opts* opts);
+hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t n_src, const hln_opts* opts,
+                               int64_t* S, int32_t* R, double* cc, int32_t* h2,
+                               void* workspace, size_t workspace_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HLN_H */

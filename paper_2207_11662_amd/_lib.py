@@ -1,0 +1,160 @@
+"""ctypes binding of ``libhln.so`` (the C ABI declared in ``include/hln.h``).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+PyTorch provides device memory (tensors) and the stream
+(``torch.cuda.current_stream()``).  If the library has not been built the
+first call raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhln.so")
+
+HLN_OK, HLN_EINVAL, HLN_ENOMEM, HLN_EDEVICE, HLN_EUNSUPPORTED = 0, 1, 2, 3, 4
+_STATUS = {0: "HLN_OK", 1: "HLN_EINVAL", 2: "HLN_ENOMEM", 3: "HLN_EDEVICE", 4: "HLN_EUNSUPPORTED"}
+
+# every symbol include/hln.h declares (checked by the tests)
+EXPORTS = [
+    "hln_last_error", "hln_version", "hln_device_cu_count", "hln_device_status",
+    "hln_csr_from_edges_workspace_size", "hln_csr_from_edges", "hln_csr_validate",
+    "hln_compose_workspace_size", "hln_compose_and", "hln_compose_or",
+    "hln_closeness_workspace_size", "hln_closeness_layer",
+]
+
+
+class HlnError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_STATUS.get(status, str(status)), msg))
+        self.status = status
+
+
+class hln_csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p)]
+
+
+class hln_opts(ctypes.Structure):
+    _fields_ = [("width_bits", ctypes.c_int32), ("direction", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libhln.so is not built (run `python -m paper_2207_11662_amd.build`); "
+                          "there is no non-HIP fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    st = ctypes.c_int
+    csr_p, opts_p = ctypes.POINTER(hln_csr), ctypes.POINTER(hln_opts)
+    sig = {
+        "hln_last_error": ([], ctypes.c_char_p),
+        "hln_version": ([], i32),
+        "hln_device_cu_count": ([], i32),
+        "hln_device_status": ([P], st),
+        "hln_csr_from_edges_workspace_size": ([i32, i64], sz),
+        "hln_csr_from_edges": ([i32, i64, P, P, P, P, P, sz, P], st),
+        "hln_csr_validate": ([csr_p, P, P], st),
+        "hln_compose_workspace_size": ([i32, i32], sz),
+        "hln_compose_and": ([csr_p, i32, P, P, i64, P, sz, P], st),
+        "hln_compose_or": ([csr_p, i32, P, P, i64, P, sz, P], st),
+        "hln_closeness_workspace_size": ([i32, i64, i32, opts_p], sz),
+        "hln_closeness_layer": ([csr_p, P, i32, opts_p, P, P, P, P, P, sz, P], st),
+    }
+    for name, (args, res) in sig.items():
+        if hasattr(L, name):
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+    _lib = L
+    return L
+
+
+def check(status: int):
+    if status != HLN_OK:
+        msg = lib().hln_last_error()
+        raise HlnError(status, msg.decode() if msg else "")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def workspace(nbytes: int, device=None) -> torch.Tensor:
+    """Caller-owned scratch; the caching allocator returns 512-byte aligned blocks."""
+    t = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device or "cuda")
+    if t.data_ptr() % 256:
+        raise HlnError(HLN_EINVAL, "workspace tensor is not 256-byte aligned")
+    return t
+
+
+class Graph:
+    """A CSR graph in device memory (int32 row_ptr[n+1], col_idx[nnz]).
+
+    nnz is the host-side arc count, or an upper bound on it when the graph
+    was produced asynchronously (the kernels read the exact count from
+    row_ptr[n])."""
+
+    def __init__(self, row_ptr: torch.Tensor, col_idx: torch.Tensor, nnz: int | None = None):
+        assert row_ptr.dtype == torch.int32 and col_idx.dtype == torch.int32
+        assert row_ptr.is_cuda and col_idx.is_cuda and row_ptr.is_contiguous() and col_idx.is_contiguous()
+        self.row_ptr = row_ptr
+        self.col_idx = col_idx
+        self.n = row_ptr.numel() - 1
+        self.nnz = int(col_idx.numel() if nnz is None else nnz)
+
+    def c(self) -> hln_csr:
+        return hln_csr(self.n, self.nnz, self.row_ptr.data_ptr(),
+                       self.col_idx.data_ptr() if self.col_idx.numel() else None)
+
+
+def device_status(stream=None):
+    check(lib().hln_device_status(_stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# a3-a6: exact closeness of one graph
+# ---------------------------------------------------------------------------
+
+def closeness_workspace_size(n: int, nnz: int, n_src: int, width_bits: int = 512, direction: int = 0) -> int:
+    o = hln_opts(width_bits, direction, 0)
+    return int(lib().hln_closeness_workspace_size(n, nnz, n_src, ctypes.byref(o)))
+
+
+def hln_closeness_layer(g: Graph, sources: torch.Tensor | None = None, width_bits: int = 512,
+                        direction: int = 0, want_cc: bool = True, want_h2: bool = False,
+                        out=None, ws: torch.Tensor | None = None, stream=None):
+    """Returns dict(S int64, R int32, cc float64 | None, h2 int32 | None)."""
+    dev = g.row_ptr.device
+    n_src = g.n if sources is None else int(sources.numel())
+    if sources is not None:
+        assert sources.dtype == torch.int32 and sources.is_cuda and sources.is_contiguous()
+    if out is None:
+        out = {"S": torch.empty(max(n_src, 1), dtype=torch.int64, device=dev),
+               "R": torch.empty(max(n_src, 1), dtype=torch.int32, device=dev),
+               "cc": torch.empty(max(n_src, 1), dtype=torch.float64, device=dev) if want_cc else None,
+               "h2": torch.empty(max(n_src, 1), dtype=torch.int32, device=dev) if want_h2 else None}
+    o = hln_opts(width_bits, direction, 0)
+    need = int(lib().hln_closeness_workspace_size(g.n, g.nnz, n_src, ctypes.byref(o)))
+    if ws is None:
+        ws = workspace(need, dev)
+    gc = g.c()
+    check(lib().hln_closeness_layer(ctypes.byref(gc), _ptr(sources), n_src, ctypes.byref(o),
+                                    _ptr(out["S"]), _ptr(out["R"]), _ptr(out["cc"]), _ptr(out["h2"]),
+                                    _ptr(ws), ws.numel(), _stream(stream)))
+    return {k: (v[:n_src] if v is not None else None) for k, v in out.items()}

@@ -1,0 +1,599 @@
+// Exact closeness of one graph by bit-parallel multi-source BFS (the Psi
+// step of the decoupling method, Sec. 3; Sec. 4: one BFS from every vertex,
+// Eq. 1 with the Wasserman-Faust normalisation for disconnected graphs).
+//
+// W = 64*NW sources run together; every vertex holds NW 64-bit words per
+// bitset (vertex-major, so one vertex's W bits are contiguous):
+//   vis  -- sources that have reached the vertex,
+//   fr   -- sources that reached it at the previous level (the frontier),
+//   nx   -- sources reaching it at this level.
+// One level, bottom-up (pull):  nx[v] = (OR_{w in N(v)} fr[w]) & ~vis[v].
+// One level, top-down (push):   for v with fr[v] != 0, OR fr[v] into every
+//   neighbour's word, keeping only bits the neighbour has not seen.
+// A level's new bits at v are the sources at distance d from v.
+//
+// Accumulation:
+//   all sources (sources == NULL): the graph is undirected, so d(s,v) =
+//     d(v,s) and the vertex v accumulates S[v] += d*popc(new), R[v] +=
+//     popc(new); after all n sources S[v], R[v] are v's own sums.  H2[v]
+//     counts the new bits at d = 2.
+//   listed sources: per-source counts c_i(d) = #{v : bit i new at d} are
+//     gathered per block in LDS and reduced over blocks at the batch end.
+//
+// Execution: one cooperative persistent launch per call.  All batches and
+// levels run inside it, separated by grid barriers with bounded waits; the
+// direction of each level and the end of each BFS are decided on the device
+// from counters of the previous level, so the host never synchronises.
+//
+// Load balance: rows are cut into segments of at most SEG arcs, ordered
+// heavy-first and then by decreasing degree.  A group of LPV lanes
+// processes one segment (NPAR = LPV/NW arcs at a time, one 64-bit word per
+// lane).  A row with several segments merges its partial ORs with atomic OR
+// into a per-vertex accumulator; the last segment to finish (atomic counter)
+// finalises the vertex, so a hub never serialises a level.
+#include "hln_internal.hpp"
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+
+namespace {
+
+using hln::dev::grid_barrier;
+using hln::dev::grid_barrier_or;
+using hln::dev::load_agent_i32;
+using hln::dev::shfl_xor_i32;
+using hln::dev::shfl_xor_u64;
+using hln::dev::store_agent_i32;
+
+// lanes per group (one segment at a time): 8, or NW when NW > 8
+template <int NW>
+constexpr int lpv() { return NW > 8 ? NW : 8; }
+constexpr int kMinLpv = 8;
+constexpr int kClasses = 40;
+
+// Every word here is read and written with agent-scope atomics only; the
+// barrier counter sits alone on its cache line.
+struct Ctrl {
+    int bins[kClasses];                    // segments per class
+    int cursor[kClasses];                  // fill cursors (segment units)
+    int n_seg;
+};
+
+struct BfsArgs {
+    int32_t n;
+    int32_t n_src;                    // number of sources (n when sources == nullptr)
+    const int32_t* row_ptr;
+    const int32_t* col_idx;
+    const int32_t* sources;           // nullptr: all vertices, per-vertex accumulation
+    uint64_t* bufA;                   // n*NW
+    uint64_t* bufB;                   // n*NW
+    uint64_t* vis;                    // n*NW
+    uint64_t* hacc;                   // n*NW partial ORs of multi-segment rows (kept zero)
+    int32_t* hcnt;                    // n finished-segment counters (kept zero)
+    int4* seg;                        // segments: vertex, first arc, end arc, segments of the row
+    long long seg_cap;                // capacity of seg
+    long long nnz_cap;                // arcs the caller declared (col_idx holds at least row_ptr[n] <= nnz_cap)
+    int32_t* flist[2];                // frontier vertex lists for top-down levels
+    int64_t* part;                    // per-source mode: [grid][2][W] block partials
+    int64_t* S;
+    int32_t* R;
+    int32_t* H2;
+    double* cc;
+    Ctrl* ctrl;
+    unsigned long long* bar;          // grid barrier words (hln::dev::kBarrierWords)
+    int* fault;
+    uint64_t wait_ticks;              // bound of one barrier wait (s_memrealtime ticks)
+    int32_t direction;                // 0 auto, 1 top-down only, 2 bottom-up only
+    int32_t seg_len;                  // SEG
+    int32_t alpha;                    // switch to bottom-up when frontier arcs > total arcs / alpha
+    int32_t beta;                     // switch back to top-down when frontier vertices < n / beta
+};
+
+__device__ __forceinline__ uint64_t full_mask(int k, int cnt) {
+    int valid = cnt - 64 * k;
+    if (valid >= 64) return ~0ull;
+    if (valid <= 0) return 0ull;
+    return (1ull << valid) - 1ull;
+}
+
+__device__ __forceinline__ int seg_class(int deg, int seg_len) {
+    if (deg > seg_len) return 0;
+    int lg = 31 - __clz(deg);                 // floor(log2 deg), deg >= 1
+    int top = 31 - __clz(seg_len);
+    return 1 + (top - lg);                    // larger degree first
+}
+
+// Finalise vertex v at level d: new bits, bitset updates, accumulation.
+// Called by the 8 lanes of a group with the group's full OR in `acc` (lane
+// (sub, k) holds word k; only sub == 0 lanes write).
+template <int NW, bool PER_SOURCE>
+__device__ __forceinline__ int finalize_vertex(const BfsArgs& a, uint64_t* nx, int v, int d, int k, int sub, int gl,
+                                               uint64_t acc, uint64_t vis_v, int32_t* s_cnt, int64_t s_old,
+                                               int32_t r_old) {
+    constexpr int LPV = lpv<NW>();
+    const size_t base = static_cast<size_t>(v) * NW + k;
+    uint64_t nw = acc & ~vis_v;
+    int c = 0;
+    if (sub == 0) {
+        nx[base] = nw;
+        if (nw) a.vis[base] = vis_v | nw;
+        c = __popcll(nw);
+        if (PER_SOURCE) {
+            uint64_t b = nw;
+            while (b) {
+                int bit = __ffsll(static_cast<long long>(b)) - 1;
+                b &= b - 1;
+                atomicAdd(&s_cnt[k * 64 + bit], 1);
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < LPV; off <<= 1) c += shfl_xor_i32(c, off);
+    if (!PER_SOURCE && gl == 0 && c) {
+        a.S[v] = s_old + static_cast<int64_t>(d) * c;
+        a.R[v] = r_old + c;
+        if (d == 2 && a.H2) a.H2[v] += c;
+    }
+    return c;
+}
+
+// OR of fr over the arcs [lo, hi) for the word k of this lane.  The group's
+// 8 lanes load 8 column ids per instruction (two such chunks per round) and
+// then every lane issues NW independent 8-byte gathers per chunk: lane
+// (sub, k) takes the chunk's arcs sub, sub + NPAR, ... (NPAR = 8 / NW).
+template <int NW>
+__device__ __forceinline__ uint64_t gather_or(const int32_t* __restrict__ col_idx, const uint64_t* __restrict__ fr,
+                                              int lo, int hi, int gl, int k, int sub, int gbase) {
+    constexpr int LPV = lpv<NW>();
+    constexpr int NPAR = LPV / NW;
+    constexpr int CH = NW >= 16 ? 1 : 2;     // chunks of LPV arcs per round
+    uint64_t acc = 0;
+    for (int c = lo; c < hi; c += CH * LPV) {
+        int cid[CH];
+#pragma unroll
+        for (int h = 0; h < CH; ++h) cid[h] = (c + h * LPV + gl < hi) ? col_idx[c + h * LPV + gl] : -1;
+        uint64_t x = 0;
+#pragma unroll
+        for (int t = 0; t < NW; ++t) {
+            const int j = t * NPAR + sub;
+#pragma unroll
+            for (int h = 0; h < CH; ++h) {
+                const int w = __shfl(cid[h], gbase + j, 64);
+                if (w >= 0) x |= fr[static_cast<size_t>(w) * NW + k];
+            }
+        }
+        acc |= x;
+    }
+    return acc;
+}
+
+template <int NW, int BLOCK, bool PER_SOURCE>
+__global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
+    constexpr int kLpv = lpv<NW>();
+    constexpr int W = 64 * NW;
+    const int n = a.n;
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (kLpv - 1);
+    const int gbase = lane - gl;
+    const int k = gl & (NW - 1);
+    const int sub = gl / NW;
+    const long long tid = static_cast<long long>(blockIdx.x) * BLOCK + threadIdx.x;
+    const long long nthreads = static_cast<long long>(gridDim.x) * BLOCK;
+    const long long gid = tid / kLpv;
+    const long long ngroups = nthreads / kLpv;
+    Ctrl* ctrl = a.ctrl;
+    const int seg_len = a.seg_len;
+
+    __shared__ int32_t s_cnt[PER_SOURCE ? W : 1];
+    __shared__ int64_t s_S[PER_SOURCE ? W : 1];
+    __shared__ int32_t s_R[PER_SOURCE ? W : 1];
+    __shared__ int s_bins[kClasses];
+
+    // ---- phase 0: zero accumulators and scratch, check the input, count
+    // segments per class.  The input is checked here so that no later access
+    // can leave its buffer: row pointers monotone within the declared arc
+    // count, column ids and listed sources in [0, n).  A violation is fault
+    // code 2.
+    if (threadIdx.x < kClasses) s_bins[threadIdx.x] = 0;
+    __syncthreads();
+    int bad = 0;
+    for (long long v = tid; v < n; v += nthreads) {
+        if (!PER_SOURCE) {
+            a.S[v] = 0;
+            a.R[v] = 1;                                      // the vertex itself (d = 0)
+            if (a.H2) a.H2[v] = 0;
+        }
+        a.hcnt[v] = 0;
+        const int e0 = a.row_ptr[v];
+        const int e1 = a.row_ptr[v + 1];
+        if (e0 < 0 || e1 < e0 || e1 > a.nnz_cap) {
+            bad = 1;
+            continue;
+        }
+        for (int e = e0; e < e1; ++e) bad |= static_cast<unsigned>(a.col_idx[e]) >= static_cast<unsigned>(n);
+        const int deg = e1 - e0;
+        if (deg > 0) atomicAdd(&s_bins[seg_class(deg, seg_len)], (deg + seg_len - 1) / seg_len);
+    }
+    if (PER_SOURCE)
+        for (long long i = tid; i < a.n_src; i += nthreads)
+            bad |= static_cast<unsigned>(a.sources[i]) >= static_cast<unsigned>(n);
+    if (bad) store_agent_i32(a.fault, 2);
+    for (long long i = tid; i < static_cast<long long>(n) * NW; i += nthreads) a.hacc[i] = 0;
+    __syncthreads();
+    if (threadIdx.x < kClasses && s_bins[threadIdx.x]) atomicAdd(&ctrl->bins[threadIdx.x], s_bins[threadIdx.x]);
+    if (!grid_barrier(a.bar, a.fault, a.wait_ticks)) return;
+    if (load_agent_i32(a.fault) != 0) return;              // uniform: read after the barrier
+
+    // ---- phase 1: class offsets
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        int acc = 0;
+        for (int c = 0; c < kClasses; ++c) {
+            int b = load_agent_i32(&ctrl->bins[c]);
+            store_agent_i32(&ctrl->cursor[c], acc);
+            acc += b;
+        }
+        store_agent_i32(&ctrl->n_seg, acc);
+    }
+    if (!grid_barrier(a.bar, a.fault, a.wait_ticks)) return;
+
+    // ---- phase 2: fill the segment list (heavy rows first, then by
+    // decreasing degree; order inside a class is arbitrary and does not
+    // affect any result)
+    for (long long v = tid; v < n; v += nthreads) {
+        const int e0 = a.row_ptr[v];
+        const int deg = a.row_ptr[v + 1] - e0;
+        if (deg > 0) {
+            const int segs = (deg + seg_len - 1) / seg_len;
+            const int pos = atomicAdd(&ctrl->cursor[seg_class(deg, seg_len)], segs);
+            for (int j = 0; j < segs && pos + j < a.seg_cap; ++j)
+                a.seg[pos + j] = make_int4(static_cast<int>(v), e0 + j * seg_len, min(e0 + (j + 1) * seg_len, e0 + deg), segs);
+        }
+    }
+    if (!grid_barrier(a.bar, a.fault, a.wait_ticks)) return;
+    const long long n_seg = min(static_cast<long long>(load_agent_i32(&ctrl->n_seg)), a.seg_cap);
+
+    const int n_batches = (a.n_src + W - 1) / W;
+    for (int b = 0; b < n_batches; ++b) {
+        const int src0 = b * W;
+        const int cnt = min(W, a.n_src - src0);
+
+        // ---- batch init: vis = fr = the batch's source bits
+        if (!PER_SOURCE) {
+            for (long long i = tid; i < static_cast<long long>(n) * NW; i += nthreads) {
+                const long long v = i / NW;
+                const int kk = static_cast<int>(i % NW);
+                const long long bit = v - src0;
+                uint64_t w0 = 0;
+                if (bit >= 0 && bit < cnt && (bit >> 6) == kk) w0 = 1ull << (bit & 63);
+                a.vis[i] = w0;
+                a.bufA[i] = w0;
+            }
+        } else {
+            for (long long i = tid; i < static_cast<long long>(n) * NW; i += nthreads) {
+                a.vis[i] = 0;
+                a.bufA[i] = 0;
+            }
+            for (int i = threadIdx.x; i < W; i += BLOCK) {
+                s_cnt[i] = 0;
+                s_S[i] = 0;
+                s_R[i] = 0;
+            }
+            if (!grid_barrier(a.bar, a.fault, a.wait_ticks)) return;
+            for (long long i = tid; i < cnt; i += nthreads) {
+                const int s = a.sources[src0 + i];
+                const size_t w = static_cast<size_t>(s) * NW + (i >> 6);
+                atomicOr(reinterpret_cast<unsigned long long*>(&a.vis[w]), 1ull << (i & 63));
+                atomicOr(reinterpret_cast<unsigned long long*>(&a.bufA[w]), 1ull << (i & 63));
+            }
+        }
+        if (!grid_barrier(a.bar, a.fault, a.wait_ticks)) return;
+
+        // ---- level loop; the barrier's OR tells every block whether any
+        // vertex got a new bit, which ends this batch's BFS
+        uint64_t* fr = a.bufA;
+        uint64_t* nx = a.bufB;
+        const uint64_t fm = full_mask(k, cnt);
+        for (int d = 1;; ++d) {
+            int any = 0;
+            long long s = gid;
+            int4 cur = s < n_seg ? a.seg[s] : make_int4(0, 0, 0, 0);
+            while (s < n_seg) {
+                const long long s_next = s + ngroups;
+                const int4 nxt = s_next < n_seg ? a.seg[s_next] : cur;   // prefetch the next segment
+                const int v = cur.x;
+                const int nseg = cur.w;
+                const size_t base = static_cast<size_t>(v) * NW + k;
+                const uint64_t vis_v = a.vis[base];
+                // the accumulators are loaded now so the load overlaps the gathers
+                int64_t s_old = 0;
+                int32_t r_old = 0;
+                if (!PER_SOURCE && gl == 0 && nseg == 1) {
+                    s_old = a.S[v];
+                    r_old = a.R[v];
+                }
+                int done = (vis_v & fm) == fm;
+#pragma unroll
+                for (int off = 1; off < NW; off <<= 1) done &= shfl_xor_i32(done, off);
+                uint64_t acc = done ? 0ull : gather_or<NW>(a.col_idx, fr, cur.y, cur.z, gl, k, sub, gbase);
+#pragma unroll
+                for (int off = NW; off < kLpv; off <<= 1) acc |= shfl_xor_u64(acc, off);
+                if (nseg == 1) {
+                    any |= finalize_vertex<NW, PER_SOURCE>(a, nx, v, d, k, sub, gl, acc, vis_v, s_cnt, s_old, r_old);
+                } else {
+                    // multi-segment row: merge, the last finisher finalises
+                    if (sub == 0 && acc)
+                        __hip_atomic_fetch_or(reinterpret_cast<unsigned long long*>(&a.hacc[base]),
+                                              static_cast<unsigned long long>(acc), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                    // the wave's OR atomics are performed before the count is
+                    // raised (agent-scope atomics complete at the coherence
+                    // point; vmcnt(0) waits for their acknowledgement)
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    __builtin_amdgcn_s_waitcnt(0);
+                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                    int old = 0;
+                    if (gl == 0)
+                        old = __hip_atomic_fetch_add(&a.hcnt[v], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    old = __shfl(old, gbase, 64);
+                    if (old == nseg - 1) {
+                        uint64_t full = 0;
+                        if (sub == 0)
+                            full = __hip_atomic_exchange(reinterpret_cast<unsigned long long*>(&a.hacc[base]), 0ull,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                        for (int off = NW; off < kLpv; off <<= 1) full |= shfl_xor_u64(full, off);
+                        if (gl == 0) {
+                            store_agent_i32(&a.hcnt[v], 0);
+                            if (!PER_SOURCE) {
+                                s_old = a.S[v];
+                                r_old = a.R[v];
+                            }
+                        }
+                        any |= finalize_vertex<NW, PER_SOURCE>(a, nx, v, d, k, sub, gl, full, vis_v, s_cnt, s_old,
+                                                               r_old);
+                    }
+                }
+                s = s_next;
+                cur = nxt;
+            }
+            if (PER_SOURCE) {
+                __syncthreads();
+                for (int i = threadIdx.x; i < W; i += BLOCK) {
+                    const int c = s_cnt[i];
+                    if (c) {
+                        s_S[i] += static_cast<int64_t>(d) * c;
+                        s_R[i] += c;
+                        s_cnt[i] = 0;
+                    }
+                }
+            }
+            const hln::dev::BarrierResult br = grid_barrier_or(a.bar, any, a.fault, a.wait_ticks);
+            if (!br.ok) return;
+            if (!br.any) break;
+            uint64_t* t = fr;
+            fr = nx;
+            nx = t;
+        }
+
+        if (PER_SOURCE) {
+            int64_t* pS = a.part + static_cast<size_t>(blockIdx.x) * 2 * W;
+            int64_t* pR = pS + W;
+            for (int i = threadIdx.x; i < W; i += BLOCK) {
+                pS[i] = s_S[i];
+                pR[i] = s_R[i];
+            }
+            if (!grid_barrier(a.bar, a.fault, a.wait_ticks)) return;
+            for (long long i = tid; i < cnt; i += nthreads) {
+                int64_t sS = 0, sR = 0;
+                for (unsigned blk = 0; blk < gridDim.x; ++blk) {
+                    const int64_t* q = a.part + static_cast<size_t>(blk) * 2 * W;
+                    sS += q[i];
+                    sR += q[W + i];
+                }
+                a.S[src0 + i] = sS;
+                a.R[src0 + i] = static_cast<int32_t>(1 + sR);
+            }
+            // the partials are rewritten only after the next batch's barriers
+        }
+    }
+
+    // ---- closeness (Eq. 1, Wasserman-Faust form, fixed operation order)
+    if (a.cc) {
+        // all-source mode: S and R were last written before the final level
+        // barrier; listed sources: the last writes are the reduction above
+        if (PER_SOURCE && !grid_barrier(a.bar, a.fault, a.wait_ticks)) return;
+        for (long long i = tid; i < a.n_src; i += nthreads) {
+            const int64_t sv = a.S[i];
+            const int32_t r = a.R[i];
+            double c = 0.0;
+            if (r > 1 && sv > 0 && n > 1) {
+                const double reach = static_cast<double>(r - 1);
+                const double q1 = reach / static_cast<double>(sv);
+                const double q2 = reach / static_cast<double>(n - 1);
+                c = q1 * q2;
+            }
+            a.cc[i] = c;
+        }
+    }
+}
+
+__global__ void k_zero_ctrl(Ctrl* c, unsigned long long* bar) {
+    int* p = reinterpret_cast<int*>(c);
+    for (int i = threadIdx.x; i < static_cast<int>(sizeof(Ctrl) / sizeof(int)); i += blockDim.x) p[i] = 0;
+    for (int i = threadIdx.x; i < hln::dev::kBarrierWords; i += blockDim.x) bar[i] = 0;
+}
+
+struct Layout {
+    size_t words;     // n * NW
+    size_t seg_cap;
+};
+
+template <int NW, int BLOCK, bool PS>
+hln_status launch(const BfsArgs& args, int grid, hipStream_t stream) {
+    if (getenv("HLN_VERBOSE"))
+        fprintf(stderr, "[hln] closeness NW=%d block=%d per_source=%d n=%d n_src=%d grid=%d\n", NW, BLOCK,
+                PS ? 1 : 0, args.n, args.n_src, grid);
+    void* kargs[] = {const_cast<BfsArgs*>(&args)};
+    HLN_TRY_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_closeness<NW, BLOCK, PS>), dim3(grid),
+                                           dim3(BLOCK), kargs, 0, stream));
+    return HLN_OK;
+}
+
+// Blocks per CU of a cooperative launch.  The occupancy query overstates
+// what becomes co-resident on this device (a grid at the reported limit did
+// not all start), so the grid stays at <= 2048 threads per CU / 2 by default.
+template <int NW, int BLOCK, bool PS>
+int max_grid(int cus) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_closeness<NW, BLOCK, PS>),
+                                                     BLOCK, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    int cap = std::max(1, 1024 / BLOCK);
+    if (const char* e = getenv("HLN_BLOCKS_PER_CU")) cap = std::max(1, atoi(e));
+    return std::max(1, cus * std::min(per_cu, cap));
+}
+
+template <int NW, int BLOCK>
+hln_status dispatch(const BfsArgs& a, bool ps, int want, int grid_cap, int cus, hipStream_t st) {
+    auto pick = [&](int maxg) { return std::max(1, std::min({want, maxg, grid_cap})); };
+    if (ps) return launch<NW, BLOCK, true>(a, pick(max_grid<NW, BLOCK, true>(cus)), st);
+    return launch<NW, BLOCK, false>(a, pick(max_grid<NW, BLOCK, false>(cus)), st);
+}
+
+template <int NW>
+hln_status dispatch_block(const BfsArgs& a, bool ps, long long want_threads, int grid_cap, int cus, hipStream_t st) {
+    int block = 512;
+    if (const char* e = getenv("HLN_BLOCK")) block = atoi(e);
+    auto want = [&](int b) { return static_cast<int>(std::min<long long>((want_threads + b - 1) / b, 1 << 20)); };
+    switch (block) {
+        case 256: return dispatch<NW, 256>(a, ps, want(256), grid_cap, cus, st);
+        case 1024: return dispatch<NW, 1024>(a, ps, want(1024), grid_cap, cus, st);
+        default: return dispatch<NW, 512>(a, ps, want(512), grid_cap, cus, st);
+    }
+}
+
+int width_words(const hln_opts* o) {
+    int w = (o && o->width_bits) ? o->width_bits : 512;
+    switch (w) {
+        case 64: return 1;
+        case 128: return 2;
+        case 256: return 4;
+        case 512: return 8;
+        case 1024: return 16;
+        case 2048: return 32;
+        default: return 0;
+    }
+}
+
+constexpr int kSegLen = 64;
+
+size_t workspace_bytes(int32_t n, int64_t nnz, int nw, int grid_cap) {
+    using hln::Arena;
+    size_t words = static_cast<size_t>(n) * nw;
+    size_t seg_cap = static_cast<size_t>(n) + static_cast<size_t>(nnz / kSegLen) + 1;
+    size_t b = 0;
+    b += Arena::round(sizeof(Ctrl));
+    b += Arena::round(hln::dev::kBarrierWords * sizeof(unsigned long long));
+    b += 4 * Arena::round(words * sizeof(uint64_t));            // A, B, vis, hacc
+    b += Arena::round(static_cast<size_t>(n) * sizeof(int32_t)); // hcnt
+    b += Arena::round(seg_cap * sizeof(int4));
+    b += Arena::round(static_cast<size_t>(grid_cap) * 2 * 64 * nw * sizeof(int64_t));  // per-source partials
+    return b;
+}
+
+int grid_cap_for(int cus) { return cus * 4; }
+
+}  // namespace
+
+extern "C" {
+
+size_t hln_closeness_workspace_size(int32_t n, int64_t nnz, int32_t n_src, const hln_opts* opts) {
+    (void)n_src;
+    int nw = width_words(opts);
+    if (nw == 0 || n < 0 || nnz < 0) return 0;
+    const hln::DeviceInfo* di = hln::device_info();
+    int cus = di ? di->cus : 256;
+    return workspace_bytes(n, nnz, nw, grid_cap_for(cus));
+}
+
+hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t n_src, const hln_opts* opts,
+                               int64_t* S, int32_t* R, double* cc, int32_t* h2, void* workspace,
+                               size_t workspace_bytes_in, void* stream) {
+    using hln::fail;
+    hln::clear_error();
+    if (!g) return fail(HLN_EINVAL, "graph is NULL");
+    if (g->n < 1) return fail(HLN_EINVAL, "n must be >= 1 (got %d)", g->n);
+    if (g->nnz < 0 || g->nnz > 0x7fffffffLL) return fail(HLN_EINVAL, "nnz out of range (%lld)", (long long)g->nnz);
+    if (!g->row_ptr || (g->nnz > 0 && !g->col_idx)) return fail(HLN_EINVAL, "graph arrays are NULL");
+    if (!S || !R) return fail(HLN_EINVAL, "S and R outputs are required");
+    if (!sources && n_src != g->n) return fail(HLN_EINVAL, "all-source mode needs n_src == n (%d != %d)", n_src, g->n);
+    if (n_src < 0) return fail(HLN_EINVAL, "n_src < 0");
+    if (sources && h2) return fail(HLN_EUNSUPPORTED, "h2 is produced in all-source mode only");
+    if (opts && opts->flags != 0) return fail(HLN_EINVAL, "opts->flags must be 0");
+    if (opts && (opts->direction < 0 || opts->direction > 2)) return fail(HLN_EINVAL, "bad direction %d", opts->direction);
+    const int nw = width_words(opts);
+    if (nw == 0) return fail(HLN_EINVAL, "width_bits must be 64, 128, 256, 512, 1024 or 2048");
+    if (!workspace) return fail(HLN_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % hln::Arena::kAlign) return fail(HLN_EINVAL, "workspace not 256-byte aligned");
+    const hln::DeviceInfo* di = hln::device_info();
+    if (!di) return HLN_EDEVICE;
+    const int grid_cap = grid_cap_for(di->cus);
+    const size_t need = workspace_bytes(g->n, g->nnz, nw, grid_cap);
+    if (workspace_bytes_in < need)
+        return fail(HLN_ENOMEM, "workspace too small: %zu < %zu bytes", workspace_bytes_in, need);
+    if (n_src == 0) return HLN_OK;
+    int* fault = hln::fault_word();
+    if (!fault) return HLN_EDEVICE;
+
+    const int n = g->n;
+    hln::Arena ar{static_cast<char*>(workspace), workspace_bytes_in};
+    const size_t words = static_cast<size_t>(n) * nw;
+    BfsArgs a{};
+    a.n = n;
+    a.n_src = n_src;
+    a.row_ptr = g->row_ptr;
+    a.col_idx = g->col_idx;
+    a.sources = sources;
+    a.ctrl = ar.take<Ctrl>(1);
+    a.bar = ar.take<unsigned long long>(hln::dev::kBarrierWords);
+    a.bufA = ar.take<uint64_t>(words);
+    a.bufB = ar.take<uint64_t>(words);
+    a.vis = ar.take<uint64_t>(words);
+    a.hacc = ar.take<uint64_t>(words);
+    a.hcnt = ar.take<int32_t>(n);
+    a.seg_cap = static_cast<long long>(n) + g->nnz / kSegLen + 1;
+    a.seg = ar.take<int4>(static_cast<size_t>(a.seg_cap));
+    a.nnz_cap = g->nnz;
+    a.part = ar.take<int64_t>(static_cast<size_t>(grid_cap) * 2 * 64 * nw);
+    a.S = S;
+    a.R = R;
+    a.H2 = h2;
+    a.cc = cc;
+    a.fault = fault;
+    a.wait_ticks = 1000000000ull;   // 10 s at 100 MHz
+    a.direction = opts ? opts->direction : 0;
+    a.seg_len = kSegLen;
+    a.alpha = 14;
+    a.beta = 24;
+    if (!a.ctrl || !a.bar || !a.part) return fail(HLN_ENOMEM, "workspace carve failed");
+
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_zero_ctrl, dim3(1), dim3(256), 0, st, a.ctrl, a.bar);
+    HLN_TRY_HIP(hipGetLastError());
+
+    // enough groups to cover the segments, capped by co-residency
+    const long long want_threads = (static_cast<long long>(n) + g->nnz / kSegLen + 1) * std::max(8, nw);
+    const bool ps = sources != nullptr;
+    switch (nw) {
+        case 1: return dispatch_block<1>(a, ps, want_threads, grid_cap, di->cus, st);
+        case 2: return dispatch_block<2>(a, ps, want_threads, grid_cap, di->cus, st);
+        case 4: return dispatch_block<4>(a, ps, want_threads, grid_cap, di->cus, st);
+        case 8: return dispatch_block<8>(a, ps, want_threads, grid_cap, di->cus, st);
+        case 16: return dispatch_block<16>(a, ps, want_threads, grid_cap, di->cus, st);
+        case 32: return dispatch_block<32>(a, ps, want_threads, grid_cap, di->cus, st);
+        default: return fail(HLN_EINVAL, "unsupported width");
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,145 @@
+"""Parity of hln_closeness_layer (HIP, through the C ABI) with the CPU oracle:
+S and R bit-exact, closeness bit-exact in FP64, 2-hop counts exact."""
+import numpy as np
+import pytest
+import torch
+
+from homln_inputs import configs as C
+from homln_inputs import generators as G
+from oracle import oracle as O
+from tests.gpu_common import csr_np, graph_dev, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2207_11662_amd")
+
+WIDTHS = [64, 128, 256, 512]
+
+
+def run_all(rp, ci, width, want_h2=True, direction=0):
+    g = graph_dev(P, rp, ci)
+    out = P.hln_closeness_layer(g, width_bits=width, want_h2=want_h2, direction=direction)
+    torch.cuda.synchronize()
+    P.device_status()
+    return {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+
+
+def check_all(n, rp, ci, width, tag):
+    say(tag, "n=%d nnz=%d W=%d" % (n, len(ci), width))
+    got = run_all(rp, ci, width)
+    S, R, H2, _, _ = O.bfs_sums(rp, ci, extras=True)
+    cc = O.closeness_wf(n, S, R)
+    assert np.array_equal(got["S"], S), (tag, np.nonzero(got["S"] != S)[0][:10])
+    assert np.array_equal(got["R"], R), tag
+    assert np.array_equal(got["h2"], H2), tag
+    assert np.array_equal(got["cc"].view(np.int64), cc.view(np.int64)), tag
+
+
+NAMED = [("path", 300), ("star", 1000), ("cycle", 257), ("complete", 150), ("hypercube", 8), ("bipartite", 70, 130)]
+
+
+@pytest.mark.parametrize("width", WIDTHS)
+@pytest.mark.parametrize("named", NAMED, ids=["%s%s" % (x[0], x[1]) for x in NAMED])
+def test_named_graphs(named, width):
+    n, eu, ev = G.named_graph(*named)
+    eu, ev = G.to_edges(n, eu, ev)
+    rp, ci = csr_np(n, eu, ev)
+    check_all(n, rp, ci, width, "named-%s" % (named,))
+
+
+@pytest.mark.parametrize("width", WIDTHS)
+def test_degenerate(width):
+    # one vertex; all isolated; a single edge plus isolated vertices
+    for n, eu, ev in [(1, [], []), (5, [], []), (7, [2], [5])]:
+        rp, ci = csr_np(n, np.array(eu, np.int64), np.array(ev, np.int64))
+        check_all(n, rp, ci, width, "degenerate-n%d" % n)
+
+
+@pytest.mark.parametrize("width", WIDTHS)
+def test_random_disconnected(width):
+    rng = np.random.default_rng(100 + width)
+    for trial in range(6):
+        n = int(rng.integers(2, 2500))
+        m = int(n * rng.choice([0.3, 0.6, 1.0, 3.0]))
+        keys = G.take_distinct(G.er_draw(n), min(m, n * (n - 1) // 2), n, rng)
+        eu, ev = G.keys_to_edges(keys, n)
+        rp, ci = csr_np(n, eu, ev)
+        check_all(n, rp, ci, width, "random-%d" % trial)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    h = C.config1()
+    layers = [csr_np(h.n, *e) for e in h.layers]
+    return h.n, layers, O.compose("and", layers), O.compose("or", layers)
+
+
+@pytest.mark.parametrize("width", WIDTHS)
+def test_config1_layers_and_or(cfg1, width):
+    n, layers, A, B = cfg1
+    for i, (rp, ci) in enumerate(layers + [A, B]):
+        check_all(n, rp, ci, width, "cfg1-graph%d" % i)
+
+
+@pytest.mark.parametrize("width", [64, 512])
+def test_config2_scaled(width):
+    h = C.config2(scale=0.04)
+    rp, ci = csr_np(h.n, *h.layers[0])
+    check_all(h.n, rp, ci, width, "cfg2-scaled-layer0")
+
+
+@pytest.mark.parametrize("width", WIDTHS)
+def test_listed_sources(width):
+    rng = np.random.default_rng(7)
+    h = C.config1()
+    rp, ci = csr_np(h.n, *h.layers[1])
+    A = O.compose("and", [csr_np(h.n, *e) for e in h.layers])
+    for (gr, gc), tag in [((rp, ci), "layer1"), (A, "and")]:
+        for count in (1, 63, 64, 65, 300, h.n):
+            src = np.sort(rng.choice(h.n, size=count, replace=False)).astype(np.int32)
+            say("listed", tag, count, width)
+            g = graph_dev(P, gr, gc)
+            out = P.hln_closeness_layer(g, sources=to_dev(src), width_bits=width)
+            torch.cuda.synchronize()
+            P.device_status()
+            S, R = O.bfs_sums(gr, gc, sources=src)
+            cc = O.closeness_wf(h.n, S, R)
+            assert np.array_equal(out["S"].cpu().numpy(), S)
+            assert np.array_equal(out["R"].cpu().numpy(), R)
+            assert np.array_equal(out["cc"].cpu().numpy().view(np.int64), cc.view(np.int64))
+
+
+def test_determinism():
+    h = C.config2(scale=0.02)
+    rp, ci = csr_np(h.n, *h.layers[2])
+    a = run_all(rp, ci, 256)
+    b = run_all(rp, ci, 256)
+    for k in ("S", "R", "cc", "h2"):
+        assert np.array_equal(a[k], b[k])
+
+
+def test_config2_full_size_sampled():
+    """Full-size config-2 layer in the benchmark's launch configuration
+    (all sources, W = 512): sampled vertices against one oracle BFS each (by
+    symmetry S[v] is the BFS sum from v), R against union-find components
+    of every vertex."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    h = C.config2()
+    n = h.n
+    rng = np.random.default_rng(3)
+    for li in (0, 3):
+        rp, ci = csr_np(n, *h.layers[li])
+        say("cfg2-full layer", li)
+        got = run_all(rp, ci, 512)
+        sample = np.sort(rng.choice(n, size=96, replace=False)).astype(np.int32)
+        S, R, H2, _, _ = O.bfs_sums(rp, ci, sources=sample, extras=True)
+        assert np.array_equal(got["S"][sample], S)
+        assert np.array_equal(got["R"][sample], R)
+        assert np.array_equal(got["h2"][sample], H2)
+        cc = O.closeness_wf(n, S, R)
+        assert np.array_equal(got["cc"][sample].view(np.int64), cc.view(np.int64))
+        adj = sp.csr_matrix((np.ones(len(ci)), ci, rp), shape=(n, n))
+        ncomp, lab = connected_components(adj, directed=False)
+        sizes = np.bincount(lab)
+        assert np.array_equal(got["R"], sizes[lab])
