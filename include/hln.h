@@ -107,7 +107,7 @@ hln_status hln_csr_validate(const hln_csr* g, int32_t* result, void* stream);
  * n+1, out_col_idx [dev] with `capacity` entries; the arc count is
  * out_row_ptr[n].  capacity must be >= min nnz (AND) or >= sum nnz (OR),
  * else HLN_ENOMEM.  1 <= r <= 64. */
-size_t hln_compose_workspace_size(int32_t n, int32_t r);
+size_t hln_compose_workspace_size(const hln_csr* layers, int32_t r);   /* 0 on bad arguments */
 hln_status hln_compose_and(const hln_csr* layers, int32_t r, int32_t* out_row_ptr, int32_t* out_col_idx,
                            int64_t capacity, void* workspace, size_t workspace_bytes, void* stream);
 hln_status hln_compose_or(const hln_csr* layers, int32_t r, int32_t* out_row_ptr, int32_t* out_col_idx,
@@ -129,6 +129,32 @@ hln_status hln_compose_or(const hln_csr* layers, int32_t r, int32_t* out_row_ptr
 size_t hln_closeness_workspace_size(int32_t n, int64_t nnz, int32_t n_src, const hln_opts* opts);
 hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t n_src, const hln_opts* opts,
                                int64_t* S, int32_t* R, double* cc, int32_t* h2,
+                               void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * CC-node selection and composition (Theta step).
+ * ------------------------------------------------------------------------
+ * HLN_RANK_WF    r = 1: score = the graph's closeness (Sec. 4, Eq. 1 in the
+ *                Wasserman-Faust form) from its S and R.
+ * HLN_RANK_CC2   r >= 1 layers: est(u) = max over layers of S + n*(n - R),
+ *                the distance sum with unreachable vertices at distance n
+ *                (Sec. 5.1); score = (n-1)/est (Sec. 5.2, Algorithm 1, then
+ *                Eq. 1); ranking by est ascending is the same order.
+ * HLN_RANK_NAIVE r >= 1 layers, k must be -1: intersection of the layers'
+ *                above-average CC-node sets (Sec. 4, naive composition).
+ * S, R [host] arrays of r device pointers to the layers' all-source outputs
+ * of hln_closeness_layer (n entries each).
+ * k >= 0: ids [dev] the k best vertices (score descending, ties by
+ *   ascending id, Sec. 5.2 "top-k"), score [dev, nullable] their scores.
+ * k = -1: every vertex whose score is >= the mean score (Sec. 4: "same or
+ *   above average"), ids ascending; the mean is the sum over ids taken
+ *   sequentially in chunks of 1024, chunk sums added in order, divided by n.
+ *   ids and score need room for n entries.
+ * count [dev] int32: number of ids written.  0 <= k <= n or k = -1. */
+typedef enum { HLN_RANK_WF = 0, HLN_RANK_CC2 = 1, HLN_RANK_NAIVE = 2 } hln_rank_mode;
+size_t hln_compose_cc_topk_workspace_size(int32_t n);
+hln_status hln_compose_cc_topk(int32_t mode, int32_t n, int32_t r, const int64_t* const* S, const int32_t* const* R,
+                               int32_t k, int32_t* ids, double* score, int32_t* count,
                                void* workspace, size_t workspace_bytes, void* stream);
 
 #ifdef __cplusplus

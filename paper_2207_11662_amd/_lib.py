@@ -24,7 +24,10 @@ EXPORTS = [
     "hln_csr_from_edges_workspace_size", "hln_csr_from_edges", "hln_csr_validate",
     "hln_compose_workspace_size", "hln_compose_and", "hln_compose_or",
     "hln_closeness_workspace_size", "hln_closeness_layer",
+    "hln_compose_cc_topk_workspace_size", "hln_compose_cc_topk",
 ]
+
+HLN_RANK_WF, HLN_RANK_CC2, HLN_RANK_NAIVE = 0, 1, 2
 
 
 class HlnError(RuntimeError):
@@ -65,11 +68,13 @@ def lib():
         "hln_csr_from_edges_workspace_size": ([i32, i64], sz),
         "hln_csr_from_edges": ([i32, i64, P, P, P, P, P, sz, P], st),
         "hln_csr_validate": ([csr_p, P, P], st),
-        "hln_compose_workspace_size": ([i32, i32], sz),
+        "hln_compose_workspace_size": ([csr_p, i32], sz),
         "hln_compose_and": ([csr_p, i32, P, P, i64, P, sz, P], st),
         "hln_compose_or": ([csr_p, i32, P, P, i64, P, sz, P], st),
         "hln_closeness_workspace_size": ([i32, i64, i32, opts_p], sz),
         "hln_closeness_layer": ([csr_p, P, i32, opts_p, P, P, P, P, P, sz, P], st),
+        "hln_compose_cc_topk_workspace_size": ([i32], sz),
+        "hln_compose_cc_topk": ([i32, i32, i32, P, P, i32, P, P, P, P, sz, P], st),
     }
     for name, (args, res) in sig.items():
         if hasattr(L, name):
@@ -122,6 +127,15 @@ class Graph:
         return hln_csr(self.n, self.nnz, self.row_ptr.data_ptr(),
                        self.col_idx.data_ptr() if self.col_idx.numel() else None)
 
+    def exact_nnz(self) -> int:
+        """Arc count from row_ptr[n] (synchronises)."""
+        return int(self.row_ptr[self.n].item())
+
+    def trimmed(self) -> "Graph":
+        """The same graph with col_idx cut to the exact arc count (synchronises)."""
+        m = self.exact_nnz()
+        return Graph(self.row_ptr, self.col_idx[:m], m)
+
 
 def device_status(stream=None):
     check(lib().hln_device_status(_stream(stream)))
@@ -158,3 +172,93 @@ def hln_closeness_layer(g: Graph, sources: torch.Tensor | None = None, width_bit
                                     _ptr(out["S"]), _ptr(out["R"]), _ptr(out["cc"]), _ptr(out["h2"]),
                                     _ptr(ws), ws.numel(), _stream(stream)))
     return {k: (v[:n_src] if v is not None else None) for k, v in out.items()}
+
+
+# ---------------------------------------------------------------------------
+# a1: ingest, validation
+# ---------------------------------------------------------------------------
+
+def hln_csr_from_edges(n: int, eu: torch.Tensor, ev: torch.Tensor, ws: torch.Tensor | None = None,
+                       out=None, stream=None) -> Graph:
+    """Normalised symmetric CSR of an arbitrary edge list (device tensors).
+    The returned Graph's col_idx has room for 2*m arcs; nnz is that bound."""
+    assert eu.dtype == torch.int32 and ev.dtype == torch.int32 and eu.numel() == ev.numel()
+    dev = eu.device
+    m = int(eu.numel())
+    if out is None:
+        out = (torch.empty(n + 1, dtype=torch.int32, device=dev), torch.empty(max(2 * m, 1), dtype=torch.int32, device=dev))
+    need = int(lib().hln_csr_from_edges_workspace_size(n, m))
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, dev)
+    check(lib().hln_csr_from_edges(n, m, _ptr(eu), _ptr(ev), _ptr(out[0]), _ptr(out[1]), _ptr(ws), ws.numel(),
+                                   _stream(stream)))
+    return Graph(out[0], out[1][:max(2 * m, 0)] if m else out[1][:0], 2 * m)
+
+
+def hln_csr_validate(g: Graph, stream=None) -> int:
+    """Bit mask of CSR convention violations (0 = valid); synchronises."""
+    res = torch.zeros(1, dtype=torch.int32, device=g.row_ptr.device)
+    gc = g.c()
+    check(lib().hln_csr_validate(ctypes.byref(gc), _ptr(res), _stream(stream)))
+    return int(res.item())
+
+
+# ---------------------------------------------------------------------------
+# a2: Boolean aggregation
+# ---------------------------------------------------------------------------
+
+def _layers_c(layers):
+    arr = (hln_csr * len(layers))(*[g.c() for g in layers])
+    return arr
+
+
+def compose_workspace_size(layers) -> int:
+    arr = _layers_c(layers)
+    return int(lib().hln_compose_workspace_size(arr, len(layers)))
+
+
+def _compose(fn, layers, capacity, ws, out, stream):
+    dev = layers[0].row_ptr.device
+    n = layers[0].n
+    arr = _layers_c(layers)
+    need = int(lib().hln_compose_workspace_size(arr, len(layers)))
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, dev)
+    if out is None:
+        out = (torch.empty(n + 1, dtype=torch.int32, device=dev), torch.empty(max(capacity, 1), dtype=torch.int32, device=dev))
+    check(fn(arr, len(layers), _ptr(out[0]), _ptr(out[1]), capacity, _ptr(ws), ws.numel(), _stream(stream)))
+    return Graph(out[0], out[1][:capacity], capacity)
+
+
+def hln_compose_and(layers, ws=None, out=None, stream=None) -> Graph:
+    """Edges present in every layer; col_idx sized by the smallest layer."""
+    return _compose(lib().hln_compose_and, layers, min(g.nnz for g in layers), ws, out, stream)
+
+
+def hln_compose_or(layers, ws=None, out=None, stream=None) -> Graph:
+    """Edges present in at least one layer; col_idx sized by the sum."""
+    return _compose(lib().hln_compose_or, layers, sum(g.nnz for g in layers), ws, out, stream)
+
+
+# ---------------------------------------------------------------------------
+# a7: selection / composition
+# ---------------------------------------------------------------------------
+
+def hln_compose_cc_topk(mode: int, n: int, S_list, R_list, k: int, ws=None, out=None, stream=None):
+    """Returns (ids, score, count) device tensors; count is a 1-element int32."""
+    dev = S_list[0].device
+    r = len(S_list)
+    Sp = (ctypes.c_void_p * r)(*[t.data_ptr() for t in S_list])
+    Rp = (ctypes.c_void_p * r)(*[t.data_ptr() for t in R_list])
+    need = int(lib().hln_compose_cc_topk_workspace_size(n))
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, dev)
+    if out is None:
+        size = n if k < 0 else max(k, 1)
+        out = (torch.empty(max(size, 1), dtype=torch.int32, device=dev),
+               torch.empty(max(size, 1), dtype=torch.float64, device=dev),
+               torch.empty(1, dtype=torch.int32, device=dev))
+    check(lib().hln_compose_cc_topk(mode, n, r, ctypes.cast(Sp, ctypes.c_void_p), ctypes.cast(Rp, ctypes.c_void_p),
+                                    k, _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _ptr(ws), ws.numel(),
+                                    _stream(stream)))
+    return out

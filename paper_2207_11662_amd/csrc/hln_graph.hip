@@ -1,0 +1,401 @@
+// Layer ingest, CSR validation and Boolean AND / OR aggregation.
+//
+// Ingest (Sec. 1: simple undirected layers over one vertex set): every edge
+// becomes the two arcs u->v and v->u keyed u*n+v, the keys are radix sorted,
+// self-loops and repeated keys are dropped, and the surviving keys are the
+// CSR (rows sorted by construction).
+//
+// Aggregation (Sec. 3.1): AND keeps an edge present in every selected
+// layer, OR one present in at least one.  Both work arc-parallel with
+// binary searches in the other layers' sorted rows, then compact with an
+// exclusive scan, so output rows come out sorted and the result does not
+// depend on scheduling.
+#include "hln_internal.hpp"
+#include "hln_prim.hpp"
+
+#include <algorithm>
+
+namespace {
+
+constexpr int kMaxLayers = 64;
+
+struct LayerSet {
+    int r;
+    int n;
+    const int32_t* rp[kMaxLayers];
+    const int32_t* ci[kMaxLayers];
+    long long base[kMaxLayers + 1];     // prefix of nnz over layers
+};
+
+__device__ __forceinline__ int row_of(const int32_t* __restrict__ rp, int n, long long e) {
+    // last u with rp[u] <= e
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rp[mid] <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// first position p in [lo, hi) with ci[p] >= x
+__device__ __forceinline__ int lower_bound(const int32_t* __restrict__ ci, int lo, int hi, int x) {
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (ci[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool in_row(const int32_t* __restrict__ rp, const int32_t* __restrict__ ci, int u, int x) {
+    const int lo = rp[u], hi = rp[u + 1];
+    const int p = lower_bound(ci, lo, hi, x);
+    return p < hi && ci[p] == x;
+}
+
+// ------------------------------------------------------------------ ingest
+
+__global__ void k_ingest_keys(int n, long long m, const int32_t* __restrict__ eu, const int32_t* __restrict__ ev,
+                              unsigned long long* keys, int32_t* vals, unsigned long long drop, int* fault) {
+    const unsigned long long N = static_cast<unsigned long long>(n);
+    for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < m;
+         i += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const int u = eu[i], v = ev[i];
+        unsigned long long k0 = drop, k1 = drop;
+        if (static_cast<unsigned>(u) >= static_cast<unsigned>(n) || static_cast<unsigned>(v) >= static_cast<unsigned>(n)) {
+            hln::dev::store_agent_i32(fault, 2);
+        } else if (u != v) {
+            k0 = static_cast<unsigned long long>(u) * N + static_cast<unsigned long long>(v);
+            k1 = static_cast<unsigned long long>(v) * N + static_cast<unsigned long long>(u);
+        }
+        keys[2 * i] = k0;
+        keys[2 * i + 1] = k1;
+        vals[2 * i] = 0;
+        vals[2 * i + 1] = 0;
+    }
+}
+
+__global__ void k_ingest_mark(const unsigned long long* __restrict__ keys, long long count, unsigned long long drop,
+                              int32_t* flag) {
+    for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+         i += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const unsigned long long k = keys[i];
+        flag[i] = (k < drop && (i == 0 || keys[i - 1] != k)) ? 1 : 0;
+    }
+}
+
+__global__ void k_zero_i32(int32_t* p, long long count) {
+    for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+         i += static_cast<long long>(gridDim.x) * blockDim.x)
+        p[i] = 0;
+}
+
+__global__ void k_ingest_fill(int n, const unsigned long long* __restrict__ keys, long long count,
+                              const int32_t* __restrict__ flag, const int32_t* __restrict__ pos, int32_t* col_idx,
+                              int32_t* deg) {
+    const unsigned long long N = static_cast<unsigned long long>(n);
+    for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+         i += static_cast<long long>(gridDim.x) * blockDim.x) {
+        if (!flag[i]) continue;
+        const unsigned long long k = keys[i];
+        col_idx[pos[i]] = static_cast<int32_t>(k % N);
+        atomicAdd(&deg[k / N], 1);
+    }
+}
+
+// ---------------------------------------------------------------- validate
+
+__global__ void k_validate(int n, long long nnz, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                           int32_t* result) {
+    int bits = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && (rp[0] != 0 || rp[n] != nnz)) bits |= 1;
+    for (long long uu = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; uu < n;
+         uu += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const int u = static_cast<int>(uu);
+        const int lo = rp[u], hi = rp[u + 1];
+        if (lo < 0 || hi < lo || hi > nnz) {
+            bits |= 1;
+            continue;
+        }
+        int prev = -1;
+        for (int e = lo; e < hi; ++e) {
+            const int v = ci[e];
+            if (static_cast<unsigned>(v) >= static_cast<unsigned>(n)) {
+                bits |= 2;
+                continue;
+            }
+            if (v <= prev) bits |= 4;
+            if (v == u) bits |= 8;
+            prev = v;
+            const int vlo = rp[v], vhi = rp[v + 1];
+            if (vlo < 0 || vhi < vlo || vhi > nnz) {
+                bits |= 1;
+                continue;
+            }
+            const int p = lower_bound(ci, vlo, vhi, u);
+            if (!(p < vhi && ci[p] == u)) bits |= 16;
+        }
+    }
+    if (bits) atomicOr(result, bits);
+}
+
+// --------------------------------------------------------------- aggregate
+
+__global__ void k_and_mark(LayerSet L, int p, int32_t* flag) {
+    const long long nnz = L.base[p + 1] - L.base[p];
+    for (long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; e < nnz;
+         e += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const int u = row_of(L.rp[p], L.n, e);
+        const int x = L.ci[p][e];
+        int keep = 1;
+        for (int l = 0; l < L.r && keep; ++l)
+            if (l != p && !in_row(L.rp[l], L.ci[l], u, x)) keep = 0;
+        flag[e] = keep;
+    }
+}
+
+__global__ void k_and_fill(LayerSet L, int p, const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
+                           int32_t* out_rp, int32_t* out_ci) {
+    const long long nnz = L.base[p + 1] - L.base[p];
+    const long long stride = static_cast<long long>(gridDim.x) * blockDim.x;
+    const long long t0 = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (long long e = t0; e < nnz; e += stride)
+        if (flag[e]) out_ci[pos[e]] = L.ci[p][e];
+    for (long long u = t0; u <= L.n; u += stride) out_rp[u] = pos[L.rp[p][u]];
+}
+
+__global__ void k_or_mark(LayerSet L, int32_t* keep) {
+    const long long total = L.base[L.r];
+    for (long long g = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
+         g += static_cast<long long>(gridDim.x) * blockDim.x) {
+        int l = 0;
+        while (L.base[l + 1] <= g) ++l;
+        const long long e = g - L.base[l];
+        const int u = row_of(L.rp[l], L.n, e);
+        const int x = L.ci[l][e];
+        int k = 1;
+        for (int q = 0; q < l && k; ++q)
+            if (in_row(L.rp[q], L.ci[q], u, x)) k = 0;      // first layer holding the edge keeps it
+        keep[g] = k;
+    }
+}
+
+__global__ void k_or_count(LayerSet L, const int32_t* __restrict__ kpos, int32_t* cnt) {
+    for (long long uu = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; uu < L.n;
+         uu += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const int u = static_cast<int>(uu);
+        int c = 0;
+        for (int l = 0; l < L.r; ++l) c += kpos[L.base[l] + L.rp[l][u + 1]] - kpos[L.base[l] + L.rp[l][u]];
+        cnt[u] = c;
+    }
+}
+
+__global__ void k_or_fill(LayerSet L, const int32_t* __restrict__ keep, const int32_t* __restrict__ kpos,
+                          const int32_t* __restrict__ out_rp, int32_t* out_ci) {
+    const long long total = L.base[L.r];
+    for (long long g = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
+         g += static_cast<long long>(gridDim.x) * blockDim.x) {
+        if (!keep[g]) continue;
+        int l = 0;
+        while (L.base[l + 1] <= g) ++l;
+        const long long e = g - L.base[l];
+        const int u = row_of(L.rp[l], L.n, e);
+        const int x = L.ci[l][e];
+        // rank of x among the union's elements of row u: kept elements < x
+        int rank = 0;
+        for (int q = 0; q < L.r; ++q) {
+            const int lo = L.rp[q][u], hi = L.rp[q][u + 1];
+            const int at = (q == l) ? static_cast<int>(e) : lower_bound(L.ci[q], lo, hi, x);
+            rank += kpos[L.base[q] + at] - kpos[L.base[q] + lo];
+        }
+        out_ci[out_rp[u] + rank] = x;
+    }
+}
+
+unsigned grid_for(long long count, int block = 256) {
+    return static_cast<unsigned>(std::max<long long>(1, std::min<long long>((count + block - 1) / block, 8192)));
+}
+
+int key_bits_for(int n) {
+    // keys u*n+v < n*n, plus the drop sentinel n*n
+    const unsigned long long top = static_cast<unsigned long long>(n) * static_cast<unsigned long long>(n);
+    int b = 1;
+    while (b < 64 && (top >> b) != 0) ++b;
+    return b;
+}
+
+hln_status check_layers(const hln_csr* layers, int32_t r, LayerSet& L) {
+    using hln::fail;
+    if (!layers) return fail(HLN_EINVAL, "layers is NULL");
+    if (r < 1 || r > kMaxLayers) return fail(HLN_EINVAL, "r must be in [1, %d] (got %d)", kMaxLayers, r);
+    L.r = r;
+    L.n = layers[0].n;
+    L.base[0] = 0;
+    if (L.n < 1) return fail(HLN_EINVAL, "n must be >= 1");
+    for (int l = 0; l < r; ++l) {
+        if (layers[l].n != L.n) return fail(HLN_EINVAL, "layer %d has n=%d, layer 0 has n=%d", l, layers[l].n, L.n);
+        if (!layers[l].row_ptr || (layers[l].nnz > 0 && !layers[l].col_idx))
+            return fail(HLN_EINVAL, "layer %d arrays are NULL", l);
+        if (layers[l].nnz < 0) return fail(HLN_EINVAL, "layer %d nnz < 0", l);
+        L.rp[l] = layers[l].row_ptr;
+        L.ci[l] = layers[l].col_idx;
+        L.base[l + 1] = L.base[l] + layers[l].nnz;
+    }
+    if (L.base[r] >= (1ll << 31)) return fail(HLN_EUNSUPPORTED, "total arcs exceed 2^31");
+    return HLN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hln_csr_from_edges_workspace_size(int32_t n, int64_t m) {
+    (void)n;
+    if (m < 0) return 0;
+    const long long a = 2 * m;
+    using hln::Arena;
+    return Arena::round(static_cast<size_t>(a + 1) * 8) + Arena::round(static_cast<size_t>(a + 1) * 4) +
+           Arena::round(static_cast<size_t>(a + 1) * 4) + Arena::round(static_cast<size_t>(a + 1) * 4) +
+           Arena::round(static_cast<size_t>(n + 1) * 4) +
+           std::max(hln::prim::sort_workspace(a), hln::prim::scan_workspace(std::max<long long>(a, n) + 1));
+}
+
+hln_status hln_csr_from_edges(int32_t n, int64_t m, const int32_t* eu, const int32_t* ev, int32_t* row_ptr,
+                              int32_t* col_idx, void* workspace, size_t workspace_bytes, void* stream) {
+    using hln::fail;
+    hln::clear_error();
+    if (n < 1) return fail(HLN_EINVAL, "n must be >= 1");
+    if (m < 0 || m > (1ll << 30)) return fail(HLN_EINVAL, "m out of range");
+    if (!row_ptr || (m > 0 && (!eu || !ev || !col_idx))) return fail(HLN_EINVAL, "NULL array");
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % hln::Arena::kAlign)
+        return fail(HLN_EINVAL, "workspace NULL or not 256-byte aligned");
+    const size_t need = hln_csr_from_edges_workspace_size(n, m);
+    if (workspace_bytes < need) return fail(HLN_ENOMEM, "workspace too small: %zu < %zu", workspace_bytes, need);
+    int* fault = hln::fault_word();
+    if (!fault) return HLN_EDEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const long long a = 2 * m;
+    hln::Arena ar{static_cast<char*>(workspace), workspace_bytes};
+    unsigned long long* keys = ar.take<unsigned long long>(a + 1);
+    int32_t* vals = ar.take<int32_t>(a + 1);
+    int32_t* flag = ar.take<int32_t>(a + 1);
+    int32_t* pos = ar.take<int32_t>(a + 1);
+    int32_t* deg = ar.take<int32_t>(n + 1);
+    void* sws = ar.base + ar.off;
+    const size_t sws_bytes = workspace_bytes - ar.off;
+    const unsigned long long drop = static_cast<unsigned long long>(n) * static_cast<unsigned long long>(n);
+    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(n + 1)), dim3(256), 0, st, deg, static_cast<long long>(n + 1));
+    if (m > 0) {
+        hipLaunchKernelGGL(k_ingest_keys, dim3(grid_for(m)), dim3(256), 0, st, n, static_cast<long long>(m), eu, ev,
+                           keys, vals, drop, fault);
+        hln_status s = hln::prim::sort_pairs(keys, vals, a, key_bits_for(n), sws, sws_bytes, st);
+        if (s != HLN_OK) return s;
+        hipLaunchKernelGGL(k_ingest_mark, dim3(grid_for(a)), dim3(256), 0, st, keys, a, drop, flag);
+        s = hln::prim::scan_exclusive<int32_t>(flag, pos, a, sws, sws_bytes, st);
+        if (s != HLN_OK) return s;
+        hipLaunchKernelGGL(k_ingest_fill, dim3(grid_for(a)), dim3(256), 0, st, n, keys, a, flag, pos, col_idx, deg);
+    }
+    hln_status s = hln::prim::scan_exclusive<int32_t>(deg, row_ptr, n, sws, sws_bytes, st);
+    if (s != HLN_OK) return s;
+    HLN_TRY_HIP(hipGetLastError());
+    return HLN_OK;
+}
+
+hln_status hln_csr_validate(const hln_csr* g, int32_t* result, void* stream) {
+    using hln::fail;
+    hln::clear_error();
+    if (!g || !result) return fail(HLN_EINVAL, "NULL argument");
+    if (g->n < 1 || g->nnz < 0 || !g->row_ptr || (g->nnz > 0 && !g->col_idx))
+        return fail(HLN_EINVAL, "bad graph descriptor");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, result, 1ll);
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(g->n)), dim3(256), 0, st, g->n, static_cast<long long>(g->nnz),
+                       g->row_ptr, g->col_idx, result);
+    HLN_TRY_HIP(hipGetLastError());
+    return HLN_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+size_t compose_ws(const LayerSet& L) {
+    using hln::Arena;
+    const long long total = L.base[L.r];
+    return Arena::round(static_cast<size_t>(total + 1) * 4) * 2 + Arena::round(static_cast<size_t>(L.n + 1) * 4) +
+           hln::prim::scan_workspace(std::max<long long>(total, L.n) + 1);
+}
+
+hln_status compose(int mode, const hln_csr* layers, int32_t r, int32_t* out_rp, int32_t* out_ci, int64_t capacity,
+                   void* workspace, size_t workspace_bytes, void* stream) {
+    using hln::fail;
+    hln::clear_error();
+    LayerSet L;
+    hln_status s = check_layers(layers, r, L);
+    if (s != HLN_OK) return s;
+    if (!out_rp || (capacity > 0 && !out_ci)) return fail(HLN_EINVAL, "NULL output");
+    long long bound = 0;
+    int p = 0;
+    if (mode == 0) {
+        for (int l = 0; l < r; ++l)
+            if (layers[l].nnz < layers[p].nnz) p = l;
+        bound = layers[p].nnz;
+    } else {
+        bound = L.base[r];
+    }
+    if (capacity < bound)
+        return fail(HLN_ENOMEM, "output capacity %lld < bound %lld", static_cast<long long>(capacity), bound);
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % hln::Arena::kAlign)
+        return fail(HLN_EINVAL, "workspace NULL or not 256-byte aligned");
+    const size_t need = compose_ws(L);
+    if (workspace_bytes < need) return fail(HLN_ENOMEM, "workspace too small: %zu < %zu", workspace_bytes, need);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hln::Arena ar{static_cast<char*>(workspace), workspace_bytes};
+    const long long total = L.base[r];
+    int32_t* flag = ar.take<int32_t>(total + 1);
+    int32_t* pos = ar.take<int32_t>(total + 1);
+    int32_t* cnt = ar.take<int32_t>(L.n + 1);
+    void* sws = ar.base + ar.off;
+    const size_t sws_bytes = workspace_bytes - ar.off;
+    if (mode == 0) {
+        const long long nnz = layers[p].nnz;
+        hipLaunchKernelGGL(k_and_mark, dim3(grid_for(nnz)), dim3(256), 0, st, L, p, flag);
+        s = hln::prim::scan_exclusive<int32_t>(flag, pos, nnz, sws, sws_bytes, st);
+        if (s != HLN_OK) return s;
+        hipLaunchKernelGGL(k_and_fill, dim3(grid_for(std::max<long long>(nnz, L.n + 1))), dim3(256), 0, st, L, p,
+                           flag, pos, out_rp, out_ci);
+    } else {
+        hipLaunchKernelGGL(k_or_mark, dim3(grid_for(total)), dim3(256), 0, st, L, flag);
+        s = hln::prim::scan_exclusive<int32_t>(flag, pos, total, sws, sws_bytes, st);
+        if (s != HLN_OK) return s;
+        hipLaunchKernelGGL(k_or_count, dim3(grid_for(L.n)), dim3(256), 0, st, L, pos, cnt);
+        s = hln::prim::scan_exclusive<int32_t>(cnt, out_rp, L.n, sws, sws_bytes, st);
+        if (s != HLN_OK) return s;
+        hipLaunchKernelGGL(k_or_fill, dim3(grid_for(total)), dim3(256), 0, st, L, flag, pos, out_rp, out_ci);
+    }
+    HLN_TRY_HIP(hipGetLastError());
+    return HLN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hln_compose_workspace_size(const hln_csr* layers, int32_t r) {
+    LayerSet L;
+    if (check_layers(layers, r, L) != HLN_OK) return 0;
+    return compose_ws(L);
+}
+
+hln_status hln_compose_and(const hln_csr* layers, int32_t r, int32_t* out_row_ptr, int32_t* out_col_idx,
+                           int64_t capacity, void* workspace, size_t workspace_bytes, void* stream) {
+    return compose(0, layers, r, out_row_ptr, out_col_idx, capacity, workspace, workspace_bytes, stream);
+}
+
+hln_status hln_compose_or(const hln_csr* layers, int32_t r, int32_t* out_row_ptr, int32_t* out_col_idx,
+                          int64_t capacity, void* workspace, size_t workspace_bytes, void* stream) {
+    return compose(1, layers, r, out_row_ptr, out_col_idx, capacity, workspace, workspace_bytes, stream);
+}
+
+}  // extern "C"

@@ -138,21 +138,26 @@ __device__ __forceinline__ int finalize_vertex(const BfsArgs& a, uint64_t* nx, i
     return c;
 }
 
-// OR of fr over the arcs [lo, hi) for the word k of this lane.  The group's
-// 8 lanes load 8 column ids per instruction (two such chunks per round) and
-// then every lane issues NW independent 8-byte gathers per chunk: lane
-// (sub, k) takes the chunk's arcs sub, sub + NPAR, ... (NPAR = 8 / NW).
+// Gathering the frontier over a segment [lo, hi) for the word k of this
+// lane.  The group's LPV lanes load LPV column ids per instruction (CH such
+// chunks per round) and then every lane issues NW independent 8-byte
+// gathers per chunk: lane (sub, k) takes the chunk's arcs sub, sub + NPAR,
+// ... (NPAR = LPV / NW).
 template <int NW>
-__device__ __forceinline__ uint64_t gather_or(const int32_t* __restrict__ col_idx, const uint64_t* __restrict__ fr,
-                                              int lo, int hi, int gl, int k, int sub, int gbase) {
-    constexpr int LPV = lpv<NW>();
-    constexpr int NPAR = LPV / NW;
-    constexpr int CH = NW >= 16 ? 1 : 2;     // chunks of LPV arcs per round
-    uint64_t acc = 0;
-    for (int c = lo; c < hi; c += CH * LPV) {
-        int cid[CH];
+struct Gather {
+    static constexpr int LPV = lpv<NW>();
+    static constexpr int NPAR = LPV / NW;
+    static constexpr int CH = NW >= 16 ? 1 : 2;     // chunks of LPV arcs per round
+    static constexpr int ROUND = CH * LPV;
+
+    __device__ __forceinline__ static void load_ids(const int32_t* __restrict__ col_idx, int c, int hi, int gl,
+                                                    int (&cid)[CH]) {
 #pragma unroll
         for (int h = 0; h < CH; ++h) cid[h] = (c + h * LPV + gl < hi) ? col_idx[c + h * LPV + gl] : -1;
+    }
+
+    __device__ __forceinline__ static uint64_t round_or(const uint64_t* __restrict__ fr, const int (&cid)[CH], int k,
+                                                        int sub, int gbase) {
         uint64_t x = 0;
 #pragma unroll
         for (int t = 0; t < NW; ++t) {
@@ -163,9 +168,39 @@ __device__ __forceinline__ uint64_t gather_or(const int32_t* __restrict__ col_id
                 if (w >= 0) x |= fr[static_cast<size_t>(w) * NW + k];
             }
         }
-        acc |= x;
+        return x;
     }
-    return acc;
+};
+
+// What a group reads for a segment before gathering: the record, the
+// first round of column ids, the vertex's visited word and (for
+// single-segment rows in all-source mode) its accumulators.  Loaded one
+// segment ahead so that these reads overlap the previous segment's gathers.
+template <int NW>
+struct SegPre {
+    int4 sg;
+    int cid[Gather<NW>::CH];
+    uint64_t vis;
+    int64_t s_old;
+    int32_t r_old;
+};
+
+template <int NW, bool PER_SOURCE>
+__device__ __forceinline__ void seg_prefetch(const BfsArgs& a, const int4 sg, bool valid, int gl, int k,
+                                             SegPre<NW>& p) {
+    p.sg = sg;
+    p.s_old = 0;
+    p.r_old = 0;
+    p.vis = 0;
+#pragma unroll
+    for (int h = 0; h < Gather<NW>::CH; ++h) p.cid[h] = -1;
+    if (!valid) return;
+    Gather<NW>::load_ids(a.col_idx, sg.y, sg.z, gl, p.cid);
+    p.vis = a.vis[static_cast<size_t>(sg.x) * NW + k];
+    if (!PER_SOURCE && gl == 0 && sg.w == 1) {
+        p.s_old = a.S[sg.x];
+        p.r_old = a.R[sg.x];
+    }
 }
 
 template <int NW, int BLOCK, bool PER_SOURCE>
@@ -296,30 +331,40 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
         const uint64_t fm = full_mask(k, cnt);
         for (int d = 1;; ++d) {
             int any = 0;
+            // software pipeline: records two segments ahead, the column ids,
+            // visited word and accumulators one segment ahead
             long long s = gid;
-            int4 cur = s < n_seg ? a.seg[s] : make_int4(0, 0, 0, 0);
+            SegPre<NW> cur;
+            seg_prefetch<NW, PER_SOURCE>(a, s < n_seg ? a.seg[s] : make_int4(0, 0, 0, 0), s < n_seg, gl, k, cur);
+            int4 rec2 = s + ngroups < n_seg ? a.seg[s + ngroups] : make_int4(0, 0, 0, 0);
             while (s < n_seg) {
-                const long long s_next = s + ngroups;
-                const int4 nxt = s_next < n_seg ? a.seg[s_next] : cur;   // prefetch the next segment
-                const int v = cur.x;
-                const int nseg = cur.w;
+                const long long s1 = s + ngroups;
+                const long long s2 = s1 + ngroups;
+                const int4 rec3 = s2 < n_seg ? a.seg[s2] : make_int4(0, 0, 0, 0);
+                SegPre<NW> nxt;
+                seg_prefetch<NW, PER_SOURCE>(a, rec2, s1 < n_seg, gl, k, nxt);
+
+                const int v = cur.sg.x;
+                const int nseg = cur.sg.w;
                 const size_t base = static_cast<size_t>(v) * NW + k;
-                const uint64_t vis_v = a.vis[base];
-                // the accumulators are loaded now so the load overlaps the gathers
-                int64_t s_old = 0;
-                int32_t r_old = 0;
-                if (!PER_SOURCE && gl == 0 && nseg == 1) {
-                    s_old = a.S[v];
-                    r_old = a.R[v];
-                }
+                const uint64_t vis_v = cur.vis;
                 int done = (vis_v & fm) == fm;
 #pragma unroll
                 for (int off = 1; off < NW; off <<= 1) done &= shfl_xor_i32(done, off);
-                uint64_t acc = done ? 0ull : gather_or<NW>(a.col_idx, fr, cur.y, cur.z, gl, k, sub, gbase);
+                uint64_t acc = 0;
+                if (!done) {
+                    acc = Gather<NW>::round_or(fr, cur.cid, k, sub, gbase);
+                    for (int c = cur.sg.y + Gather<NW>::ROUND; c < cur.sg.z; c += Gather<NW>::ROUND) {
+                        int cid[Gather<NW>::CH];
+                        Gather<NW>::load_ids(a.col_idx, c, cur.sg.z, gl, cid);
+                        acc |= Gather<NW>::round_or(fr, cid, k, sub, gbase);
+                    }
+                }
 #pragma unroll
                 for (int off = NW; off < kLpv; off <<= 1) acc |= shfl_xor_u64(acc, off);
                 if (nseg == 1) {
-                    any |= finalize_vertex<NW, PER_SOURCE>(a, nx, v, d, k, sub, gl, acc, vis_v, s_cnt, s_old, r_old);
+                    any |= finalize_vertex<NW, PER_SOURCE>(a, nx, v, d, k, sub, gl, acc, vis_v, s_cnt, cur.s_old,
+                                                           cur.r_old);
                 } else {
                     // multi-segment row: merge, the last finisher finalises
                     if (sub == 0 && acc)
@@ -343,6 +388,8 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
                         for (int off = NW; off < kLpv; off <<= 1) full |= shfl_xor_u64(full, off);
+                        int64_t s_old = 0;
+                        int32_t r_old = 0;
                         if (gl == 0) {
                             store_agent_i32(&a.hcnt[v], 0);
                             if (!PER_SOURCE) {
@@ -354,8 +401,9 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                                                                r_old);
                     }
                 }
-                s = s_next;
+                s = s1;
                 cur = nxt;
+                rec2 = rec3;
             }
             if (PER_SOURCE) {
                 __syncthreads();
@@ -461,15 +509,27 @@ hln_status dispatch(const BfsArgs& a, bool ps, int want, int grid_cap, int cus, 
     return launch<NW, BLOCK, false>(a, pick(max_grid<NW, BLOCK, false>(cus)), st);
 }
 
+template <int NW, int BLOCK>
+bool fits(bool ps) {
+    int per_cu = 0;
+    const void* f = ps ? reinterpret_cast<const void*>(&k_closeness<NW, BLOCK, true>)
+                       : reinterpret_cast<const void*>(&k_closeness<NW, BLOCK, false>);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, BLOCK, 0) == hipSuccess && per_cu >= 1;
+}
+
+// Block size: 1024 threads by default (fewest barrier participants for the
+// same number of waves), smaller if the kernel's registers do not allow it.
 template <int NW>
 hln_status dispatch_block(const BfsArgs& a, bool ps, long long want_threads, int grid_cap, int cus, hipStream_t st) {
-    int block = 512;
+    int block = 1024;
     if (const char* e = getenv("HLN_BLOCK")) block = atoi(e);
+    if (block >= 1024 && !fits<NW, 1024>(ps)) block = 512;
+    if (block >= 512 && block < 1024 && !fits<NW, 512>(ps)) block = 256;
     auto want = [&](int b) { return static_cast<int>(std::min<long long>((want_threads + b - 1) / b, 1 << 20)); };
     switch (block) {
         case 256: return dispatch<NW, 256>(a, ps, want(256), grid_cap, cus, st);
-        case 1024: return dispatch<NW, 1024>(a, ps, want(1024), grid_cap, cus, st);
-        default: return dispatch<NW, 512>(a, ps, want(512), grid_cap, cus, st);
+        case 512: return dispatch<NW, 512>(a, ps, want(512), grid_cap, cus, st);
+        default: return dispatch<NW, 1024>(a, ps, want(1024), grid_cap, cus, st);
     }
 }
 

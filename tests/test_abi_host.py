@@ -1,0 +1,103 @@
+"""The C-ABI library loads, exports every symbol include/hln.h declares, and
+rejects bad arguments on the host before touching the device (these run
+without a GPU: device pointers are never dereferenced on the host)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+P = pytest.importorskip("paper_2207_11662_amd")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = ctypes.c_void_p(0x100000)       # stands for a device pointer; never read on the host
+HLN_EINVAL, HLN_ENOMEM, HLN_EUNSUPPORTED = 1, 2, 4
+
+
+def header_symbols():
+    with open(os.path.join(ROOT, "include", "hln.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(hln_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = P.lib()
+    declared = header_symbols()
+    assert declared, "no declarations parsed"
+    missing = [s for s in declared if not hasattr(L, s)]
+    assert not missing, missing
+    assert sorted(P.EXPORTS) == declared
+
+
+def test_version_and_error_string():
+    L = P.lib()
+    assert L.hln_version() >= 0x000100
+    assert isinstance(L.hln_last_error(), bytes)
+
+
+def _csr(n=10, nnz=20):
+    return P._lib.hln_csr(n, nnz, 0x100000, 0x200000)
+
+
+def test_closeness_argument_checks():
+    L = P.lib()
+    o = P._lib.hln_opts(512, 0, 0)
+    g = _csr()
+    call = lambda **kw: L.hln_closeness_layer(kw.get("g", ctypes.byref(g)), kw.get("src", None), kw.get("n_src", 10),
+                                              kw.get("opts", ctypes.byref(o)), kw.get("S", FAKE), kw.get("R", FAKE),
+                                              None, None, kw.get("ws", FAKE), kw.get("wsb", 1 << 30), None)
+    assert call(g=None) == HLN_EINVAL
+    assert call(S=None) == HLN_EINVAL
+    assert call(n_src=9) == HLN_EINVAL                      # all-source mode needs n_src == n
+    bad = P._lib.hln_opts(100, 0, 0)
+    assert call(opts=ctypes.byref(bad)) == HLN_EINVAL
+    assert b"width_bits" in L.hln_last_error()
+    bad = P._lib.hln_opts(512, 7, 0)
+    assert call(opts=ctypes.byref(bad)) == HLN_EINVAL
+    assert call(ws=None) == HLN_EINVAL
+    assert call(ws=ctypes.c_void_p(0x100001)) == HLN_EINVAL    # misaligned workspace
+    g0 = _csr(0, 0)
+    assert call(g=ctypes.byref(g0)) == HLN_EINVAL
+
+
+def test_ingest_argument_checks():
+    L = P.lib()
+    assert L.hln_csr_from_edges(0, 1, FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 30, None) == HLN_EINVAL
+    assert L.hln_csr_from_edges(5, -1, FAKE, FAKE, FAKE, FAKE, FAKE, 1 << 30, None) == HLN_EINVAL
+    assert L.hln_csr_from_edges(5, 3, None, FAKE, FAKE, FAKE, FAKE, 1 << 30, None) == HLN_EINVAL
+    need = L.hln_csr_from_edges_workspace_size(5, 3)
+    assert need > 0
+    assert L.hln_csr_from_edges(5, 3, FAKE, FAKE, FAKE, FAKE, FAKE, need - 1, None) == HLN_ENOMEM
+
+
+def test_compose_argument_checks():
+    L = P.lib()
+    a, b = _csr(10, 20), _csr(10, 30)
+    arr = (P._lib.hln_csr * 2)(a, b)
+    ws = L.hln_compose_workspace_size(arr, 2)
+    assert ws > 0
+    assert L.hln_compose_and(arr, 0, FAKE, FAKE, 20, FAKE, ws, None) == HLN_EINVAL       # r = 0
+    assert L.hln_compose_and(arr, 65, FAKE, FAKE, 20, FAKE, ws, None) == HLN_EINVAL      # r > 64
+    assert L.hln_compose_and(arr, 2, FAKE, FAKE, 19, FAKE, ws, None) == HLN_ENOMEM       # capacity < min nnz
+    assert L.hln_compose_or(arr, 2, FAKE, FAKE, 49, FAKE, ws, None) == HLN_ENOMEM        # capacity < sum nnz
+    assert L.hln_compose_or(arr, 2, FAKE, FAKE, 50, FAKE, ws - 1, None) == HLN_ENOMEM
+    c = _csr(11, 20)
+    arr2 = (P._lib.hln_csr * 2)(a, c)
+    assert L.hln_compose_and(arr2, 2, FAKE, FAKE, 20, FAKE, ws, None) == HLN_EINVAL      # n mismatch
+    assert L.hln_compose_workspace_size(arr2, 2) == 0
+
+
+def test_select_argument_checks():
+    L = P.lib()
+    S = (ctypes.c_void_p * 2)(0x100000, 0x100000)
+    R = (ctypes.c_void_p * 2)(0x200000, 0x200000)
+    ws = L.hln_compose_cc_topk_workspace_size(100)
+    args = lambda mode, r, k, wsb=ws: L.hln_compose_cc_topk(mode, 100, r, ctypes.cast(S, ctypes.c_void_p),
+                                                           ctypes.cast(R, ctypes.c_void_p), k, FAKE, FAKE, FAKE,
+                                                           FAKE, wsb, None)
+    assert args(9, 1, 5) == HLN_EINVAL                    # bad mode
+    assert args(0, 2, 5) == HLN_EINVAL                    # WF ranks one graph
+    assert args(0, 1, 101) == HLN_EINVAL                  # k > n
+    assert args(0, 1, -2) == HLN_EINVAL
+    assert args(2, 2, 5) == HLN_EINVAL                    # naive needs k = -1
+    assert args(1, 2, 5, ws - 1) == HLN_ENOMEM

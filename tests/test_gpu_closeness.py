@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 P = pytest.importorskip("paper_2207_11662_amd")
 
-WIDTHS = [64, 128, 256, 512]
+WIDTHS = [64, 128, 256, 512, 1024, 2048]
 
 
 def run_all(rp, ci, width, want_h2=True, direction=0):

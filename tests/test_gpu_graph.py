@@ -1,0 +1,140 @@
+"""Parity of layer ingest (hln_csr_from_edges), CSR validation and AND / OR
+aggregation (hln_compose_and / hln_compose_or) with the CPU oracle:
+row pointers and column ids bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+from homln_inputs import configs as C
+from homln_inputs import generators as G
+from oracle import oracle as O
+from tests.gpu_common import csr_np, graph_dev, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2207_11662_amd")
+
+
+def ingest(n, eu, ev):
+    g = P.hln_csr_from_edges(n, to_dev(eu), to_dev(ev))
+    torch.cuda.synchronize()
+    P.device_status()
+    g = g.trimmed()
+    return g.row_ptr.cpu().numpy(), g.col_idx.cpu().numpy(), g
+
+
+def test_ingest_messy_edge_lists():
+    rng = np.random.default_rng(1)
+    for trial in range(12):
+        n = int(rng.integers(1, 3000))
+        m = int(rng.integers(0, 4 * n + 1))
+        eu = rng.integers(0, n, size=m).astype(np.int32)
+        ev = rng.integers(0, n, size=m).astype(np.int32)
+        if m and trial % 3 == 0:                       # repeated edges and both orientations
+            eu = np.concatenate([eu, ev[: m // 2]])
+            ev = np.concatenate([ev, eu[: m // 2]])
+        say("ingest", trial, n, len(eu))
+        rp, ci, _ = ingest(n, eu, ev)
+        rp_o, ci_o = O.csr_from_edges(n, eu, ev)
+        assert np.array_equal(rp, rp_o) and np.array_equal(ci, ci_o)
+
+
+def test_ingest_degenerate():
+    for n, eu, ev in [(1, [], []), (4, [], []), (3, [1, 1, 2], [1, 1, 2]), (2, [0, 1, 0], [1, 0, 1])]:
+        eu = np.array(eu, np.int32)
+        ev = np.array(ev, np.int32)
+        rp, ci, _ = ingest(n, eu, ev)
+        rp_o, ci_o = O.csr_from_edges(n, eu, ev)
+        assert np.array_equal(rp, rp_o) and np.array_equal(ci, ci_o)
+
+
+@pytest.mark.parametrize("cfg,scale", [(1, 1.0), (2, 1.0)])
+def test_ingest_configs(cfg, scale):
+    h = C.make_config(cfg, scale)
+    for li, (eu, ev) in enumerate(h.layers):
+        say("ingest cfg", cfg, li)
+        rp, ci, g = ingest(h.n, eu, ev)
+        rp_o, ci_o = O.csr_from_edges(h.n, eu, ev)
+        assert np.array_equal(rp, rp_o) and np.array_equal(ci, ci_o)
+        assert P.hln_csr_validate(g) == 0
+
+
+def test_ingest_rejects_out_of_range_ids():
+    eu = np.array([0, 1, 7], np.int32)
+    ev = np.array([1, 2, 0], np.int32)
+    P.hln_csr_from_edges(4, to_dev(eu), to_dev(ev))
+    with pytest.raises(P.HlnError):
+        P.device_status()
+    P.device_status()                                  # the fault word was cleared
+
+
+def test_validate_flags():
+    n, eu, ev = G.named_graph("cycle", 9)
+    rp, ci = csr_np(n, *G.to_edges(n, eu, ev))
+    assert P.hln_csr_validate(graph_dev(P, rp, ci)) == 0
+    bad = ci.copy()
+    bad[0], bad[1] = bad[1], bad[0]                    # unsorted row 0
+    assert P.hln_csr_validate(graph_dev(P, rp, bad)) & 4
+    bad = ci.copy()
+    bad[0] = 0                                         # self-loop at vertex 0, and asymmetric
+    assert P.hln_csr_validate(graph_dev(P, rp, bad)) & 8
+    bad = ci.copy()
+    bad[0] = 3                                         # 0->3 without 3->0
+    assert P.hln_csr_validate(graph_dev(P, rp, bad)) & 16
+    bad = ci.copy()
+    bad[0] = 99                                        # id out of range
+    assert P.hln_csr_validate(graph_dev(P, rp, bad)) & 2
+
+
+def compose_both(layers_np, n):
+    gs = [graph_dev(P, rp, ci) for rp, ci in layers_np]
+    out = {}
+    for mode, fn in (("and", P.hln_compose_and), ("or", P.hln_compose_or)):
+        g = fn(gs)
+        torch.cuda.synchronize()
+        P.device_status()
+        g = g.trimmed()
+        out[mode] = (g.row_ptr.cpu().numpy(), g.col_idx.cpu().numpy())
+    return out
+
+
+def test_compose_random():
+    rng = np.random.default_rng(2)
+    for trial in range(10):
+        n = int(rng.integers(2, 2000))
+        r = int(rng.integers(1, 7))
+        base = G.take_distinct(G.er_draw(n), min(n * 2, n * (n - 1) // 4), n, rng)
+        layers = []
+        for _ in range(r):
+            extra = G.take_distinct(G.er_draw(n), min(n, n * (n - 1) // 4), n, rng)
+            keep = base[rng.random(len(base)) < 0.7]
+            eu, ev = G.keys_to_edges(np.concatenate([keep, extra]), n)
+            layers.append(csr_np(n, eu, ev))
+        say("compose", trial, n, r)
+        got = compose_both(layers, n)
+        for mode in ("and", "or"):
+            rp_o, ci_o = O.compose(mode, layers)
+            assert np.array_equal(got[mode][0], rp_o) and np.array_equal(got[mode][1], ci_o), mode
+
+
+def test_compose_with_empty_and_identical_layers():
+    n, eu, ev = G.named_graph("hypercube", 6)
+    full = csr_np(n, *G.to_edges(n, eu, ev))
+    empty = (np.zeros(n + 1, np.int32), np.zeros(0, np.int32))
+    got = compose_both([full, empty], n)
+    assert got["and"][0][-1] == 0
+    assert np.array_equal(got["or"][0], full[0]) and np.array_equal(got["or"][1], full[1])
+    got = compose_both([full, full, full], n)
+    for mode in ("and", "or"):
+        assert np.array_equal(got[mode][0], full[0]) and np.array_equal(got[mode][1], full[1])
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_compose_configs(cfg):
+    h = C.make_config(cfg)
+    layers = [csr_np(h.n, *e) for e in h.layers]
+    say("compose cfg", cfg)
+    got = compose_both(layers, h.n)
+    for mode in ("and", "or"):
+        rp_o, ci_o = O.compose(mode, layers)
+        assert np.array_equal(got[mode][0], rp_o) and np.array_equal(got[mode][1], ci_o), mode
