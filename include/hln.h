@@ -62,6 +62,8 @@ typedef struct {
     int32_t width_bits;   /* sources per batch: 64, 128, 256, 512, 1024 or 2048; 0 = library default (512) */
     int32_t direction;    /* 0 = automatic per level, 1 = top-down only, 2 = bottom-up only */
     int32_t flags;        /* reserved, must be 0 */
+    int32_t* levels;      /* [dev] nullable: per batch of width_bits sources, the BFS levels run
+                             (1 + the largest eccentricity among the batch's sources) */
 } hln_opts;
 
 /* Thread-local text of the last error of this thread ("" if none). */

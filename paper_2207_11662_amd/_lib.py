@@ -42,7 +42,8 @@ class hln_csr(ctypes.Structure):
 
 
 class hln_opts(ctypes.Structure):
-    _fields_ = [("width_bits", ctypes.c_int32), ("direction", ctypes.c_int32), ("flags", ctypes.c_int32)]
+    _fields_ = [("width_bits", ctypes.c_int32), ("direction", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("levels", ctypes.c_void_p)]
 
 
 _lib = None
@@ -146,14 +147,16 @@ def device_status(stream=None):
 # ---------------------------------------------------------------------------
 
 def closeness_workspace_size(n: int, nnz: int, n_src: int, width_bits: int = 512, direction: int = 0) -> int:
-    o = hln_opts(width_bits, direction, 0)
+    o = hln_opts(width_bits, direction, 0, None)
     return int(lib().hln_closeness_workspace_size(n, nnz, n_src, ctypes.byref(o)))
 
 
 def hln_closeness_layer(g: Graph, sources: torch.Tensor | None = None, width_bits: int = 512,
                         direction: int = 0, want_cc: bool = True, want_h2: bool = False,
-                        out=None, ws: torch.Tensor | None = None, stream=None):
-    """Returns dict(S int64, R int32, cc float64 | None, h2 int32 | None)."""
+                        out=None, ws: torch.Tensor | None = None, stream=None, levels: torch.Tensor | None = None):
+    """Returns dict(S int64, R int32, cc float64 | None, h2 int32 | None).
+    `levels` (int32, ceil(n_src / width_bits) entries) receives the BFS levels
+    run per source batch."""
     dev = g.row_ptr.device
     n_src = g.n if sources is None else int(sources.numel())
     if sources is not None:
@@ -163,9 +166,9 @@ def hln_closeness_layer(g: Graph, sources: torch.Tensor | None = None, width_bit
                "R": torch.empty(max(n_src, 1), dtype=torch.int32, device=dev),
                "cc": torch.empty(max(n_src, 1), dtype=torch.float64, device=dev) if want_cc else None,
                "h2": torch.empty(max(n_src, 1), dtype=torch.int32, device=dev) if want_h2 else None}
-    o = hln_opts(width_bits, direction, 0)
+    o = hln_opts(width_bits, direction, 0, None if levels is None else levels.data_ptr())
     need = int(lib().hln_closeness_workspace_size(g.n, g.nnz, n_src, ctypes.byref(o)))
-    if ws is None:
+    if ws is None or ws.numel() < need:
         ws = workspace(need, dev)
     gc = g.c()
     check(lib().hln_closeness_layer(ctypes.byref(gc), _ptr(sources), n_src, ctypes.byref(o),

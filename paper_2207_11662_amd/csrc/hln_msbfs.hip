@@ -85,6 +85,7 @@ struct BfsArgs {
     int* fault;
     uint64_t wait_ticks;              // bound of one barrier wait (s_memrealtime ticks)
     int32_t direction;                // 0 auto, 1 top-down only, 2 bottom-up only
+    int32_t* levels;                  // nullable: levels run per batch
     int32_t seg_len;                  // SEG
     int32_t alpha;                    // switch to bottom-up when frontier arcs > total arcs / alpha
     int32_t beta;                     // switch back to top-down when frontier vertices < n / beta
@@ -418,7 +419,11 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
             }
             const hln::dev::BarrierResult br = grid_barrier_or(a.bar, any, a.fault, a.wait_ticks);
             if (!br.ok) return;
-            if (!br.any) break;
+            if (!br.any) {
+                // level d found nothing new: the batch's largest eccentricity is d - 1
+                if (a.levels && blockIdx.x == 0 && threadIdx.x == 0) a.levels[b] = d;
+                break;
+            }
             uint64_t* t = fr;
             fr = nx;
             nx = t;
@@ -633,6 +638,7 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
     a.fault = fault;
     a.wait_ticks = 1000000000ull;   // 10 s at 100 MHz
     a.direction = opts ? opts->direction : 0;
+    a.levels = opts ? opts->levels : nullptr;
     a.seg_len = kSegLen;
     a.alpha = 14;
     a.beta = 24;

@@ -41,7 +41,7 @@ def _csr(n=10, nnz=20):
 
 def test_closeness_argument_checks():
     L = P.lib()
-    o = P._lib.hln_opts(512, 0, 0)
+    o = P._lib.hln_opts(512, 0, 0, None)
     g = _csr()
     call = lambda **kw: L.hln_closeness_layer(kw.get("g", ctypes.byref(g)), kw.get("src", None), kw.get("n_src", 10),
                                               kw.get("opts", ctypes.byref(o)), kw.get("S", FAKE), kw.get("R", FAKE),
@@ -49,10 +49,10 @@ def test_closeness_argument_checks():
     assert call(g=None) == HLN_EINVAL
     assert call(S=None) == HLN_EINVAL
     assert call(n_src=9) == HLN_EINVAL                      # all-source mode needs n_src == n
-    bad = P._lib.hln_opts(100, 0, 0)
+    bad = P._lib.hln_opts(100, 0, 0, None)
     assert call(opts=ctypes.byref(bad)) == HLN_EINVAL
     assert b"width_bits" in L.hln_last_error()
-    bad = P._lib.hln_opts(512, 7, 0)
+    bad = P._lib.hln_opts(512, 7, 0, None)
     assert call(opts=ctypes.byref(bad)) == HLN_EINVAL
     assert call(ws=None) == HLN_EINVAL
     assert call(ws=ctypes.c_void_p(0x100001)) == HLN_EINVAL    # misaligned workspace

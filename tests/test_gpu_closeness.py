@@ -143,3 +143,20 @@ def test_config2_full_size_sampled():
         ncomp, lab = connected_components(adj, directed=False)
         sizes = np.bincount(lab)
         assert np.array_equal(got["R"], sizes[lab])
+
+
+@pytest.mark.parametrize("width", [64, 512, 2048])
+def test_levels_per_batch(width):
+    """The kernel's per-batch level count is 1 + the largest eccentricity of
+    the batch's sources (the L_b of the byte model), from the oracle."""
+    h = C.config1()
+    n = h.n
+    for rp, ci in [csr_np(n, *h.layers[0]), O.compose("and", [csr_np(n, *e) for e in h.layers])]:
+        nb = (n + width - 1) // width
+        lv = torch.zeros(nb, dtype=torch.int32, device="cuda")
+        g = graph_dev(P, rp, ci)
+        P.hln_closeness_layer(g, width_bits=width, levels=lv)
+        torch.cuda.synchronize()
+        _, _, _, ecc, _ = O.bfs_sums(rp, ci, extras=True)
+        ref = [1 + int(ecc[b * width:(b + 1) * width].max()) for b in range(nb)]
+        assert lv.cpu().numpy().tolist() == ref
