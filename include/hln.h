@@ -64,6 +64,11 @@ typedef struct {
     int32_t flags;        /* reserved, must be 0 */
     int32_t* levels;      /* [dev] nullable: per batch of width_bits sources, the BFS levels run
                              (1 + the largest eccentricity among the batch's sources) */
+    int64_t* trace;       /* [dev] nullable, zero-filled by the caller: per level run (in order, over
+                             all batches) 4 int64: s_memrealtime ticks (100 MHz) when the level's
+                             barrier completed, vertices given new bits, new (vertex, source) pairs,
+                             the level's direction (0 bottom-up, 1 top-down) */
+    int32_t trace_cap;    /* levels `trace` can hold; later levels are not recorded */
 } hln_opts;
 
 /* Thread-local text of the last error of this thread ("" if none). */

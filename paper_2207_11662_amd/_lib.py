@@ -43,7 +43,7 @@ class hln_csr(ctypes.Structure):
 
 class hln_opts(ctypes.Structure):
     _fields_ = [("width_bits", ctypes.c_int32), ("direction", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("levels", ctypes.c_void_p)]
+                ("levels", ctypes.c_void_p), ("trace", ctypes.c_void_p), ("trace_cap", ctypes.c_int32)]
 
 
 _lib = None
@@ -153,10 +153,12 @@ def closeness_workspace_size(n: int, nnz: int, n_src: int, width_bits: int = 512
 
 def hln_closeness_layer(g: Graph, sources: torch.Tensor | None = None, width_bits: int = 512,
                         direction: int = 0, want_cc: bool = True, want_h2: bool = False,
-                        out=None, ws: torch.Tensor | None = None, stream=None, levels: torch.Tensor | None = None):
+                        out=None, ws: torch.Tensor | None = None, stream=None, levels: torch.Tensor | None = None,
+                        trace: torch.Tensor | None = None):
     """Returns dict(S int64, R int32, cc float64 | None, h2 int32 | None).
     `levels` (int32, ceil(n_src / width_bits) entries) receives the BFS levels
-    run per source batch."""
+    run per source batch; `trace` (int64 [levels, 4], zero-filled) the
+    per-level trace described in include/hln.h."""
     dev = g.row_ptr.device
     n_src = g.n if sources is None else int(sources.numel())
     if sources is not None:
@@ -166,7 +168,8 @@ def hln_closeness_layer(g: Graph, sources: torch.Tensor | None = None, width_bit
                "R": torch.empty(max(n_src, 1), dtype=torch.int32, device=dev),
                "cc": torch.empty(max(n_src, 1), dtype=torch.float64, device=dev) if want_cc else None,
                "h2": torch.empty(max(n_src, 1), dtype=torch.int32, device=dev) if want_h2 else None}
-    o = hln_opts(width_bits, direction, 0, None if levels is None else levels.data_ptr())
+    o = hln_opts(width_bits, direction, 0, None if levels is None else levels.data_ptr(),
+                 None if trace is None else trace.data_ptr(), 0 if trace is None else trace.shape[0])
     need = int(lib().hln_closeness_workspace_size(g.n, g.nnz, n_src, ctypes.byref(o)))
     if ws is None or ws.numel() < need:
         ws = workspace(need, dev)

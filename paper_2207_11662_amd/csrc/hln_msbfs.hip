@@ -68,6 +68,8 @@ struct BfsArgs {
     const int32_t* sources;           // nullptr: all vertices, per-vertex accumulation
     uint64_t* bufA;                   // n*NW
     uint64_t* bufB;                   // n*NW
+    uint32_t* flagA;                  // n word masks: bit k clear implies bufA word k of v is zero
+    uint32_t* flagB;                  // n: the same for bufB
     uint64_t* vis;                    // n*NW
     uint64_t* hacc;                   // n*NW partial ORs of multi-segment rows (kept zero)
     int32_t* hcnt;                    // n finished-segment counters (kept zero)
@@ -86,17 +88,12 @@ struct BfsArgs {
     uint64_t wait_ticks;              // bound of one barrier wait (s_memrealtime ticks)
     int32_t direction;                // 0 auto, 1 top-down only, 2 bottom-up only
     int32_t* levels;                  // nullable: levels run per batch
+    int64_t* trace;                   // nullable: per level {ticks, vertices with new bits, new pairs, direction}
+    int32_t trace_cap;
     int32_t seg_len;                  // SEG
     int32_t alpha;                    // switch to bottom-up when frontier arcs > total arcs / alpha
     int32_t beta;                     // switch back to top-down when frontier vertices < n / beta
 };
-
-__device__ __forceinline__ uint64_t full_mask(int k, int cnt) {
-    int valid = cnt - 64 * k;
-    if (valid >= 64) return ~0ull;
-    if (valid <= 0) return 0ull;
-    return (1ull << valid) - 1ull;
-}
 
 __device__ __forceinline__ int seg_class(int deg, int seg_len) {
     if (deg > seg_len) return 0;
@@ -105,36 +102,51 @@ __device__ __forceinline__ int seg_class(int deg, int seg_len) {
     return 1 + (top - lg);                    // larger degree first
 }
 
+__device__ __forceinline__ int trace_add(int64_t* row, int verts, long long pairs) {
+    atomicAdd(reinterpret_cast<unsigned long long*>(row + 1), static_cast<unsigned long long>(verts));
+    atomicAdd(reinterpret_cast<unsigned long long*>(row + 2), static_cast<unsigned long long>(pairs));
+    return 0;
+}
+
 // Finalise vertex v at level d: new bits, bitset updates, accumulation.
 // Called by the 8 lanes of a group with the group's full OR in `acc` (lane
 // (sub, k) holds word k; only sub == 0 lanes write).
 template <int NW, bool PER_SOURCE>
-__device__ __forceinline__ int finalize_vertex(const BfsArgs& a, uint64_t* nx, int v, int d, int k, int sub, int gl,
-                                               uint64_t acc, uint64_t vis_v, int32_t* s_cnt, int64_t s_old,
-                                               int32_t r_old) {
+__device__ __forceinline__ int finalize_vertex(const BfsArgs& a, uint64_t* nx, uint32_t* flag_nx, int v, int d, int k,
+                                               int sub, int gl, int gbase, uint64_t acc, uint64_t vis_v,
+                                               int32_t* s_cnt, int64_t s_old, int32_t r_old, uint32_t flag_old) {
     constexpr int LPV = lpv<NW>();
+    constexpr uint32_t kWordMask = NW >= 32 ? 0xffffffffu : ((1u << NW) - 1u);
     const size_t base = static_cast<size_t>(v) * NW + k;
-    uint64_t nw = acc & ~vis_v;
-    int c = 0;
+    const uint64_t nw = acc & ~vis_v;
+    // lanes with sub == 0 hold word k at group lane k
+    const uint32_t nmask = static_cast<uint32_t>((__ballot(sub == 0 && nw != 0) >> gbase) & kWordMask);
+    int c = sub == 0 ? __popcll(nw) : 0;
+#pragma unroll
+    for (int off = 1; off < LPV; off <<= 1) c += shfl_xor_i32(c, off);
     if (sub == 0) {
-        nx[base] = nw;
-        if (nw) a.vis[base] = vis_v | nw;
-        c = __popcll(nw);
-        if (PER_SOURCE) {
-            uint64_t b = nw;
-            while (b) {
-                int bit = __ffsll(static_cast<long long>(b)) - 1;
-                b &= b - 1;
-                atomicAdd(&s_cnt[k * 64 + bit], 1);
+        // new bits go to the next frontier; a word that held an older
+        // frontier and has nothing new is cleared; other words stay zero
+        if (nw != 0 || ((flag_old >> k) & 1u)) nx[base] = nw;
+        if (nw) {
+            a.vis[base] = vis_v | nw;
+            if (PER_SOURCE) {
+                uint64_t b = nw;
+                while (b) {
+                    const int bit = __ffsll(static_cast<long long>(b)) - 1;
+                    b &= b - 1;
+                    atomicAdd(&s_cnt[k * 64 + bit], 1);
+                }
             }
         }
     }
-#pragma unroll
-    for (int off = 1; off < LPV; off <<= 1) c += shfl_xor_i32(c, off);
-    if (!PER_SOURCE && gl == 0 && c) {
-        a.S[v] = s_old + static_cast<int64_t>(d) * c;
-        a.R[v] = r_old + c;
-        if (d == 2 && a.H2) a.H2[v] += c;
+    if (gl == 0) {
+        if (nmask != flag_old) flag_nx[v] = nmask;
+        if (!PER_SOURCE && c) {
+            a.S[v] = s_old + static_cast<int64_t>(d) * c;
+            a.R[v] = r_old + c;
+            if (d == 2 && a.H2) a.H2[v] += c;
+        }
     }
     return c;
 }
@@ -157,8 +169,16 @@ struct Gather {
         for (int h = 0; h < CH; ++h) cid[h] = (c + h * LPV + gl < hi) ? col_idx[c + h * LPV + gl] : -1;
     }
 
-    __device__ __forceinline__ static uint64_t round_or(const uint64_t* __restrict__ fr, const int (&cid)[CH], int k,
-                                                        int sub, int gbase) {
+    // word masks of the neighbours' frontier slots (0 for no neighbour)
+    __device__ __forceinline__ static void load_masks(const uint32_t* __restrict__ flag_fr, const int (&cid)[CH],
+                                                      uint32_t (&msk)[CH]) {
+#pragma unroll
+        for (int h = 0; h < CH; ++h) msk[h] = cid[h] >= 0 ? flag_fr[cid[h]] : 0u;
+    }
+
+    // only the words whose mask bit is set are gathered
+    __device__ __forceinline__ static uint64_t round_or(const uint64_t* __restrict__ fr, const int (&cid)[CH],
+                                                        const uint32_t (&msk)[CH], int k, int sub, int gbase) {
         uint64_t x = 0;
 #pragma unroll
         for (int t = 0; t < NW; ++t) {
@@ -166,42 +186,54 @@ struct Gather {
 #pragma unroll
             for (int h = 0; h < CH; ++h) {
                 const int w = __shfl(cid[h], gbase + j, 64);
-                if (w >= 0) x |= fr[static_cast<size_t>(w) * NW + k];
+                const uint32_t m = static_cast<uint32_t>(__shfl(static_cast<int>(msk[h]), gbase + j, 64));
+                if ((m >> k) & 1u) x |= fr[static_cast<size_t>(w) * NW + k];
             }
         }
         return x;
     }
 };
 
-// What a group reads for a segment before gathering: the record, the
-// first round of column ids, the vertex's visited word and (for
-// single-segment rows in all-source mode) its accumulators.  Loaded one
-// segment ahead so that these reads overlap the previous segment's gathers.
+// What a group reads for a segment before gathering: the record, the first
+// round of column ids, the activity flags of those neighbours, the flag of
+// the vertex's next-frontier slot and (single-segment rows, all-source mode)
+// its accumulators.  The segment loop runs a three-stage pipeline -- records
+// three segments ahead, ids and accumulators two ahead, neighbour flags one
+// ahead -- so that a segment waits only for its own frontier gathers.
 template <int NW>
 struct SegPre {
     int4 sg;
     int cid[Gather<NW>::CH];
-    uint64_t vis;
+    uint32_t fl[Gather<NW>::CH]; // frontier word masks of the neighbours in cid
     int64_t s_old;
     int32_t r_old;
+    uint32_t flag_old;           // word mask of the vertex's next-frontier slot
 };
 
 template <int NW, bool PER_SOURCE>
-__device__ __forceinline__ void seg_prefetch(const BfsArgs& a, const int4 sg, bool valid, int gl, int k,
-                                             SegPre<NW>& p) {
+__device__ __forceinline__ void seg_prefetch(const BfsArgs& a, const uint32_t* flag_nx, const int4 sg, bool valid,
+                                             int gl, SegPre<NW>& p) {
     p.sg = sg;
     p.s_old = 0;
     p.r_old = 0;
-    p.vis = 0;
+    p.flag_old = 0;
 #pragma unroll
-    for (int h = 0; h < Gather<NW>::CH; ++h) p.cid[h] = -1;
+    for (int h = 0; h < Gather<NW>::CH; ++h) {
+        p.cid[h] = -1;
+        p.fl[h] = 0;
+    }
     if (!valid) return;
     Gather<NW>::load_ids(a.col_idx, sg.y, sg.z, gl, p.cid);
-    p.vis = a.vis[static_cast<size_t>(sg.x) * NW + k];
+    if (sg.w == 1) p.flag_old = flag_nx[sg.x];
     if (!PER_SOURCE && gl == 0 && sg.w == 1) {
         p.s_old = a.S[sg.x];
         p.r_old = a.R[sg.x];
     }
+}
+
+template <int NW>
+__device__ __forceinline__ void seg_flags(const uint32_t* __restrict__ flag_fr, SegPre<NW>& p) {
+    Gather<NW>::load_masks(flag_fr, p.cid, p.fl);
 }
 
 template <int NW, int BLOCK, bool PER_SOURCE>
@@ -225,6 +257,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
     __shared__ int64_t s_S[PER_SOURCE ? W : 1];
     __shared__ int32_t s_R[PER_SOURCE ? W : 1];
     __shared__ int s_bins[kClasses];
+    __shared__ long long s_trace[2];
 
     // ---- phase 0: zero accumulators and scratch, check the input, count
     // segments per class.  The input is checked here so that no later access
@@ -255,7 +288,14 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
         for (long long i = tid; i < a.n_src; i += nthreads)
             bad |= static_cast<unsigned>(a.sources[i]) >= static_cast<unsigned>(n);
     if (bad) store_agent_i32(a.fault, 2);
-    for (long long i = tid; i < static_cast<long long>(n) * NW; i += nthreads) a.hacc[i] = 0;
+    for (long long i = tid; i < static_cast<long long>(n) * NW; i += nthreads) {
+        a.hacc[i] = 0;
+        a.bufB[i] = 0;
+    }
+    for (long long v = tid; v < n; v += nthreads) {
+        a.flagA[v] = 0;
+        a.flagB[v] = 0;
+    }
     __syncthreads();
     if (threadIdx.x < kClasses && s_bins[threadIdx.x]) atomicAdd(&ctrl->bins[threadIdx.x], s_bins[threadIdx.x]);
     if (!grid_barrier(a.bar, a.fault, a.wait_ticks)) return;
@@ -290,6 +330,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
     const long long n_seg = min(static_cast<long long>(load_agent_i32(&ctrl->n_seg)), a.seg_cap);
 
     const int n_batches = (a.n_src + W - 1) / W;
+    int trace_row = 0;
     for (int b = 0; b < n_batches; ++b) {
         const int src0 = b * W;
         const int cnt = min(W, a.n_src - src0);
@@ -305,11 +346,14 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                 a.vis[i] = w0;
                 a.bufA[i] = w0;
             }
+            for (long long v = tid; v < n; v += nthreads)
+                a.flagA[v] = (v >= src0 && v < src0 + cnt) ? (1u << ((v - src0) >> 6)) : 0u;
         } else {
             for (long long i = tid; i < static_cast<long long>(n) * NW; i += nthreads) {
                 a.vis[i] = 0;
                 a.bufA[i] = 0;
             }
+            for (long long v = tid; v < n; v += nthreads) a.flagA[v] = 0;
             for (int i = threadIdx.x; i < W; i += BLOCK) {
                 s_cnt[i] = 0;
                 s_S[i] = 0;
@@ -321,6 +365,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                 const size_t w = static_cast<size_t>(s) * NW + (i >> 6);
                 atomicOr(reinterpret_cast<unsigned long long*>(&a.vis[w]), 1ull << (i & 63));
                 atomicOr(reinterpret_cast<unsigned long long*>(&a.bufA[w]), 1ull << (i & 63));
+                atomicOr(&a.flagA[s], 1u << (i >> 6));
             }
         }
         if (!grid_barrier(a.bar, a.fault, a.wait_ticks)) return;
@@ -329,43 +374,62 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
         // vertex got a new bit, which ends this batch's BFS
         uint64_t* fr = a.bufA;
         uint64_t* nx = a.bufB;
-        const uint64_t fm = full_mask(k, cnt);
+        uint32_t* flag_fr = a.flagA;
+        uint32_t* flag_nx = a.flagB;
         for (int d = 1;; ++d) {
             int any = 0;
-            // software pipeline: records two segments ahead, the column ids,
-            // visited word and accumulators one segment ahead
+            long long t_pairs = 0;
+            int t_verts = 0;
             long long s = gid;
-            SegPre<NW> cur;
-            seg_prefetch<NW, PER_SOURCE>(a, s < n_seg ? a.seg[s] : make_int4(0, 0, 0, 0), s < n_seg, gl, k, cur);
-            int4 rec2 = s + ngroups < n_seg ? a.seg[s + ngroups] : make_int4(0, 0, 0, 0);
+            const int4 kNone = make_int4(0, 0, 0, 0);
+            SegPre<NW> cur, nxt;
+            seg_prefetch<NW, PER_SOURCE>(a, flag_nx, s < n_seg ? a.seg[s] : kNone, s < n_seg, gl, cur);
+            seg_prefetch<NW, PER_SOURCE>(a, flag_nx, s + ngroups < n_seg ? a.seg[s + ngroups] : kNone,
+                                         s + ngroups < n_seg, gl, nxt);
+            seg_flags<NW>(flag_fr, cur);
+            int4 rec2 = s + 2 * ngroups < n_seg ? a.seg[s + 2 * ngroups] : kNone;
             while (s < n_seg) {
                 const long long s1 = s + ngroups;
                 const long long s2 = s1 + ngroups;
-                const int4 rec3 = s2 < n_seg ? a.seg[s2] : make_int4(0, 0, 0, 0);
-                SegPre<NW> nxt;
-                seg_prefetch<NW, PER_SOURCE>(a, rec2, s1 < n_seg, gl, k, nxt);
+                const long long s3 = s2 + ngroups;
+                const int4 rec3 = s3 < n_seg ? a.seg[s3] : kNone;                  // record, 3 ahead
+                SegPre<NW> nn;
+                seg_prefetch<NW, PER_SOURCE>(a, flag_nx, rec2, s2 < n_seg, gl, nn);  // ids, 2 ahead
+                seg_flags<NW>(flag_fr, nxt);                                        // flags, 1 ahead
 
                 const int v = cur.sg.x;
                 const int nseg = cur.sg.w;
                 const size_t base = static_cast<size_t>(v) * NW + k;
-                const uint64_t vis_v = cur.vis;
-                int done = (vis_v & fm) == fm;
+                bool active = false;
 #pragma unroll
-                for (int off = 1; off < NW; off <<= 1) done &= shfl_xor_i32(done, off);
+                for (int h = 0; h < Gather<NW>::CH; ++h) active |= cur.fl[h] != 0u;
+                // the visited word is read only when a neighbour is active, the
+                // segment has further rounds or the row has several segments (its
+                // finaliser needs it), together with the gathers
+                const unsigned long long gmask = (kLpv >= 64 ? ~0ull : ((1ull << kLpv) - 1ull)) << gbase;
+                const bool need = ((__ballot(active) & gmask) != 0) || (cur.sg.z - cur.sg.y > Gather<NW>::ROUND) ||
+                                  nseg > 1;
+                uint64_t vis_v = 0;
                 uint64_t acc = 0;
-                if (!done) {
-                    acc = Gather<NW>::round_or(fr, cur.cid, k, sub, gbase);
+                if (need) {
+                    vis_v = a.vis[base];
+                    acc = Gather<NW>::round_or(fr, cur.cid, cur.fl, k, sub, gbase);
                     for (int c = cur.sg.y + Gather<NW>::ROUND; c < cur.sg.z; c += Gather<NW>::ROUND) {
                         int cid[Gather<NW>::CH];
+                        uint32_t msk[Gather<NW>::CH];
                         Gather<NW>::load_ids(a.col_idx, c, cur.sg.z, gl, cid);
-                        acc |= Gather<NW>::round_or(fr, cid, k, sub, gbase);
+                        Gather<NW>::load_masks(flag_fr, cid, msk);
+                        acc |= Gather<NW>::round_or(fr, cid, msk, k, sub, gbase);
                     }
                 }
 #pragma unroll
                 for (int off = NW; off < kLpv; off <<= 1) acc |= shfl_xor_u64(acc, off);
                 if (nseg == 1) {
-                    any |= finalize_vertex<NW, PER_SOURCE>(a, nx, v, d, k, sub, gl, acc, vis_v, s_cnt, cur.s_old,
-                                                           cur.r_old);
+                    const int c = finalize_vertex<NW, PER_SOURCE>(a, nx, flag_nx, v, d, k, sub, gl, gbase, acc, vis_v,
+                                                                  s_cnt, cur.s_old, cur.r_old, cur.flag_old);
+                    any |= c;
+                    t_pairs += c;
+                    t_verts += c != 0;
                 } else {
                     // multi-segment row: merge, the last finisher finalises
                     if (sub == 0 && acc)
@@ -391,6 +455,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                         for (int off = NW; off < kLpv; off <<= 1) full |= shfl_xor_u64(full, off);
                         int64_t s_old = 0;
                         int32_t r_old = 0;
+                        const uint32_t flag_old = flag_nx[v];
                         if (gl == 0) {
                             store_agent_i32(&a.hcnt[v], 0);
                             if (!PER_SOURCE) {
@@ -398,12 +463,16 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                                 r_old = a.R[v];
                             }
                         }
-                        any |= finalize_vertex<NW, PER_SOURCE>(a, nx, v, d, k, sub, gl, full, vis_v, s_cnt, s_old,
-                                                               r_old);
+                        const int c = finalize_vertex<NW, PER_SOURCE>(a, nx, flag_nx, v, d, k, sub, gl, gbase, full,
+                                                                      vis_v, s_cnt, s_old, r_old, flag_old);
+                        any |= c;
+                        t_pairs += c;
+                        t_verts += c != 0;
                     }
                 }
                 s = s1;
                 cur = nxt;
+                nxt = nn;
                 rec2 = rec3;
             }
             if (PER_SOURCE) {
@@ -417,8 +486,26 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                     }
                 }
             }
+            if (a.trace && trace_row < a.trace_cap) {
+                // block totals in LDS, then one global add per block
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    s_trace[0] = 0;
+                    s_trace[1] = 0;
+                }
+                __syncthreads();
+                if (gl == 0 && t_verts) {
+                    atomicAdd(reinterpret_cast<unsigned long long*>(&s_trace[0]), static_cast<unsigned long long>(t_verts));
+                    atomicAdd(reinterpret_cast<unsigned long long*>(&s_trace[1]), static_cast<unsigned long long>(t_pairs));
+                }
+                __syncthreads();
+                if (threadIdx.x == 0 && s_trace[0]) (void)trace_add(a.trace + 4 * trace_row, s_trace[0], s_trace[1]);
+            }
             const hln::dev::BarrierResult br = grid_barrier_or(a.bar, any, a.fault, a.wait_ticks);
             if (!br.ok) return;
+            if (a.trace && trace_row < a.trace_cap && blockIdx.x == 0 && threadIdx.x == 0)
+                a.trace[4 * trace_row] = static_cast<int64_t>(__builtin_amdgcn_s_memrealtime());
+            ++trace_row;
             if (!br.any) {
                 // level d found nothing new: the batch's largest eccentricity is d - 1
                 if (a.levels && blockIdx.x == 0 && threadIdx.x == 0) a.levels[b] = d;
@@ -427,6 +514,9 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
             uint64_t* t = fr;
             fr = nx;
             nx = t;
+            uint32_t* tf = flag_fr;
+            flag_fr = flag_nx;
+            flag_nx = tf;
         }
 
         if (PER_SOURCE) {
@@ -561,6 +651,7 @@ size_t workspace_bytes(int32_t n, int64_t nnz, int nw, int grid_cap) {
     b += Arena::round(sizeof(Ctrl));
     b += Arena::round(hln::dev::kBarrierWords * sizeof(unsigned long long));
     b += 4 * Arena::round(words * sizeof(uint64_t));            // A, B, vis, hacc
+    b += 2 * Arena::round(static_cast<size_t>(n) * 4);          // word masks of A, B
     b += Arena::round(static_cast<size_t>(n) * sizeof(int32_t)); // hcnt
     b += Arena::round(seg_cap * sizeof(int4));
     b += Arena::round(static_cast<size_t>(grid_cap) * 2 * 64 * nw * sizeof(int64_t));  // per-source partials
@@ -626,6 +717,8 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
     a.bufB = ar.take<uint64_t>(words);
     a.vis = ar.take<uint64_t>(words);
     a.hacc = ar.take<uint64_t>(words);
+    a.flagA = ar.take<uint32_t>(n);
+    a.flagB = ar.take<uint32_t>(n);
     a.hcnt = ar.take<int32_t>(n);
     a.seg_cap = static_cast<long long>(n) + g->nnz / kSegLen + 1;
     a.seg = ar.take<int4>(static_cast<size_t>(a.seg_cap));
@@ -639,10 +732,12 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
     a.wait_ticks = 1000000000ull;   // 10 s at 100 MHz
     a.direction = opts ? opts->direction : 0;
     a.levels = opts ? opts->levels : nullptr;
+    a.trace = opts ? opts->trace : nullptr;
+    a.trace_cap = opts ? opts->trace_cap : 0;
     a.seg_len = kSegLen;
     a.alpha = 14;
     a.beta = 24;
-    if (!a.ctrl || !a.bar || !a.part) return fail(HLN_ENOMEM, "workspace carve failed");
+    if (!a.ctrl || !a.bar || !a.part || !a.flagB) return fail(HLN_ENOMEM, "workspace carve failed");
 
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(k_zero_ctrl, dim3(1), dim3(256), 0, st, a.ctrl, a.bar);
