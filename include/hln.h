@@ -164,6 +164,43 @@ hln_status hln_compose_cc_topk(int32_t mode, int32_t n, int32_t r, const int64_t
                                int32_t k, int32_t* ids, double* score, int32_t* count,
                                void* workspace, size_t workspace_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched closeness of many graphs (Sec. 3: every layer is analysed
+ * independently and in parallel; the layers and AND / OR aggregates of many
+ * HoMLNs in one persistent launch per source-width class).
+ * ------------------------------------------------------------------------
+ * A plan is an opaque host object: tuned source widths per graph-size class,
+ * pinned staging for the per-call descriptors, and optionally one captured
+ * hipGraph of a whole batch.  Plans are not thread-safe; destroy with
+ * hln_plan_destroy (waits for its staging copies).
+ * Graphs: n in [1, 65535] (tile graphs keep frontier and next bitsets of the
+ * whole graph in LDS); larger graphs use hln_closeness_layer.
+ * S[g], R[g], cc[g], h2[g]: host arrays of n_graphs device pointers (n_g
+ * entries each); cc and h2 (arrays or entries) nullable.  Every source of
+ * every graph is used; outputs as hln_closeness_layer's all-source mode.
+ * hln_plan_tune times, for each log2(n) class present, the class's largest
+ * graph with every source width whose bitsets fit in LDS (64/32/16/8) and
+ * keeps the fastest; it synchronises `stream` and overwrites that graph's
+ * S and R.  hln_plan_width reports the width a graph of n vertices gets.
+ * hln_plan_capture records the whole batch (staging copy, preparation,
+ * tile launches, closeness pass) into a hipGraph owned by the plan, which
+ * hln_plan_replay launches on `stream`; the captured buffers must stay
+ * valid while replays are possible.  Capture needs a non-null stream. */
+typedef struct hln_plan hln_plan;
+hln_status hln_plan_create(hln_plan** plan);
+void hln_plan_destroy(hln_plan* plan);
+int32_t hln_plan_width(const hln_plan* plan, int32_t n);
+size_t hln_closeness_batch_workspace_size(const hln_plan* plan, const hln_csr* graphs, int32_t n_graphs);
+hln_status hln_closeness_batch(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs, int64_t* const* S,
+                               int32_t* const* R, double* const* cc, int32_t* const* h2,
+                               void* workspace, size_t workspace_bytes, void* stream);
+hln_status hln_plan_tune(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs, int64_t* const* S,
+                         int32_t* const* R, void* workspace, size_t workspace_bytes, void* stream);
+hln_status hln_plan_capture(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs, int64_t* const* S,
+                            int32_t* const* R, double* const* cc, int32_t* const* h2,
+                            void* workspace, size_t workspace_bytes, void* stream);
+hln_status hln_plan_replay(hln_plan* plan, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

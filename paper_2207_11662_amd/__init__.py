@@ -6,5 +6,5 @@ from ._lib import (  # noqa: F401
     HLN_RANK_WF, HLN_RANK_CC2, HLN_RANK_NAIVE,
     closeness_workspace_size, compose_workspace_size,
     hln_closeness_layer, hln_csr_from_edges, hln_csr_validate, hln_compose_and, hln_compose_or,
-    hln_compose_cc_topk,
+    hln_compose_cc_topk, Plan,
 )

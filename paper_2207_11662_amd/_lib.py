@@ -25,6 +25,8 @@ EXPORTS = [
     "hln_compose_workspace_size", "hln_compose_and", "hln_compose_or",
     "hln_closeness_workspace_size", "hln_closeness_layer",
     "hln_compose_cc_topk_workspace_size", "hln_compose_cc_topk",
+    "hln_plan_create", "hln_plan_destroy", "hln_plan_width", "hln_closeness_batch_workspace_size",
+    "hln_closeness_batch", "hln_plan_tune", "hln_plan_capture", "hln_plan_replay",
 ]
 
 HLN_RANK_WF, HLN_RANK_CC2, HLN_RANK_NAIVE = 0, 1, 2
@@ -76,6 +78,14 @@ def lib():
         "hln_closeness_layer": ([csr_p, P, i32, opts_p, P, P, P, P, P, sz, P], st),
         "hln_compose_cc_topk_workspace_size": ([i32], sz),
         "hln_compose_cc_topk": ([i32, i32, i32, P, P, i32, P, P, P, P, sz, P], st),
+        "hln_plan_create": ([ctypes.POINTER(ctypes.c_void_p)], st),
+        "hln_plan_destroy": ([P], None),
+        "hln_plan_width": ([P, i32], i32),
+        "hln_closeness_batch_workspace_size": ([P, csr_p, i32], sz),
+        "hln_closeness_batch": ([P, csr_p, i32, P, P, P, P, P, sz, P], st),
+        "hln_plan_tune": ([P, csr_p, i32, P, P, P, sz, P], st),
+        "hln_plan_capture": ([P, csr_p, i32, P, P, P, P, P, sz, P], st),
+        "hln_plan_replay": ([P, P], st),
     }
     for name, (args, res) in sig.items():
         if hasattr(L, name):
@@ -268,3 +278,86 @@ def hln_compose_cc_topk(mode: int, n: int, S_list, R_list, k: int, ws=None, out=
                                     k, _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _ptr(ws), ws.numel(),
                                     _stream(stream)))
     return out
+
+
+# ---------------------------------------------------------------------------
+# a8: batched closeness (persistent LDS tiles, hipGraph capture, autotuner)
+# ---------------------------------------------------------------------------
+
+def _ptr_array(tensors):
+    if tensors is None:
+        return None
+    arr = (ctypes.c_void_p * len(tensors))(*[None if t is None else t.data_ptr() for t in tensors])
+    return ctypes.cast(arr, ctypes.c_void_p)
+
+
+class Plan:
+    """Owner of an hln_plan (tuned widths, staging, captured graph)."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        check(lib().hln_plan_create(ctypes.byref(h)))
+        self.h = h
+        self._keep = None
+
+    def close(self):
+        if self.h:
+            lib().hln_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def width(self, n: int) -> int:
+        return int(lib().hln_plan_width(self.h, n))
+
+    def _args(self, graphs, outs):
+        arr = _layers_c(graphs)
+        S = _ptr_array([o["S"] for o in outs])
+        R = _ptr_array([o["R"] for o in outs])
+        cc = _ptr_array([o.get("cc") for o in outs])
+        h2 = _ptr_array([o.get("h2") for o in outs]) if any(o.get("h2") is not None for o in outs) else None
+        return arr, S, R, cc, h2
+
+    def workspace_size(self, graphs) -> int:
+        arr = _layers_c(graphs)
+        return int(lib().hln_closeness_batch_workspace_size(self.h, arr, len(graphs)))
+
+    @staticmethod
+    def outputs(graphs, want_h2=False):
+        out = []
+        for g in graphs:
+            dev = g.row_ptr.device
+            out.append({"S": torch.empty(g.n, dtype=torch.int64, device=dev),
+                        "R": torch.empty(g.n, dtype=torch.int32, device=dev),
+                        "cc": torch.empty(g.n, dtype=torch.float64, device=dev),
+                        "h2": torch.empty(g.n, dtype=torch.int32, device=dev) if want_h2 else None})
+        return out
+
+    def run(self, graphs, outs, ws=None, stream=None):
+        arr, S, R, cc, h2 = self._args(graphs, outs)
+        need = self.workspace_size(graphs)
+        if ws is None or ws.numel() < need:
+            ws = workspace(need, graphs[0].row_ptr.device)
+        check(lib().hln_closeness_batch(self.h, arr, len(graphs), S, R, cc, h2, _ptr(ws), ws.numel(),
+                                        _stream(stream)))
+        return ws
+
+    def tune(self, graphs, outs, ws=None, stream=None):
+        arr, S, R, _, _ = self._args(graphs, outs)
+        need = self.workspace_size(graphs)
+        if ws is None or ws.numel() < need:
+            ws = workspace(need, graphs[0].row_ptr.device)
+        check(lib().hln_plan_tune(self.h, arr, len(graphs), S, R, _ptr(ws), ws.numel(), _stream(stream)))
+
+    def capture(self, graphs, outs, ws, stream):
+        arr, S, R, cc, h2 = self._args(graphs, outs)
+        self._keep = (graphs, outs, ws)       # captured buffers must outlive replays
+        check(lib().hln_plan_capture(self.h, arr, len(graphs), S, R, cc, h2, _ptr(ws), ws.numel(),
+                                     _stream(stream)))
+
+    def replay(self, stream=None):
+        check(lib().hln_plan_replay(self.h, _stream(stream)))

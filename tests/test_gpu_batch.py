@@ -1,0 +1,115 @@
+"""Parity of the batched path (hln_closeness_batch: persistent LDS tiles,
+hipGraph capture and replay, autotuned widths) with the CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+from homln_inputs import configs as C
+from homln_inputs import generators as G
+from oracle import oracle as O
+from tests.gpu_common import csr_np, graph_dev, say
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2207_11662_amd")
+
+
+def check(graphs_np, outs, tag):
+    for i, ((rp, ci), o) in enumerate(zip(graphs_np, outs)):
+        n = len(rp) - 1
+        S, R, H2, _, _ = O.bfs_sums(rp, ci, extras=True)
+        cc = O.closeness_wf(n, S, R)
+        assert np.array_equal(o["S"].cpu().numpy(), S), (tag, i)
+        assert np.array_equal(o["R"].cpu().numpy(), R), (tag, i)
+        assert np.array_equal(o["cc"].cpu().numpy().view(np.int64), cc.view(np.int64)), (tag, i)
+        if o.get("h2") is not None:
+            assert np.array_equal(o["h2"].cpu().numpy(), H2), (tag, i)
+
+
+def mixed_graphs(seed, sizes):
+    rng = np.random.default_rng(seed)
+    out = []
+    for n in sizes:
+        m = int(n * rng.choice([0.4, 1.0, 3.0, 6.0]))
+        keys = G.take_distinct(G.er_draw(n), min(m, n * (n - 1) // 2), n, rng)
+        out.append(csr_np(n, *G.keys_to_edges(keys, n)))
+    return out
+
+
+def test_batch_mixed_sizes_all_width_classes():
+    # sizes chosen so that the widest fitting word is 64, 32, 16 and 8 bits
+    sizes = [1, 2, 5, 63, 64, 65, 700, 3000, 9000, 20000, 38000, 60000]
+    gnp = mixed_graphs(1, sizes)
+    plan = P.Plan()
+    say("widths", [plan.width(n) for n in sizes])
+    graphs = [graph_dev(P, rp, ci) for rp, ci in gnp]
+    outs = P.Plan.outputs(graphs, want_h2=True)
+    plan.run(graphs, outs)
+    torch.cuda.synchronize()
+    P.device_status()
+    check(gnp, outs, "mixed")
+
+
+def test_batch_config1_and_named():
+    h = C.config1()
+    layers = [csr_np(h.n, *e) for e in h.layers]
+    gnp = layers + [O.compose("and", layers), O.compose("or", layers)]
+    for kind, arg in [("star", 500), ("path", 300), ("complete", 90), ("hypercube", 9)]:
+        n, eu, ev = G.named_graph(kind, arg)
+        gnp.append(csr_np(n, *G.to_edges(n, eu, ev)))
+    plan = P.Plan()
+    graphs = [graph_dev(P, rp, ci) for rp, ci in gnp]
+    outs = P.Plan.outputs(graphs, want_h2=True)
+    plan.run(graphs, outs)
+    torch.cuda.synchronize()
+    P.device_status()
+    check(gnp, outs, "cfg1")
+
+
+def test_batch_config3_subset():
+    gnp = []
+    for hh in range(3):
+        hm = C.config3_homln(hh, scale=0.25)
+        layers = [csr_np(hm.n, *e) for e in hm.layers]
+        gnp += layers + [O.compose("and", layers)]
+    say("cfg3 subset graphs", len(gnp), [len(g[0]) - 1 for g in gnp])
+    plan = P.Plan()
+    graphs = [graph_dev(P, rp, ci) for rp, ci in gnp]
+    outs = P.Plan.outputs(graphs)
+    plan.run(graphs, outs)
+    torch.cuda.synchronize()
+    P.device_status()
+    check(gnp, outs, "cfg3")
+
+
+def test_batch_capture_replay_and_tune():
+    gnp = mixed_graphs(7, [100, 1500, 5000, 12000])
+    graphs = [graph_dev(P, rp, ci) for rp, ci in gnp]
+    plan = P.Plan()
+    outs = P.Plan.outputs(graphs)
+    plan.tune(graphs, outs)
+    say("tuned widths", [plan.width(g.n) for g in graphs])
+    ws = P.workspace(plan.workspace_size(graphs))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan.capture(graphs, outs, ws, stream)
+    for rep in range(3):
+        for o in outs:                          # eager work between replays
+            o["S"].fill_(-1)
+            o["R"].fill_(-1)
+            o["cc"].fill_(-1.0)
+        torch.cuda.synchronize()
+        plan.replay(stream)
+        stream.synchronize()
+        P.device_status()
+        check(gnp, outs, "replay%d" % rep)
+
+
+def test_batch_rejects_large_graph():
+    plan = P.Plan()
+    n = 70000
+    rp = np.zeros(n + 1, np.int32)
+    g = graph_dev(P, rp, np.zeros(0, np.int32))
+    outs = P.Plan.outputs([g])
+    with pytest.raises(P.HlnError):
+        plan.run([g], outs)
