@@ -185,7 +185,11 @@ hln_status hln_compose_cc_topk(int32_t mode, int32_t n, int32_t r, const int64_t
  * hln_plan_capture records the whole batch (staging copy, preparation,
  * tile launches, closeness pass) into a hipGraph owned by the plan, which
  * hln_plan_replay launches on `stream`; the captured buffers must stay
- * valid while replays are possible.  Capture needs a non-null stream. */
+ * valid while replays are possible.  Capture needs a non-null stream.
+ * hln_closeness_batch may also be called while the caller captures
+ * `stream` into a graph of its own: call hln_plan_reserve for the same
+ * graphs before that capture (it allocates the staging that the captured
+ * copy reads; one such capture per plan). */
 typedef struct hln_plan hln_plan;
 hln_status hln_plan_create(hln_plan** plan);
 void hln_plan_destroy(hln_plan* plan);
@@ -199,6 +203,7 @@ hln_status hln_plan_tune(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs
 hln_status hln_plan_capture(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs, int64_t* const* S,
                             int32_t* const* R, double* const* cc, int32_t* const* h2,
                             void* workspace, size_t workspace_bytes, void* stream);
+hln_status hln_plan_reserve(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs);
 hln_status hln_plan_replay(hln_plan* plan, void* stream);
 
 #ifdef __cplusplus

@@ -26,7 +26,7 @@ EXPORTS = [
     "hln_closeness_workspace_size", "hln_closeness_layer",
     "hln_compose_cc_topk_workspace_size", "hln_compose_cc_topk",
     "hln_plan_create", "hln_plan_destroy", "hln_plan_width", "hln_closeness_batch_workspace_size",
-    "hln_closeness_batch", "hln_plan_tune", "hln_plan_capture", "hln_plan_replay",
+    "hln_closeness_batch", "hln_plan_tune", "hln_plan_capture", "hln_plan_replay", "hln_plan_reserve",
 ]
 
 HLN_RANK_WF, HLN_RANK_CC2, HLN_RANK_NAIVE = 0, 1, 2
@@ -86,6 +86,7 @@ def lib():
         "hln_plan_tune": ([P, csr_p, i32, P, P, P, sz, P], st),
         "hln_plan_capture": ([P, csr_p, i32, P, P, P, P, P, sz, P], st),
         "hln_plan_replay": ([P, P], st),
+        "hln_plan_reserve": ([P, csr_p, i32], st),
     }
     for name, (args, res) in sig.items():
         if hasattr(L, name):
@@ -358,6 +359,11 @@ class Plan:
         self._keep = (graphs, outs, ws)       # captured buffers must outlive replays
         check(lib().hln_plan_capture(self.h, arr, len(graphs), S, R, cc, h2, _ptr(ws), ws.numel(),
                                      _stream(stream)))
+
+    def reserve(self, graphs):
+        """Staging for a capture made by the caller (e.g. torch.cuda.graph)."""
+        arr = _layers_c(graphs)
+        check(lib().hln_plan_reserve(self.h, arr, len(graphs)))
 
     def replay(self, stream=None):
         check(lib().hln_plan_replay(self.h, _stream(stream)))

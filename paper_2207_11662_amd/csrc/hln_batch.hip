@@ -36,7 +36,9 @@
 
 struct hln_plan {
     int device = -1;
-    int width_for_class[32];        // tuned source width per log2(n) class; 0 = untuned
+    // tuned source width per log2(n) class: 8..64 = LDS tiles, 512..2048 =
+    // the persistent cooperative kernel (hln_closeness_layer); 0 = untuned
+    int width_for_class[32];
     void* pinned = nullptr;         // staging for per-call descriptors
     size_t pinned_bytes = 0;
     hipEvent_t staged = nullptr;    // completion of the last staging copy
@@ -187,6 +189,7 @@ __global__ void k_batch_prep(const TileGraph* graphs, int n_graphs, int* counter
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_counters; i += gridDim.x * blockDim.x) counters[i] = 0;
     for (int g = blockIdx.y; g < n_graphs; g += gridDim.y) {
         const TileGraph G = graphs[g];
+        if (G.width >= 512) continue;                 // on the cooperative kernel
         for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < G.n; v += gridDim.x * blockDim.x) {
             G.S[v] = 0;
             G.R[v] = 0;
@@ -201,6 +204,7 @@ __global__ void k_batch_prep(const TileGraph* graphs, int n_graphs, int* counter
 __global__ void k_batch_pack(const TileGraph* graphs, int n_graphs, int* fault) {
     for (int g = blockIdx.y; g < n_graphs; g += gridDim.y) {
         const TileGraph G = graphs[g];
+        if (G.width >= 512) continue;
         for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < G.n; v += gridDim.x * blockDim.x) {
             const int e0 = G.row_ptr[v], e1 = G.row_ptr[v + 1];
             if (e0 < 0 || e1 < e0 || e1 > G.nnz) {
@@ -223,7 +227,7 @@ __global__ void k_batch_pack(const TileGraph* graphs, int n_graphs, int* fault) 
 __global__ void k_batch_cc(const TileGraph* graphs, int n_graphs) {
     for (int g = blockIdx.y; g < n_graphs; g += gridDim.y) {
         const TileGraph G = graphs[g];
-        if (!G.cc) continue;
+        if (!G.cc || G.width >= 512) continue;
         const int n = G.n;
         for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
             const int64_t s = G.S[v];
@@ -269,20 +273,29 @@ struct Layout {
     int n_tiles[4] = {0, 0, 0, 0};   // per width class: 64, 32, 16, 8
     int max_n_class[4] = {0, 0, 0, 0};
     int grid = 0;
+    size_t coop_bytes = 0;             // workspace of the largest graph on the cooperative kernel
     size_t desc_bytes = 0, tiles_bytes = 0, counters_bytes = 0, heavy_bytes = 0;
     size_t vis_bytes = 0, part_bytes = 0, total = 0;
 };
 
 int cls_of(int w) { return w == 64 ? 0 : w == 32 ? 1 : w == 16 ? 2 : 3; }
 
+// Source width of a graph of n vertices: the tuned choice of its size class,
+// else the widest LDS tile that fits, else the cooperative kernel at 2048.
 int chosen_width(const hln_plan* plan, int n, size_t budget) {
     const int fit = widest_fit(n, budget);
-    if (!fit) return 0;
     int w = plan ? plan->width_for_class[log2_class(n)] : 0;
+    if (w >= 512) return w;
+    if (!fit) return 2048;
     if (w <= 0 || w > fit) w = fit;
     return w;
 }
 
+bool is_coop(int w) { return w >= 512; }
+
+// Workspace layout.  Sizes are worst cases over every width a graph could be
+// tuned to (tiles of 8 sources, the cooperative kernel at 2048), so the
+// workspace size does not change when the plan is tuned.
 hln_status plan_layout(const hln_plan* plan, const hln_csr* graphs, int32_t n_graphs, Layout& L) {
     using hln::fail;
     if (!graphs || n_graphs < 1) return fail(HLN_EINVAL, "need at least one graph");
@@ -290,30 +303,36 @@ hln_status plan_layout(const hln_plan* plan, const hln_csr* graphs, int32_t n_gr
     if (!di) return HLN_EDEVICE;
     const size_t budget = lds_budget();
     L.n_graphs = n_graphs;
+    long long max_tiles = 0;
     for (int g = 0; g < n_graphs; ++g) {
         const hln_csr& c = graphs[g];
         if (c.n < 1 || c.nnz < 0 || !c.row_ptr || (c.nnz > 0 && !c.col_idx))
             return fail(HLN_EINVAL, "graph %d: bad descriptor", g);
+        hln_opts o{2048, 0, 0, nullptr, nullptr, 0};
+        L.coop_bytes = std::max(L.coop_bytes, hln_closeness_workspace_size(c.n, c.nnz, c.n, &o));
+        if (widest_fit(c.n, budget)) {
+            max_tiles += (c.n + 7) / 8;
+            L.max_n = std::max(L.max_n, c.n);
+            L.total_n += c.n;
+            L.total_nnz += c.nnz;
+        }
         const int w = chosen_width(plan, c.n, budget);
-        if (!w) return fail(HLN_EUNSUPPORTED, "graph %d: n=%d does not fit the LDS tiles (use hln_closeness_layer)", g, c.n);
+        if (is_coop(w)) continue;
         const int k = cls_of(w);
         L.n_tiles[k] += (c.n + w - 1) / w;
         L.max_n_class[k] = std::max(L.max_n_class[k], c.n);
-        L.max_n = std::max(L.max_n, c.n);
-        L.total_n += c.n;
-        L.total_nnz += c.nnz;
     }
     using hln::Arena;
     L.grid = di->cus;
-    int tiles = 0;
-    for (int k = 0; k < 4; ++k) tiles += L.n_tiles[k];
     L.desc_bytes = Arena::round(sizeof(TileGraph) * n_graphs);
-    L.tiles_bytes = Arena::round(sizeof(int2) * std::max(tiles, 1));
+    L.tiles_bytes = Arena::round(sizeof(int2) * static_cast<size_t>(std::max<long long>(max_tiles, 1)));
     L.counters_bytes = Arena::round(sizeof(int) * 4);
     L.heavy_bytes = Arena::round(sizeof(uint32_t) * static_cast<size_t>(L.total_nnz + 1));
-    L.vis_bytes = Arena::round(static_cast<size_t>(L.grid) * L.max_n * 8);
-    L.part_bytes = Arena::round(static_cast<size_t>(L.grid) * L.max_n * 4);
-    L.total = L.desc_bytes + L.tiles_bytes + L.counters_bytes + L.heavy_bytes + L.vis_bytes + 2 * L.part_bytes;
+    L.vis_bytes = Arena::round(static_cast<size_t>(L.grid) * std::max(L.max_n, 1) * 8);
+    L.part_bytes = Arena::round(static_cast<size_t>(L.grid) * std::max(L.max_n, 1) * 4);
+    L.coop_bytes = Arena::round(L.coop_bytes);
+    L.total = L.desc_bytes + L.tiles_bytes + L.counters_bytes + L.heavy_bytes + L.vis_bytes + 2 * L.part_bytes +
+              L.coop_bytes;
     return HLN_OK;
 }
 
@@ -334,11 +353,11 @@ void build_tables(const hln_plan* plan, const hln_csr* graphs, int32_t n_graphs,
         desc[g].R = R[g];
         desc[g].H2 = h2 ? h2[g] : nullptr;
         desc[g].cc = cc ? cc[g] : nullptr;
-        desc[g].arcs = arcs + off;
         desc[g].nnz = c.nnz;
         desc[g].n = c.n;
         desc[g].width = chosen_width(plan, c.n, budget);
-        off += c.nnz;
+        desc[g].arcs = arcs + off;
+        if (!is_coop(desc[g].width)) off += c.nnz;
         order[g] = g;
     }
     std::sort(order.begin(), order.end(), [&](int x, int y) {
@@ -382,17 +401,27 @@ hln_status enqueue_batch(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs
         return fail(HLN_EINVAL, "workspace NULL or not 256-byte aligned");
     if (workspace_bytes < L.total) return fail(HLN_ENOMEM, "workspace too small: %zu < %zu", workspace_bytes, L.total);
     const size_t stage = L.desc_bytes + L.tiles_bytes;
+    // inside a stream capture (ours or the caller's) the staging is the
+    // frozen buffer reserved beforehand: no allocation, no host wait
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HLN_TRY_HIP(hipStreamIsCapturing(st, &cap));
+    if (cap == hipStreamCaptureStatusActive) capture_staging = true;
     void** pin = capture_staging ? &plan->cap_pinned : &plan->pinned;
     size_t* pin_bytes = capture_staging ? &plan->cap_pinned_bytes : &plan->pinned_bytes;
-    if (!capture_staging && plan->staged_pending) {
-        HLN_TRY_HIP(hipEventSynchronize(plan->staged));   // the previous copy has read the staging
-        plan->staged_pending = false;
-    }
-    if (*pin_bytes < stage) {
-        if (*pin) HLN_TRY_HIP(hipHostFree(*pin));
-        *pin = nullptr;
-        HLN_TRY_HIP(hipHostMalloc(pin, stage, hipHostMallocDefault));
-        *pin_bytes = stage;
+    if (capture_staging) {
+        if (*pin_bytes < stage)
+            return fail(HLN_EINVAL, "capturing: reserve the plan's staging first (hln_plan_reserve)");
+    } else {
+        if (plan->staged_pending) {
+            HLN_TRY_HIP(hipEventSynchronize(plan->staged));   // the previous copy has read the staging
+            plan->staged_pending = false;
+        }
+        if (*pin_bytes < stage) {
+            if (*pin) HLN_TRY_HIP(hipHostFree(*pin));
+            *pin = nullptr;
+            HLN_TRY_HIP(hipHostMalloc(pin, stage, hipHostMallocDefault));
+            *pin_bytes = stage;
+        }
     }
     char* dev = static_cast<char*>(workspace);
     TileGraph* desc_h = static_cast<TileGraph*>(*pin);
@@ -447,6 +476,16 @@ hln_status enqueue_batch(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs
     }
     hipLaunchKernelGGL(k_batch_cc, dim3(gx, gy), dim3(256), 0, st, desc_d, n_graphs);
     HLN_TRY_HIP(hipGetLastError());
+    // graphs tuned (or too large) for the persistent cooperative kernel,
+    // one launch each, sharing one workspace region in stream order
+    void* coop_ws = p + L.vis_bytes + 2 * L.part_bytes;
+    for (int g = 0; g < n_graphs; ++g) {
+        if (!is_coop(desc_h[g].width)) continue;
+        hln_opts o{desc_h[g].width, 0, 0, nullptr, nullptr, 0};
+        hln_status r = hln_closeness_layer(&graphs[g], nullptr, graphs[g].n, &o, S[g], R[g], cc ? cc[g] : nullptr,
+                                           h2 ? h2[g] : nullptr, coop_ws, L.coop_bytes, st);
+        if (r != HLN_OK) return r;
+    }
     return HLN_OK;
 }
 
@@ -542,6 +581,22 @@ hln_status hln_plan_capture(hln_plan* plan, const hln_csr* graphs, int32_t n_gra
     return HLN_OK;
 }
 
+hln_status hln_plan_reserve(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs) {
+    hln::clear_error();
+    if (!plan) return hln::fail(HLN_EINVAL, "plan is NULL");
+    Layout L;
+    hln_status s = plan_layout(plan, graphs, n_graphs, L);
+    if (s != HLN_OK) return s;
+    const size_t stage = L.desc_bytes + L.tiles_bytes;
+    if (plan->cap_pinned_bytes >= stage) return HLN_OK;
+    if (plan->cap_pinned) HLN_TRY_HIP(hipHostFree(plan->cap_pinned));
+    plan->cap_pinned = nullptr;
+    plan->cap_pinned_bytes = 0;
+    HLN_TRY_HIP(hipHostMalloc(&plan->cap_pinned, stage, hipHostMallocDefault));
+    plan->cap_pinned_bytes = stage;
+    return HLN_OK;
+}
+
 hln_status hln_plan_replay(hln_plan* plan, void* stream) {
     hln::clear_error();
     if (!plan || !plan->exec) return hln::fail(HLN_EINVAL, "no captured graph in this plan");
@@ -575,8 +630,14 @@ hln_status hln_plan_tune(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs
         const int g = rep[c];
         const int fit = widest_fit(graphs[g].n, budget);
         float best = 1e30f;
-        int best_w = fit;
-        for (int w = fit; w >= 8 && result == HLN_OK; w >>= 1) {
+        int best_w = fit ? fit : 2048;
+        int cands[8];
+        int nc = 0;
+        for (int w = fit; w >= 8 && fit; w >>= 1) cands[nc++] = w;
+        cands[nc++] = 1024;
+        cands[nc++] = 2048;
+        for (int ci = 0; ci < nc && result == HLN_OK; ++ci) {
+            const int w = cands[ci];
             plan->width_for_class[c] = w;
             float ms = 0.f;
             for (int rep_i = 0; rep_i < 2 && result == HLN_OK; ++rep_i) {   // first run warms up

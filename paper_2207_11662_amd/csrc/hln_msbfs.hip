@@ -578,8 +578,22 @@ hln_status launch(const BfsArgs& args, int grid, hipStream_t stream) {
         fprintf(stderr, "[hln] closeness NW=%d block=%d per_source=%d n=%d n_src=%d grid=%d\n", NW, BLOCK,
                 PS ? 1 : 0, args.n, args.n_src, grid);
     void* kargs[] = {const_cast<BfsArgs*>(&args)};
-    HLN_TRY_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_closeness<NW, BLOCK, PS>), dim3(grid),
-                                           dim3(BLOCK), kargs, 0, stream));
+    hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_closeness<NW, BLOCK, PS>), dim3(grid),
+                                              dim3(BLOCK), kargs, 0, stream);
+    if (e != hipSuccess) {
+        // Inside a stream capture a cooperative launch may be refused; the
+        // same grid (one block per compute unit at most, well under what fits
+        // at once) is then launched as an ordinary kernel node.  Every wait in
+        // the kernel is bounded, so a grid that did not all start would end
+        // with fault code 1 rather than hang.
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(stream, &cap) == hipSuccess && cap == hipStreamCaptureStatusActive) {
+            (void)hipGetLastError();
+            hipLaunchKernelGGL((k_closeness<NW, BLOCK, PS>), dim3(grid), dim3(BLOCK), 0, stream, args);
+            e = hipGetLastError();
+        }
+    }
+    if (e != hipSuccess) return hln::fail(HLN_EDEVICE, "closeness launch failed: %s", hipGetErrorString(e));
     return HLN_OK;
 }
 

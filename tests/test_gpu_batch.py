@@ -89,6 +89,7 @@ def test_batch_capture_replay_and_tune():
     outs = P.Plan.outputs(graphs)
     plan.tune(graphs, outs)
     say("tuned widths", [plan.width(g.n) for g in graphs])
+    assert all(plan.width(g.n) in (8, 16, 32, 64, 1024, 2048) for g in graphs)
     ws = P.workspace(plan.workspace_size(graphs))
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -105,11 +106,15 @@ def test_batch_capture_replay_and_tune():
         check(gnp, outs, "replay%d" % rep)
 
 
-def test_batch_rejects_large_graph():
+def test_batch_large_graphs_use_the_persistent_kernel():
+    """Graphs too large for LDS tiles (n > 65,535) go through the persistent
+    cooperative kernel inside the same batch call."""
+    gnp = mixed_graphs(3, [70000, 1200])
     plan = P.Plan()
-    n = 70000
-    rp = np.zeros(n + 1, np.int32)
-    g = graph_dev(P, rp, np.zeros(0, np.int32))
-    outs = P.Plan.outputs([g])
-    with pytest.raises(P.HlnError):
-        plan.run([g], outs)
+    assert plan.width(70000) >= 512 and plan.width(1200) <= 64
+    graphs = [graph_dev(P, rp, ci) for rp, ci in gnp]
+    outs = P.Plan.outputs(graphs, want_h2=True)
+    plan.run(graphs, outs)
+    torch.cuda.synchronize()
+    P.device_status()
+    check(gnp, outs, "large")
