@@ -113,8 +113,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
-    ap.add_argument("--workload", choices=["cfg2", "cfg3"], default="cfg2",
-                    help="cfg2 (default): the benchmark line; cfg3: the batched path on 64 HoMLNs")
+    ap.add_argument("--workload", choices=["cfg2", "cfg3", "cfg5"], default="cfg2",
+                    help="cfg2 (default): the benchmark line; cfg3: the batched path on 64 HoMLNs; "
+                         "cfg5: the learned candidate proposer against exhaustive AND closeness")
+    ap.add_argument("--train-steps", type=int, default=3000, help="cfg5: proposer training steps")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -131,6 +133,9 @@ def main():
         return
     if args.workload == "cfg3":
         run_cfg3(args)
+        return
+    if args.workload == "cfg5":
+        run_cfg5(args)
         return
 
     dev = torch.device("cuda", 0)
@@ -343,6 +348,118 @@ def run_cfg3(args):
                                   "batched all-source closeness (persistent LDS tiles), CC2 top-10%; one hipGraph replay per step",
                       "graphs": len(all_graphs), "teps_edges_per_step": int(teps), "tile_widths": widths,
                       "tune_seconds": round(tune_s, 3)}}
+    print(json.dumps(rec), flush=True)
+
+
+def run_cfg5(args):
+    """Learned candidate proposer on 5 Chung-Lu layers x 200,000 vertices.
+    Trained on configs 1-3 (labels: percentile rank of exact AND-graph
+    closeness).  Query arm: features -> MLP -> top 5% candidates -> exact
+    per-source BFS on the AND graph -> top 1%.  Exhaustive arm: all-source
+    BFS on the AND graph -> top 1%.  Both arms start from the shared Psi
+    outputs and the composed AND graph; CC2 (Sec. 5.2) at the same
+    candidate budget is the non-learned baseline."""
+    import torch
+    import paper_2207_11662_amd as P
+    from paper_2207_11662_amd import proposer as PR
+    from homln_inputs import configs as C
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    plan = P.Plan()
+    t0 = time.perf_counter()
+    train = [C.config1(), C.config2()] + C.config3()
+    log("generated %d training HoMLNs in %.1fs" % (len(train), time.perf_counter() - t0))
+    t0 = time.perf_counter()
+    Xs, ys = [], []
+    for h in train:
+        X, lab = PR.training_example(plan, h)
+        Xs.append(X)
+        ys.append(lab)
+    X = torch.cat(Xs)
+    y = torch.cat(ys)
+    del Xs, ys
+    torch.cuda.synchronize()
+    P.device_status()
+    t_data = time.perf_counter() - t0
+    log("training set: %d vertices in %.1fs" % (X.shape[0], t_data))
+    t0 = time.perf_counter()
+    model = PR.Proposer(seed=0).fit(X, y, steps=args.train_steps, lr=2e-3, batch=65536,
+                                    log_every=max(1, args.train_steps // 10))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log("trained %d steps in %.1fs; loss %s" % (args.train_steps, t_train, model.history))
+    del X, y
+
+    h = C.config5()
+    n = h.n
+    layers = PR.upload_homln(h)
+    t0 = time.perf_counter()
+    psi_outs = PR.psi(plan, layers)
+    g_and = P.hln_compose_and(layers).trimmed()
+    torch.cuda.synchronize()
+    t_psi = time.perf_counter() - t0
+    n_cand, k = n // 20, n // 100
+    ex = {"S": torch.empty(n, dtype=torch.int64, device=dev), "R": torch.empty(n, dtype=torch.int32, device=dev),
+          "cc": torch.empty(n, dtype=torch.float64, device=dev), "h2": None}
+    ex_ws = P.workspace(P.closeness_workspace_size(n, g_and.nnz, n, args.width), dev)
+    ex_ids = torch.empty(k, dtype=torch.int32, device=dev)
+    q = PR.Query(g_and, n_cand, k, width_bits=args.width)
+
+    def exhaustive():
+        P.hln_closeness_layer(g_and, None, width_bits=args.width, out=ex, ws=ex_ws)
+        P.hln_topk(ex["cc"], k, ids=ex_ids, ws=q.ws_topk)
+
+    def timed(fn, reps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        P.device_status()
+        return a.elapsed_time(b) / reps
+
+    t_ex = timed(exhaustive, args.steps)
+    t_q = timed(lambda: q.run(model, layers, psi_outs), args.steps)
+    truth = ex_ids.cpu().numpy()
+    cc_all = ex["cc"].cpu().numpy()
+    ids, cc_ids = q.result()
+    assert np.array_equal(cc_ids.view(np.int64), cc_all[ids].view(np.int64)), "candidate closeness differs"
+    thr = cc_all[truth[-1]]
+
+    def precision(sel):
+        return len(set(sel.tolist()) & set(truth.tolist())) / k, float(np.mean(cc_all[sel] >= thr))
+
+    p_learned = precision(ids)
+    # CC2 at the same candidate budget, refined by the same exact BFS
+    nl = len(layers)
+    cc2_ids, _, _ = P.hln_compose_cc_topk(P.HLN_RANK_CC2, n, [o["S"] for o in psi_outs], [o["R"] for o in psi_outs],
+                                          n_cand)
+    q.cand[:n_cand].copy_(cc2_ids[:n_cand])
+    q.refine()
+    ids_cc2, _ = q.result()
+    p_cc2 = precision(ids_cc2)
+    cc2_k, _, _ = P.hln_compose_cc_topk(P.HLN_RANK_CC2, n, [o["S"] for o in psi_outs], [o["R"] for o in psi_outs], k)
+    p_cc2_direct = precision(cc2_k[:k].cpu().numpy())
+    speed = t_ex / t_q
+    amort = (t_psi * 1000 / 26 + t_ex) / (t_psi * 1000 / 26 + t_q)
+    rec = {"metric": "learned proposer: query speedup over exhaustive AND closeness at precision@1%",
+           "value": round(speed, 3), "unit": "x", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(t_q, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 (MLP), i64/f64 (BFS, closeness)", "data": "synthetic",
+           "config": {"workload": "5 Chung-Lu layers x 200,000 vertices (config 5); AND graph; candidates 5%, answer 1%",
+                      "n": n, "and_arcs": int(g_and.nnz), "candidates": n_cand, "k": k,
+                      "train_vertices": int(sum(t.n for t in train)), "train_steps": args.train_steps},
+           "exhaustive_ms": round(t_ex, 3), "proposer_ms": round(t_q, 3),
+           "precision_at_k": p_learned[0], "precision_at_k_ties": p_learned[1],
+           "cc2_same_budget_precision": p_cc2[0], "cc2_same_budget_precision_ties": p_cc2[1],
+           "cc2_direct_precision": p_cc2_direct[0], "cc2_direct_precision_ties": p_cc2_direct[1],
+           "psi_plus_compose_ms": round(t_psi * 1000, 3), "speedup_e2e_psi_amortised_26": round(amort, 3),
+           "train_seconds": round(t_train, 2), "train_data_seconds": round(t_data, 2),
+           "train_loss": model.history[-1][1] if model.history else None}
     print(json.dumps(rec), flush=True)
 
 

@@ -206,6 +206,54 @@ hln_status hln_plan_capture(hln_plan* plan, const hln_csr* graphs, int32_t n_gra
 hln_status hln_plan_reserve(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs);
 hln_status hln_plan_replay(hln_plan* plan, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Learned candidate proposer (not in the paper; its inputs are the Psi
+ * step's per-layer outputs: degree, closeness and 2-hop count, echoing
+ * CC1's degree bound, Sec. 5.1, and CC2's per-layer sums, Sec. 5.2).
+ * ------------------------------------------------------------------------
+ * hln_proposer_features: X [dev] float[n][16]; for each of four per-layer
+ *   quantities -- log1p(deg / mean degree of the layer), the closeness
+ *   ((R-1)/S)((R-1)/(n-1)), log1p(h2 / mean degree^2) and the penalised
+ *   closeness (n-1)/(S + n(n-R)) (its minimum over the layers is CC2's
+ *   score) -- the min, max, mean and standard deviation over the r layers.
+ *   row_ptr, S, R, h2: [host] arrays of r device pointers (n+1, n, n, n
+ *   entries; S, R, h2 as hln_closeness_layer's all-source outputs); nnz
+ *   [host] r exact arc counts.  1 <= r <= 64.
+ * The MLP is 16 -> 64 (ReLU) -> 64 (ReLU) -> 1 in FP32 with
+ *   hln_mlp_param_count() parameters in the order W1[16][64], b1[64],
+ *   W2[64][64], b2[64], w3[64], b3 (params [dev] float).
+ * hln_mlp_init: Glorot-uniform weights from a counter-based generator
+ *   (splitmix64 of seed and index), zero biases; zeroes adam_m / adam_v
+ *   (nullable).
+ * hln_mlp_forward: y [dev] float[n] scores for X.
+ * hln_mlp_train_step: one Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8,
+ *   bias-corrected with `step` >= 1) on the mean squared error of the n
+ *   rows of X against target [dev] float[n]; *loss [dev, nullable] the loss
+ *   before the step.  Deterministic (block partials summed in order).
+ * hln_topk: ids [dev] of the k largest scores (float64 dtype 0, float32
+ *   dtype 1), descending, ties by ascending index; -0.0 ties with +0.0;
+ *   scores must not be NaN.  0 <= k <= n.
+ * hln_rank_labels: label [dev] float[n] = log((n+1)/(g+1)) / log(n+1)
+ *   with g the number of vertices with a strictly larger score (computed in
+ *   double, rounded to float): the log-rank the proposer is trained to
+ *   predict, 1 for the best vertex.  Both take hln_topk_workspace_size(n)
+ *   bytes of workspace. */
+int32_t hln_mlp_param_count(void);
+hln_status hln_proposer_features(int32_t n, int32_t r, const int32_t* const* row_ptr, const int64_t* const* S,
+                                 const int32_t* const* R, const int32_t* const* h2, const int64_t* nnz, float* X,
+                                 void* stream);
+hln_status hln_mlp_init(float* params, float* adam_m, float* adam_v, uint64_t seed, void* stream);
+hln_status hln_mlp_forward(const float* params, const float* X, int32_t n, float* y, void* stream);
+size_t hln_mlp_train_workspace_size(int32_t n);
+hln_status hln_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t step, float lr, const float* X,
+                              const float* target, int32_t n, float* loss, void* workspace, size_t workspace_bytes,
+                              void* stream);
+size_t hln_topk_workspace_size(int32_t n);
+hln_status hln_topk(int32_t n, const void* score, int32_t dtype, int32_t k, int32_t* ids,
+                    void* workspace, size_t workspace_bytes, void* stream);
+hln_status hln_rank_labels(int32_t n, const void* score, int32_t dtype, float* label,
+                           void* workspace, size_t workspace_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,4 +7,6 @@ from ._lib import (  # noqa: F401
     closeness_workspace_size, compose_workspace_size,
     hln_closeness_layer, hln_csr_from_edges, hln_csr_validate, hln_compose_and, hln_compose_or,
     hln_compose_cc_topk, Plan,
+    mlp_param_count, hln_proposer_features, hln_mlp_init, hln_mlp_forward, hln_mlp_train_step, hln_topk,
+    hln_rank_labels,
 )

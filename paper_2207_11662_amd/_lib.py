@@ -27,6 +27,8 @@ EXPORTS = [
     "hln_compose_cc_topk_workspace_size", "hln_compose_cc_topk",
     "hln_plan_create", "hln_plan_destroy", "hln_plan_width", "hln_closeness_batch_workspace_size",
     "hln_closeness_batch", "hln_plan_tune", "hln_plan_capture", "hln_plan_replay", "hln_plan_reserve",
+    "hln_mlp_param_count", "hln_proposer_features", "hln_mlp_init", "hln_mlp_forward",
+    "hln_mlp_train_workspace_size", "hln_mlp_train_step", "hln_topk_workspace_size", "hln_topk", "hln_rank_labels",
 ]
 
 HLN_RANK_WF, HLN_RANK_CC2, HLN_RANK_NAIVE = 0, 1, 2
@@ -87,6 +89,15 @@ def lib():
         "hln_plan_capture": ([P, csr_p, i32, P, P, P, P, P, sz, P], st),
         "hln_plan_replay": ([P, P], st),
         "hln_plan_reserve": ([P, csr_p, i32], st),
+        "hln_mlp_param_count": ([], i32),
+        "hln_proposer_features": ([i32, i32, P, P, P, P, P, P, P], st),
+        "hln_mlp_init": ([P, P, P, ctypes.c_uint64, P], st),
+        "hln_mlp_forward": ([P, P, i32, P, P], st),
+        "hln_mlp_train_workspace_size": ([i32], sz),
+        "hln_mlp_train_step": ([P, P, P, i32, ctypes.c_float, P, P, i32, P, P, sz, P], st),
+        "hln_topk_workspace_size": ([i32], sz),
+        "hln_topk": ([i32, P, i32, i32, P, P, sz, P], st),
+        "hln_rank_labels": ([i32, P, i32, P, P, sz, P], st),
     }
     for name, (args, res) in sig.items():
         if hasattr(L, name):
@@ -367,3 +378,75 @@ class Plan:
 
     def replay(self, stream=None):
         check(lib().hln_plan_replay(self.h, _stream(stream)))
+
+
+# ---------------------------------------------------------------------------
+# a9: learned candidate proposer (features, FP32 MLP, generic top-k)
+# ---------------------------------------------------------------------------
+
+def mlp_param_count() -> int:
+    return int(lib().hln_mlp_param_count())
+
+
+def hln_proposer_features(graphs, S_list, R_list, h2s, X=None, stream=None) -> torch.Tensor:
+    """16 features per vertex from r layers' CSR and all-source S, R, h2.
+    Each Graph's nnz must be its exact arc count (it sets the mean degree)."""
+    n = graphs[0].n
+    r = len(graphs)
+    if X is None:
+        X = torch.empty((n, 16), dtype=torch.float32, device=graphs[0].row_ptr.device)
+    nnz = (ctypes.c_int64 * r)(*[g.nnz for g in graphs])
+    check(lib().hln_proposer_features(n, r, _ptr_array([g.row_ptr for g in graphs]), _ptr_array(S_list),
+                                      _ptr_array(R_list), _ptr_array(h2s), ctypes.cast(nnz, ctypes.c_void_p),
+                                      _ptr(X), _stream(stream)))
+    return X
+
+
+def hln_mlp_init(params, m=None, v=None, seed: int = 0, stream=None):
+    check(lib().hln_mlp_init(_ptr(params), _ptr(m), _ptr(v), seed, _stream(stream)))
+
+
+def hln_mlp_forward(params, X, y=None, stream=None):
+    if y is None:
+        y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    check(lib().hln_mlp_forward(_ptr(params), _ptr(X), X.shape[0], _ptr(y), _stream(stream)))
+    return y
+
+
+def hln_mlp_train_step(params, m, v, step: int, lr: float, X, target, loss=None, ws=None, stream=None):
+    n = X.shape[0]
+    need = int(lib().hln_mlp_train_workspace_size(n))
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, X.device)
+    check(lib().hln_mlp_train_step(_ptr(params), _ptr(m), _ptr(v), step, lr, _ptr(X), _ptr(target), n, _ptr(loss),
+                                   _ptr(ws), ws.numel(), _stream(stream)))
+    return ws
+
+
+def hln_topk(score: torch.Tensor, k: int, ids=None, ws=None, stream=None) -> torch.Tensor:
+    """Indices of the k largest scores (float64 or float32), descending,
+    ties by ascending index."""
+    n = score.numel()
+    dtype = 0 if score.dtype == torch.float64 else 1
+    assert score.dtype in (torch.float64, torch.float32)
+    need = int(lib().hln_topk_workspace_size(n))
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, score.device)
+    if ids is None:
+        ids = torch.empty(max(k, 1), dtype=torch.int32, device=score.device)
+    check(lib().hln_topk(n, _ptr(score), dtype, k, _ptr(ids), _ptr(ws), ws.numel(), _stream(stream)))
+    return ids[:k]
+
+
+def hln_rank_labels(score: torch.Tensor, label=None, ws=None, stream=None) -> torch.Tensor:
+    """Log-rank labels: log((n+1)/(g+1)) / log(n+1), g = count of strictly
+    larger scores."""
+    n = score.numel()
+    dtype = 0 if score.dtype == torch.float64 else 1
+    need = int(lib().hln_topk_workspace_size(n))
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, score.device)
+    if label is None:
+        label = torch.empty(n, dtype=torch.float32, device=score.device)
+    check(lib().hln_rank_labels(n, _ptr(score), dtype, _ptr(label), _ptr(ws), ws.numel(), _stream(stream)))
+    return label
