@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--width", type=int, default=2048, help="sources per BFS batch")
+    ap.add_argument("--direction", type=int, default=0, choices=[0, 1, 2],
+                    help="BFS level direction: 0 automatic, 1 top-down only, 2 bottom-up only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
@@ -181,7 +183,8 @@ def main():
         for gi, g in enumerate(graphs):
             if events is not None:
                 events[gi][0].record(stream)
-            P.hln_closeness_layer(g, width_bits=W, want_h2=True, out=outs[gi], ws=ws, levels=levels[gi])
+            P.hln_closeness_layer(g, width_bits=W, want_h2=True, out=outs[gi], ws=ws, levels=levels[gi],
+                                  direction=args.direction)
             if events is not None:
                 events[gi][1].record(stream)
         for gi in range(G):

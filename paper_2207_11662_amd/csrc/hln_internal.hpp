@@ -84,93 +84,118 @@ __device__ __forceinline__ void store_agent_i32(int* p, int v) {
 }
 
 // Grid-wide barrier for a cooperative launch that also ORs a per-block flag
-// over the grid.  Two levels, so that no counter takes more than
-// ~grid/kSubs arrivals:
-//   bar[kSub*i]          sub-group i (blocks with blockIdx % kSubs == i):
-//                        low 32 bits arrivals, high 32 bits flagged arrivals,
-//   bar[kSub*kSubs]      the same for the last arrival of each sub-group,
-//   bar[kSub*(kSubs+1)]  release word: 2*(barriers completed) + OR of flags,
-//   bar[kSub*(kSubs+2)+i] flagged totals seen at the previous barrier.
-// Counters grow monotonically during a launch (never reset) and sit 4 KB
-// apart.  The wait is bounded in wall-clock time (s_memrealtime, 100 MHz):
-// after `limit_ticks` the block records fault code 1; when another block has
-// already recorded a fault it stops waiting.  Either way ok = false and the
-// caller leaves the kernel, so every block exits.
+// over the grid and hands every block one bit decided by the last arrival.
+// Two levels, so that no counter takes more than ~grid/kSubs arrivals, and
+// two counter sets used by alternate barriers (every block counts the
+// barriers it has passed, so all agree on the parity):
+//   bar[kSub*(i + kSubs*p)]      sub-group i (blocks with blockIdx % kSubs
+//                                == i), parity p: low 32 bits arrivals,
+//                                high 32 bits flagged arrivals;
+//   bar[kSub*(2*kSubs + p)]      the same for the sub-groups' last arrivals;
+//   bar[kSub*(2*kSubs + 2)]      release word: 4*(barriers completed) +
+//                                2*decision + OR of the flags.
+// The last arrival at a counter resets it to zero for the barrier after
+// next (every block passes the next barrier first, so the reset is done
+// before the counter's next use).  Words sit 4 KB apart.  `pre()` runs on
+// each block's thread 0 after the block has synchronised and before it
+// arrives (its memory operations complete before the arrival counts);
+// `decide()` runs on the releasing thread after every block has arrived,
+// and its result is returned to all blocks.  The wait is bounded in
+// wall-clock time (s_memrealtime, 100 MHz): after `limit` ticks the block
+// records fault code 1; when another block has already recorded a fault it
+// stops waiting.  Either way ok = false and the caller leaves the kernel,
+// so every block exits.
 constexpr int kSubs = 16;
 constexpr int kSub = 512;                       // 4 KB of unsigned long long
-constexpr int kBarrierWords = kSub * (kSubs + 3);
+constexpr int kBarrierWords = kSub * (2 * kSubs + 3);
 
 struct BarrierResult {
     bool ok;
     bool any;
+    bool decision;
 };
 
-__device__ __forceinline__ unsigned long long flagged_delta(unsigned long long* prev, unsigned long long total) {
-    const unsigned long long before = load_agent(prev);
-    __hip_atomic_store(prev, total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_s_waitcnt(0);
-    return total - before;
-}
+struct NoHook {
+    __device__ void operator()() const {}
+};
+struct NoDecision {
+    __device__ bool operator()() const { return false; }
+};
 
-__device__ __forceinline__ BarrierResult grid_barrier_or(unsigned long long* bar, int flag, int* fault,
-                                                         uint64_t limit_ticks) {
-    __shared__ int s_ok;
-    __shared__ int s_any;
-    const int blk_flag = __syncthreads_or(flag);
-    if (threadIdx.x == 0) {
-        __threadfence();  // publish this block's writes device-wide
-        const unsigned nb = gridDim.x;
-        const unsigned groups = nb < kSubs ? nb : kSubs;
-        const unsigned g = blockIdx.x % groups;
-        const unsigned members = nb / groups + (g < nb % groups ? 1u : 0u);
-        const unsigned long long add = 1ull + (blk_flag ? (1ull << 32) : 0ull);
-        const unsigned long long old = atomic_add_agent(bar + kSub * g, add);
-        const unsigned cnt = static_cast<unsigned>(old);
-        const unsigned long long epoch = cnt / members + 1ull;   // barriers completed once this one is
-        unsigned long long* release = bar + kSub * (kSubs + 1);
-        int ok = 1;
-        int any = 0;
-        bool released = false;
-        if (cnt % members == members - 1) {
-            const unsigned long long d = flagged_delta(bar + kSub * (kSubs + 2) + g, (old + add) >> 32);
-            const unsigned long long radd = 1ull + (d ? (1ull << 32) : 0ull);
-            const unsigned long long r = atomic_add_agent(bar + kSub * kSubs, radd);
-            if (static_cast<unsigned>(r) % groups == groups - 1) {
-                const unsigned long long dr = flagged_delta(bar + kSub * (kSubs + 2) + kSubs, (r + radd) >> 32);
-                any = dr != 0;
-                __hip_atomic_store(release, 2ull * epoch + (any ? 1ull : 0ull), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                released = true;
-            }
-        }
-        if (!released) {
-            const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-            unsigned long long rel;
-            while (((rel = load_agent(release)) >> 1) < epoch) {
-                __builtin_amdgcn_s_sleep(8);
-                if (load_agent_i32(fault) != 0) {  // another block failed: keep its code
-                    ok = 0;
-                    break;
+struct GridBarrier {
+    unsigned long long* bar;
+    int* fault;
+    uint64_t limit;
+    unsigned passed;                            // barriers this block has passed (thread 0's copy is used)
+
+    template <class Pre = NoHook, class Decide = NoDecision>
+    __device__ __forceinline__ BarrierResult sync(int flag, Pre pre = Pre(), Decide decide = Decide()) {
+        __shared__ int s_ok;
+        __shared__ int s_any;
+        __shared__ int s_dec;
+        const int blk_flag = __syncthreads_or(flag);
+        if (threadIdx.x == 0) {
+            pre();
+            // release: this block's writes reach the device coherence point
+            // (L2 write-back) before its arrival is counted
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const unsigned e = passed;
+            const unsigned par = e & 1u;
+            const unsigned nb = gridDim.x;
+            const unsigned groups = nb < kSubs ? nb : kSubs;
+            const unsigned g = blockIdx.x % groups;
+            const unsigned members = nb / groups + (g < nb % groups ? 1u : 0u);
+            unsigned long long* sub = bar + kSub * (g + kSubs * par);
+            unsigned long long* root = bar + kSub * (2 * kSubs + par);
+            unsigned long long* release = bar + kSub * (2 * kSubs + 2);
+            const unsigned long long add = 1ull + (blk_flag ? (1ull << 32) : 0ull);
+            const unsigned long long old = atomic_add_agent(sub, add);
+            int ok = 1;
+            unsigned long long rel = 0;
+            bool released = false;
+            if (static_cast<unsigned>(old) == members - 1) {
+                const unsigned long long radd = 1ull + (((old + add) >> 32) ? (1ull << 32) : 0ull);
+                __hip_atomic_store(sub, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned long long r = atomic_add_agent(root, radd);
+                if (static_cast<unsigned>(r) == groups - 1) {
+                    const bool any = ((r + radd) >> 32) != 0;
+                    __hip_atomic_store(root, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    // decide() reads agent-scope atomics only, which every
+                    // block completed before its arrival
+                    rel = 4ull * (e + 1ull) + (decide() ? 2ull : 0ull) + (any ? 1ull : 0ull);
+                    __hip_atomic_store(release, rel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    released = true;
                 }
-                if (__builtin_amdgcn_s_memrealtime() - t0 > limit_ticks) {
-                    store_agent_i32(fault, 1);
-                    ok = 0;
-                    break;
+            }
+            if (!released) {
+                const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+                while (((rel = load_agent(release)) >> 2) < e + 1ull) {
+                    __builtin_amdgcn_s_sleep(4);
+                    if (load_agent_i32(fault) != 0) {  // another block failed: keep its code
+                        ok = 0;
+                        break;
+                    }
+                    if (__builtin_amdgcn_s_memrealtime() - t0 > limit) {
+                        store_agent_i32(fault, 1);
+                        ok = 0;
+                        break;
+                    }
                 }
             }
-            any = static_cast<int>(rel & 1ull);
+            passed = e + 1;
+            // acquire: drop stale L2 lines so that later loads see every
+            // block's writes
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            s_ok = ok;
+            s_any = static_cast<int>(rel & 1ull);
+            s_dec = static_cast<int>((rel >> 1) & 1ull);
         }
-        __threadfence();  // see every other block's writes
-        s_ok = ok;
-        s_any = any;
+        __syncthreads();
+        return BarrierResult{s_ok != 0, s_any != 0, s_dec != 0};
     }
-    __syncthreads();
-    return BarrierResult{s_ok != 0, s_any != 0};
-}
 
-__device__ __forceinline__ bool grid_barrier(unsigned long long* bar, int* fault, uint64_t limit_ticks) {
-    return grid_barrier_or(bar, 0, fault, limit_ticks).ok;
-}
+    __device__ __forceinline__ bool wait() { return sync(0).ok; }
+};
 
 }  // namespace dev
 }  // namespace hln

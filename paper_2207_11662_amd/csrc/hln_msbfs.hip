@@ -7,10 +7,21 @@
 //   vis  -- sources that have reached the vertex,
 //   fr   -- sources that reached it at the previous level (the frontier),
 //   nx   -- sources reaching it at this level.
-// One level, bottom-up (pull):  nx[v] = (OR_{w in N(v)} fr[w]) & ~vis[v].
-// One level, top-down (push):   for v with fr[v] != 0, OR fr[v] into every
-//   neighbour's word, keeping only bits the neighbour has not seen.
+// One level, bottom-up (pull):  nx[v] = (OR_{w in N(v)} fr[w]) & ~vis[v];
+//   a lane stops gathering a word once vis | OR covers all 64 bits.
+// One level, top-down (push): every segment of a frontier vertex u ORs
+//   fr[u] into its neighbours' accumulators (agent-scope atomics) and marks
+//   them touched; after a grid barrier the touched vertices are finalised
+//   as in the pull case and stale words of the older frontier are cleared.
 // A level's new bits at v are the sources at distance d from v.
+// Direction: every finalised vertex with new bits appends its segments to
+// its block's frontier list in LDS and adds its arc-words (arcs times the
+// frontier words holding new bits, which is what a push ORs) to a per-phase
+// counter; a top-down level's blocks push their own lists.  A level runs
+// top-down when alpha * (frontier arc-words) < arcs of the graph (after
+// Beamer, Asanovic and Patterson, SC'12, with the bit-parallel frontier's
+// word count in the cost) and no block's list overflowed; the barrier's
+// releasing thread decides and every block receives the same bit.
 //
 // Accumulation:
 //   all sources (sources == NULL): the graph is undirected, so d(s,v) =
@@ -39,8 +50,6 @@
 
 namespace {
 
-using hln::dev::grid_barrier;
-using hln::dev::grid_barrier_or;
 using hln::dev::load_agent_i32;
 using hln::dev::shfl_xor_i32;
 using hln::dev::shfl_xor_u64;
@@ -58,7 +67,14 @@ struct Ctrl {
     int bins[kClasses];                    // segments per class
     int cursor[kClasses];                  // fill cursors (segment units)
     int n_seg;
+    int fbad[3];                           // nonzero: a block's frontier list overflowed (slot = phase mod 3)
+    unsigned long long farcs[3];           // frontier arc-words of the same phases
 };
+
+// LDS frontier-list entries per block and phase; a phase that lists more in
+// one block makes the next level bottom-up (such a frontier is far past the
+// top-down threshold anyway).
+constexpr int kFlCap = 4096;
 
 struct BfsArgs {
     int32_t n;
@@ -76,7 +92,7 @@ struct BfsArgs {
     int4* seg;                        // segments: vertex, first arc, end arc, segments of the row
     long long seg_cap;                // capacity of seg
     long long nnz_cap;                // arcs the caller declared (col_idx holds at least row_ptr[n] <= nnz_cap)
-    int32_t* flist[2];                // frontier vertex lists for top-down levels
+    int32_t* seg_first;               // n: index of the vertex's first segment
     int64_t* part;                    // per-source mode: [grid][2][W] block partials
     int64_t* S;
     int32_t* R;
@@ -91,9 +107,65 @@ struct BfsArgs {
     int64_t* trace;                   // nullable: per level {ticks, vertices with new bits, new pairs, direction}
     int32_t trace_cap;
     int32_t seg_len;                  // SEG
-    int32_t alpha;                    // switch to bottom-up when frontier arcs > total arcs / alpha
-    int32_t beta;                     // switch back to top-down when frontier vertices < n / beta
+    int32_t alpha;                    // top-down when alpha * frontier arc-words < arcs of the graph
 };
+
+// A block's frontier lists in LDS, double-buffered by phase parity: the
+// vertices its groups finalised with new bits, as segment indices.
+struct FrontierLds {
+    int32_t fl[2][kFlCap];
+    int cnt[2];
+    unsigned long long arcs[2];
+};
+
+// Record that a vertex got new bits: its segments [first, first + nseg)
+// join the list of parity `par`.  Called by one lane.
+__device__ __forceinline__ void frontier_note(FrontierLds& f, int par, int first, int nseg, int arcs) {
+    atomicAdd(&f.arcs[par], static_cast<unsigned long long>(arcs));
+    const int p = atomicAdd(&f.cnt[par], nseg);
+    if (p + nseg <= kFlCap)
+        for (int j = 0; j < nseg; ++j) f.fl[par][p + j] = first + j;
+}
+
+// Barrier hooks at the end of a phase.  PhaseEnd (each block's thread 0,
+// block synchronised): adds the block's frontier arcs to the phase's
+// counter, flags an overflowed list and clears the other parity's list for
+// the next phase (the previous phase's list was last read before this
+// barrier).  Decide (the releasing thread): the direction of the next level.
+struct PhaseEnd {
+    FrontierLds* f;
+    Ctrl* ctrl;
+    int phase;
+    __device__ void operator()() const {
+        const int par = phase & 1;
+        const int slot = phase % 3;
+        if (f->arcs[par]) hln::dev::atomic_add_agent(&ctrl->farcs[slot], f->arcs[par]);
+        if (f->cnt[par] > kFlCap) store_agent_i32(&ctrl->fbad[slot], 1);
+        f->cnt[par ^ 1] = 0;
+        f->arcs[par ^ 1] = 0;
+    }
+};
+
+struct Decide {
+    Ctrl* ctrl;
+    long long m_arcs;
+    int direction;
+    int alpha;
+    int phase;
+    __device__ bool operator()() const {
+        const int slot = phase % 3;
+        if (direction == 2 || load_agent_i32(&ctrl->fbad[slot]) != 0) return false;
+        if (direction == 1) return true;
+        const unsigned long long arcs = hln::dev::load_agent(&ctrl->farcs[slot]);
+        return static_cast<long long>(arcs) * alpha < m_arcs;
+    }
+};
+
+// Segments of vertex v, for the list: (first index, count, arcs).
+__device__ __forceinline__ int3 vertex_segments(const BfsArgs& a, int v) {
+    const int deg = a.row_ptr[v + 1] - a.row_ptr[v];
+    return make_int3(a.seg_first[v], (deg + a.seg_len - 1) / a.seg_len, deg);
+}
 
 __device__ __forceinline__ int seg_class(int deg, int seg_len) {
     if (deg > seg_len) return 0;
@@ -109,10 +181,11 @@ __device__ __forceinline__ int trace_add(int64_t* row, int verts, long long pair
 }
 
 // Finalise vertex v at level d: new bits, bitset updates, accumulation.
-// Called by the 8 lanes of a group with the group's full OR in `acc` (lane
-// (sub, k) holds word k; only sub == 0 lanes write).
+// Called by the lanes of a group with the group's full OR in `acc` (lane
+// (sub, k) holds word k; only sub == 0 lanes write).  Returns the number of
+// new bits and the number of words holding them.
 template <int NW, bool PER_SOURCE>
-__device__ __forceinline__ int finalize_vertex(const BfsArgs& a, uint64_t* nx, uint32_t* flag_nx, int v, int d, int k,
+__device__ __forceinline__ int2 finalize_vertex(const BfsArgs& a, uint64_t* nx, uint32_t* flag_nx, int v, int d, int k,
                                                int sub, int gl, int gbase, uint64_t acc, uint64_t vis_v,
                                                int32_t* s_cnt, int64_t s_old, int32_t r_old, uint32_t flag_old) {
     constexpr int LPV = lpv<NW>();
@@ -148,7 +221,7 @@ __device__ __forceinline__ int finalize_vertex(const BfsArgs& a, uint64_t* nx, u
             if (d == 2 && a.H2) a.H2[v] += c;
         }
     }
-    return c;
+    return make_int2(c, __popc(nmask));
 }
 
 // Gathering the frontier over a segment [lo, hi) for the word k of this
@@ -176,9 +249,12 @@ struct Gather {
         for (int h = 0; h < CH; ++h) msk[h] = cid[h] >= 0 ? flag_fr[cid[h]] : 0u;
     }
 
-    // only the words whose mask bit is set are gathered
+    // only the words whose mask bit is set are gathered, and none when the
+    // lane's word is already saturated (skip: vis | OR so far is all ones,
+    // so no further gather can add a bit outside vis)
     __device__ __forceinline__ static uint64_t round_or(const uint64_t* __restrict__ fr, const int (&cid)[CH],
-                                                        const uint32_t (&msk)[CH], int k, int sub, int gbase) {
+                                                        const uint32_t (&msk)[CH], int k, int sub, int gbase,
+                                                        bool skip) {
         uint64_t x = 0;
 #pragma unroll
         for (int t = 0; t < NW; ++t) {
@@ -187,7 +263,7 @@ struct Gather {
             for (int h = 0; h < CH; ++h) {
                 const int w = __shfl(cid[h], gbase + j, 64);
                 const uint32_t m = static_cast<uint32_t>(__shfl(static_cast<int>(msk[h]), gbase + j, 64));
-                if ((m >> k) & 1u) x |= fr[static_cast<size_t>(w) * NW + k];
+                if (((m >> k) & 1u) && !skip) x |= fr[static_cast<size_t>(w) * NW + k];
             }
         }
         return x;
@@ -250,14 +326,20 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
     const long long nthreads = static_cast<long long>(gridDim.x) * BLOCK;
     const long long gid = tid / kLpv;
     const long long ngroups = nthreads / kLpv;
+    // block-interleaved thread and group numbers: consecutive indices fall in
+    // different blocks, which spreads the block-local frontier lists
+    const long long tid_x = static_cast<long long>(threadIdx.x) * gridDim.x + blockIdx.x;
+    const long long gid_x = static_cast<long long>(threadIdx.x / kLpv) * gridDim.x + blockIdx.x;
     Ctrl* ctrl = a.ctrl;
     const int seg_len = a.seg_len;
+    hln::dev::GridBarrier gb{a.bar, a.fault, a.wait_ticks, 0u};
 
     __shared__ int32_t s_cnt[PER_SOURCE ? W : 1];
     __shared__ int64_t s_S[PER_SOURCE ? W : 1];
     __shared__ int32_t s_R[PER_SOURCE ? W : 1];
     __shared__ int s_bins[kClasses];
     __shared__ long long s_trace[2];
+    __shared__ FrontierLds s_fr;
 
     // ---- phase 0: zero accumulators and scratch, check the input, count
     // segments per class.  The input is checked here so that no later access
@@ -265,6 +347,10 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
     // count, column ids and listed sources in [0, n).  A violation is fault
     // code 2.
     if (threadIdx.x < kClasses) s_bins[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        s_fr.cnt[0] = s_fr.cnt[1] = 0;
+        s_fr.arcs[0] = s_fr.arcs[1] = 0;
+    }
     __syncthreads();
     int bad = 0;
     for (long long v = tid; v < n; v += nthreads) {
@@ -298,7 +384,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
     }
     __syncthreads();
     if (threadIdx.x < kClasses && s_bins[threadIdx.x]) atomicAdd(&ctrl->bins[threadIdx.x], s_bins[threadIdx.x]);
-    if (!grid_barrier(a.bar, a.fault, a.wait_ticks)) return;
+    if (!gb.wait()) return;
     if (load_agent_i32(a.fault) != 0) return;              // uniform: read after the barrier
 
     // ---- phase 1: class offsets
@@ -311,7 +397,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
         }
         store_agent_i32(&ctrl->n_seg, acc);
     }
-    if (!grid_barrier(a.bar, a.fault, a.wait_ticks)) return;
+    if (!gb.wait()) return;
 
     // ---- phase 2: fill the segment list (heavy rows first, then by
     // decreasing degree; order inside a class is arbitrary and does not
@@ -322,53 +408,80 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
         if (deg > 0) {
             const int segs = (deg + seg_len - 1) / seg_len;
             const int pos = atomicAdd(&ctrl->cursor[seg_class(deg, seg_len)], segs);
+            a.seg_first[v] = pos;
             for (int j = 0; j < segs && pos + j < a.seg_cap; ++j)
                 a.seg[pos + j] = make_int4(static_cast<int>(v), e0 + j * seg_len, min(e0 + (j + 1) * seg_len, e0 + deg), segs);
         }
     }
-    if (!grid_barrier(a.bar, a.fault, a.wait_ticks)) return;
+    if (!gb.wait()) return;
     const long long n_seg = min(static_cast<long long>(load_agent_i32(&ctrl->n_seg)), a.seg_cap);
 
     const int n_batches = (a.n_src + W - 1) / W;
+    const long long m_arcs = a.row_ptr[n];               // checked against nnz_cap in phase 0
+    const unsigned long long gmask = (kLpv >= 64 ? ~0ull : ((1ull << kLpv) - 1ull)) << gbase;
     int trace_row = 0;
+    int phase = 0;                                       // list slot of a phase: phase % 3
     for (int b = 0; b < n_batches; ++b) {
         const int src0 = b * W;
         const int cnt = min(W, a.n_src - src0);
 
-        // ---- batch init: vis = fr = the batch's source bits
-        if (!PER_SOURCE) {
-            for (long long i = tid; i < static_cast<long long>(n) * NW; i += nthreads) {
-                const long long v = i / NW;
-                const int kk = static_cast<int>(i % NW);
-                const long long bit = v - src0;
-                uint64_t w0 = 0;
-                if (bit >= 0 && bit < cnt && (bit >> 6) == kk) w0 = 1ull << (bit & 63);
-                a.vis[i] = w0;
-                a.bufA[i] = w0;
+        // ---- batch init: vis = fr = the batch's source bits; the sources'
+        // segments form the first frontier list
+        bool push;
+        {
+            const int par = phase & 1;
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                const int nx_slot = (phase + 1) % 3;
+                store_agent_i32(&ctrl->fbad[nx_slot], 0);
+                __hip_atomic_store(&ctrl->farcs[nx_slot], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            for (long long v = tid; v < n; v += nthreads)
-                a.flagA[v] = (v >= src0 && v < src0 + cnt) ? (1u << ((v - src0) >> 6)) : 0u;
-        } else {
-            for (long long i = tid; i < static_cast<long long>(n) * NW; i += nthreads) {
-                a.vis[i] = 0;
-                a.bufA[i] = 0;
+            if (!PER_SOURCE) {
+                for (long long i = tid; i < static_cast<long long>(n) * NW; i += nthreads) {
+                    const long long v = i / NW;
+                    const int kk = static_cast<int>(i % NW);
+                    const long long bit = v - src0;
+                    uint64_t w0 = 0;
+                    if (bit >= 0 && bit < cnt && (bit >> 6) == kk) w0 = 1ull << (bit & 63);
+                    a.vis[i] = w0;
+                    a.bufA[i] = w0;
+                }
+                for (long long v = tid; v < n; v += nthreads)
+                    a.flagA[v] = (v >= src0 && v < src0 + cnt) ? (1u << ((v - src0) >> 6)) : 0u;
+                for (long long i = tid_x; i < cnt; i += nthreads) {
+                    const int3 sg = vertex_segments(a, static_cast<int>(src0 + i));
+                    if (sg.y > 0) frontier_note(s_fr, par, sg.x, sg.y, sg.z);
+                }
+            } else {
+                for (long long i = tid; i < static_cast<long long>(n) * NW; i += nthreads) {
+                    a.vis[i] = 0;
+                    a.bufA[i] = 0;
+                }
+                for (long long v = tid; v < n; v += nthreads) a.flagA[v] = 0;
+                for (int i = threadIdx.x; i < W; i += BLOCK) {
+                    s_cnt[i] = 0;
+                    s_S[i] = 0;
+                    s_R[i] = 0;
+                }
+                if (!gb.wait()) return;
+                for (long long i = tid_x; i < cnt; i += nthreads) {
+                    const int s = a.sources[src0 + i];
+                    const size_t w = static_cast<size_t>(s) * NW + (i >> 6);
+                    atomicOr(reinterpret_cast<unsigned long long*>(&a.vis[w]), 1ull << (i & 63));
+                    atomicOr(reinterpret_cast<unsigned long long*>(&a.bufA[w]), 1ull << (i & 63));
+                    // the first source bit on a vertex lists it (once, even if
+                    // the vertex is listed as a source more than once)
+                    if (atomicOr(&a.flagA[s], 1u << (i >> 6)) == 0u) {
+                        const int3 sg = vertex_segments(a, s);
+                        if (sg.y > 0) frontier_note(s_fr, par, sg.x, sg.y, sg.z);
+                    }
+                }
             }
-            for (long long v = tid; v < n; v += nthreads) a.flagA[v] = 0;
-            for (int i = threadIdx.x; i < W; i += BLOCK) {
-                s_cnt[i] = 0;
-                s_S[i] = 0;
-                s_R[i] = 0;
-            }
-            if (!grid_barrier(a.bar, a.fault, a.wait_ticks)) return;
-            for (long long i = tid; i < cnt; i += nthreads) {
-                const int s = a.sources[src0 + i];
-                const size_t w = static_cast<size_t>(s) * NW + (i >> 6);
-                atomicOr(reinterpret_cast<unsigned long long*>(&a.vis[w]), 1ull << (i & 63));
-                atomicOr(reinterpret_cast<unsigned long long*>(&a.bufA[w]), 1ull << (i & 63));
-                atomicOr(&a.flagA[s], 1u << (i >> 6));
-            }
+            const hln::dev::BarrierResult br =
+                gb.sync(0, PhaseEnd{&s_fr, ctrl, phase}, Decide{ctrl, m_arcs, a.direction, a.alpha, phase});
+            if (!br.ok) return;
+            push = br.decision;
+            ++phase;
         }
-        if (!grid_barrier(a.bar, a.fault, a.wait_ticks)) return;
 
         // ---- level loop; the barrier's OR tells every block whether any
         // vertex got a new bit, which ends this batch's BFS
@@ -377,103 +490,190 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
         uint32_t* flag_fr = a.flagA;
         uint32_t* flag_nx = a.flagB;
         for (int d = 1;; ++d) {
+            const int par = phase & 1;                   // this phase's list; the previous one is par ^ 1
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                const int nx_slot = (phase + 1) % 3;
+                store_agent_i32(&ctrl->fbad[nx_slot], 0);
+                __hip_atomic_store(&ctrl->farcs[nx_slot], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
             int any = 0;
             long long t_pairs = 0;
             int t_verts = 0;
-            long long s = gid;
-            const int4 kNone = make_int4(0, 0, 0, 0);
-            SegPre<NW> cur, nxt;
-            seg_prefetch<NW, PER_SOURCE>(a, flag_nx, s < n_seg ? a.seg[s] : kNone, s < n_seg, gl, cur);
-            seg_prefetch<NW, PER_SOURCE>(a, flag_nx, s + ngroups < n_seg ? a.seg[s + ngroups] : kNone,
-                                         s + ngroups < n_seg, gl, nxt);
-            seg_flags<NW>(flag_fr, cur);
-            int4 rec2 = s + 2 * ngroups < n_seg ? a.seg[s + 2 * ngroups] : kNone;
-            while (s < n_seg) {
-                const long long s1 = s + ngroups;
-                const long long s2 = s1 + ngroups;
-                const long long s3 = s2 + ngroups;
-                const int4 rec3 = s3 < n_seg ? a.seg[s3] : kNone;                  // record, 3 ahead
-                SegPre<NW> nn;
-                seg_prefetch<NW, PER_SOURCE>(a, flag_nx, rec2, s2 < n_seg, gl, nn);  // ids, 2 ahead
-                seg_flags<NW>(flag_fr, nxt);                                        // flags, 1 ahead
-
-                const int v = cur.sg.x;
-                const int nseg = cur.sg.w;
-                const size_t base = static_cast<size_t>(v) * NW + k;
-                bool active = false;
+            if (push) {
+                // ---- top-down, part 1: each block ORs the frontier words of
+                // the segments on its own list into their neighbours'
+                // accumulators (no block's list overflowed, or the level
+                // would be bottom-up)
+                const int flen = min(s_fr.cnt[par ^ 1], kFlCap);
+                for (int i = static_cast<int>(threadIdx.x) / kLpv; i < flen; i += BLOCK / kLpv) {
+                    const int4 sg = a.seg[s_fr.fl[par ^ 1][i]];
+                    const int u = sg.x;
+                    const uint32_t fm = flag_fr[u];
+                    const uint64_t x = ((fm >> k) & 1u) ? fr[static_cast<size_t>(u) * NW + k] : 0ull;
+                    for (int c = sg.y; c < sg.z; c += kLpv) {
+                        const int wl = (c + gl < sg.z) ? a.col_idx[c + gl] : -1;
 #pragma unroll
-                for (int h = 0; h < Gather<NW>::CH; ++h) active |= cur.fl[h] != 0u;
-                // the visited word is read only when a neighbour is active, the
-                // segment has further rounds or the row has several segments (its
-                // finaliser needs it), together with the gathers
-                const unsigned long long gmask = (kLpv >= 64 ? ~0ull : ((1ull << kLpv) - 1ull)) << gbase;
-                const bool need = ((__ballot(active) & gmask) != 0) || (cur.sg.z - cur.sg.y > Gather<NW>::ROUND) ||
-                                  nseg > 1;
-                uint64_t vis_v = 0;
-                uint64_t acc = 0;
-                if (need) {
-                    vis_v = a.vis[base];
-                    acc = Gather<NW>::round_or(fr, cur.cid, cur.fl, k, sub, gbase);
-                    for (int c = cur.sg.y + Gather<NW>::ROUND; c < cur.sg.z; c += Gather<NW>::ROUND) {
-                        int cid[Gather<NW>::CH];
-                        uint32_t msk[Gather<NW>::CH];
-                        Gather<NW>::load_ids(a.col_idx, c, cur.sg.z, gl, cid);
-                        Gather<NW>::load_masks(flag_fr, cid, msk);
-                        acc |= Gather<NW>::round_or(fr, cid, msk, k, sub, gbase);
+                        for (int t = 0; t < NW; ++t) {
+                            const int w = __shfl(wl, gbase + t * Gather<NW>::NPAR + sub, 64);
+                            if (w >= 0 && x)
+                                __hip_atomic_fetch_or(reinterpret_cast<unsigned long long*>(&a.hacc[static_cast<size_t>(w) * NW + k]),
+                                                      static_cast<unsigned long long>(x), __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                        if (wl >= 0) store_agent_i32(&a.hcnt[wl], 1);
                     }
                 }
-#pragma unroll
-                for (int off = NW; off < kLpv; off <<= 1) acc |= shfl_xor_u64(acc, off);
-                if (nseg == 1) {
-                    const int c = finalize_vertex<NW, PER_SOURCE>(a, nx, flag_nx, v, d, k, sub, gl, gbase, acc, vis_v,
-                                                                  s_cnt, cur.s_old, cur.r_old, cur.flag_old);
-                    any |= c;
-                    t_pairs += c;
-                    t_verts += c != 0;
-                } else {
-                    // multi-segment row: merge, the last finisher finalises
-                    if (sub == 0 && acc)
-                        __hip_atomic_fetch_or(reinterpret_cast<unsigned long long*>(&a.hacc[base]),
-                                              static_cast<unsigned long long>(acc), __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-                    // the wave's OR atomics are performed before the count is
-                    // raised (agent-scope atomics complete at the coherence
-                    // point; vmcnt(0) waits for their acknowledgement)
-                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                    __builtin_amdgcn_s_waitcnt(0);
-                    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                    int old = 0;
-                    if (gl == 0)
-                        old = __hip_atomic_fetch_add(&a.hcnt[v], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    old = __shfl(old, gbase, 64);
-                    if (old == nseg - 1) {
-                        uint64_t full = 0;
-                        if (sub == 0)
-                            full = __hip_atomic_exchange(reinterpret_cast<unsigned long long*>(&a.hacc[base]), 0ull,
-                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-#pragma unroll
-                        for (int off = NW; off < kLpv; off <<= 1) full |= shfl_xor_u64(full, off);
+                if (!gb.wait()) return;
+                // ---- part 2: finalise touched vertices; vertices that hold
+                // words of the older frontier in nx get them cleared
+                for (long long v0 = gid_x * kLpv; v0 < n; v0 += ngroups * kLpv) {
+                    const long long vl = v0 + gl;
+                    int touched = 0;
+                    uint32_t fo = 0;
+                    if (vl < n) {
+                        touched = load_agent_i32(&a.hcnt[vl]);
+                        fo = flag_nx[vl];
+                    }
+                    unsigned long long ball = (__ballot(touched != 0 || fo != 0u) & gmask) >> gbase;
+                    while (ball) {
+                        const int j = __ffsll(static_cast<long long>(ball)) - 1;
+                        ball &= ball - 1;
+                        const int v = static_cast<int>(v0 + j);
+                        const int tj = __shfl(touched, gbase + j, 64);
+                        const uint32_t foj = static_cast<uint32_t>(__shfl(static_cast<int>(fo), gbase + j, 64));
+                        const size_t base = static_cast<size_t>(v) * NW + k;
+                        uint64_t acc = 0, vis_v = 0;
                         int64_t s_old = 0;
                         int32_t r_old = 0;
-                        const uint32_t flag_old = flag_nx[v];
-                        if (gl == 0) {
-                            store_agent_i32(&a.hcnt[v], 0);
-                            if (!PER_SOURCE) {
-                                s_old = a.S[v];
-                                r_old = a.R[v];
+                        if (tj) {
+                            if (sub == 0) {
+                                acc = __hip_atomic_exchange(reinterpret_cast<unsigned long long*>(&a.hacc[base]), 0ull,
+                                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                vis_v = a.vis[base];
+                            }
+                            if (gl == 0) {
+                                store_agent_i32(&a.hcnt[v], 0);
+                                if (!PER_SOURCE) {
+                                    s_old = a.S[v];
+                                    r_old = a.R[v];
+                                }
                             }
                         }
-                        const int c = finalize_vertex<NW, PER_SOURCE>(a, nx, flag_nx, v, d, k, sub, gl, gbase, full,
-                                                                      vis_v, s_cnt, s_old, r_old, flag_old);
-                        any |= c;
-                        t_pairs += c;
-                        t_verts += c != 0;
+                        const int2 cw = finalize_vertex<NW, PER_SOURCE>(a, nx, flag_nx, v, d, k, sub, gl, gbase, acc,
+                                                                        vis_v, s_cnt, s_old, r_old, foj);
+                        if (cw.x) {
+                            any = 1;
+                            t_pairs += cw.x;
+                            t_verts += 1;
+                            if (gl == 0) {
+                                const int3 sgv = vertex_segments(a, v);
+                                if (sgv.y > 0) frontier_note(s_fr, par, sgv.x, sgv.y, sgv.z * cw.y);
+                            }
+                        }
                     }
                 }
-                s = s1;
-                cur = nxt;
-                nxt = nn;
-                rec2 = rec3;
+            } else {
+                // ---- bottom-up over all segments
+                long long s = gid;
+                const int4 kNone = make_int4(0, 0, 0, 0);
+                SegPre<NW> cur, nxt;
+                seg_prefetch<NW, PER_SOURCE>(a, flag_nx, s < n_seg ? a.seg[s] : kNone, s < n_seg, gl, cur);
+                seg_prefetch<NW, PER_SOURCE>(a, flag_nx, s + ngroups < n_seg ? a.seg[s + ngroups] : kNone,
+                                             s + ngroups < n_seg, gl, nxt);
+                seg_flags<NW>(flag_fr, cur);
+                int4 rec2 = s + 2 * ngroups < n_seg ? a.seg[s + 2 * ngroups] : kNone;
+                while (s < n_seg) {
+                    const long long s1 = s + ngroups;
+                    const long long s2 = s1 + ngroups;
+                    const long long s3 = s2 + ngroups;
+                    const int4 rec3 = s3 < n_seg ? a.seg[s3] : kNone;                  // record, 3 ahead
+                    SegPre<NW> nn;
+                    seg_prefetch<NW, PER_SOURCE>(a, flag_nx, rec2, s2 < n_seg, gl, nn);  // ids, 2 ahead
+                    seg_flags<NW>(flag_fr, nxt);                                        // flags, 1 ahead
+
+                    const int v = cur.sg.x;
+                    const int nseg = cur.sg.w;
+                    const size_t base = static_cast<size_t>(v) * NW + k;
+                    bool active = false;
+#pragma unroll
+                    for (int h = 0; h < Gather<NW>::CH; ++h) active |= cur.fl[h] != 0u;
+                    // the visited word is read only when a neighbour is active, the
+                    // segment has further rounds or the row has several segments (its
+                    // finaliser needs it), together with the gathers
+                    const bool need = ((__ballot(active) & gmask) != 0) || (cur.sg.z - cur.sg.y > Gather<NW>::ROUND) ||
+                                      nseg > 1;
+                    uint64_t vis_v = 0;
+                    uint64_t acc = 0;
+                    if (need) {
+                        vis_v = a.vis[base];
+                        acc = Gather<NW>::round_or(fr, cur.cid, cur.fl, k, sub, gbase, vis_v == ~0ull);
+                        for (int c = cur.sg.y + Gather<NW>::ROUND; c < cur.sg.z; c += Gather<NW>::ROUND) {
+                            int cid[Gather<NW>::CH];
+                            uint32_t msk[Gather<NW>::CH];
+                            Gather<NW>::load_ids(a.col_idx, c, cur.sg.z, gl, cid);
+                            Gather<NW>::load_masks(flag_fr, cid, msk);
+                            acc |= Gather<NW>::round_or(fr, cid, msk, k, sub, gbase, (vis_v | acc) == ~0ull);
+                        }
+                    }
+#pragma unroll
+                    for (int off = NW; off < kLpv; off <<= 1) acc |= shfl_xor_u64(acc, off);
+                    if (nseg == 1) {
+                        const int2 cw = finalize_vertex<NW, PER_SOURCE>(a, nx, flag_nx, v, d, k, sub, gl, gbase, acc,
+                                                                        vis_v, s_cnt, cur.s_old, cur.r_old, cur.flag_old);
+                        if (cw.x) {
+                            any = 1;
+                            t_pairs += cw.x;
+                            t_verts += 1;
+                            if (gl == 0) frontier_note(s_fr, par, static_cast<int>(s), 1, (cur.sg.z - cur.sg.y) * cw.y);
+                        }
+                    } else {
+                        // multi-segment row: merge, the last finisher finalises
+                        if (sub == 0 && acc)
+                            __hip_atomic_fetch_or(reinterpret_cast<unsigned long long*>(&a.hacc[base]),
+                                                  static_cast<unsigned long long>(acc), __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+                        // the wave's OR atomics are performed before the count is
+                        // raised (agent-scope atomics complete at the coherence
+                        // point; vmcnt(0) waits for their acknowledgement)
+                        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                        __builtin_amdgcn_s_waitcnt(0);
+                        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                        int old = 0;
+                        if (gl == 0)
+                            old = __hip_atomic_fetch_add(&a.hcnt[v], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        old = __shfl(old, gbase, 64);
+                        if (old == nseg - 1) {
+                            uint64_t full = 0;
+                            if (sub == 0)
+                                full = __hip_atomic_exchange(reinterpret_cast<unsigned long long*>(&a.hacc[base]), 0ull,
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                            for (int off = NW; off < kLpv; off <<= 1) full |= shfl_xor_u64(full, off);
+                            int64_t s_old = 0;
+                            int32_t r_old = 0;
+                            const uint32_t flag_old = flag_nx[v];
+                            if (gl == 0) {
+                                store_agent_i32(&a.hcnt[v], 0);
+                                if (!PER_SOURCE) {
+                                    s_old = a.S[v];
+                                    r_old = a.R[v];
+                                }
+                            }
+                            const int2 cw = finalize_vertex<NW, PER_SOURCE>(a, nx, flag_nx, v, d, k, sub, gl, gbase,
+                                                                            full, vis_v, s_cnt, s_old, r_old, flag_old);
+                            if (cw.x) {
+                                any = 1;
+                                t_pairs += cw.x;
+                                t_verts += 1;
+                                if (gl == 0) frontier_note(s_fr, par, a.seg_first[v], nseg, nseg * seg_len * cw.y);
+                            }
+                        }
+                    }
+                    s = s1;
+                    cur = nxt;
+                    nxt = nn;
+                    rec2 = rec3;
+                }
             }
             if (PER_SOURCE) {
                 __syncthreads();
@@ -501,10 +701,15 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                 __syncthreads();
                 if (threadIdx.x == 0 && s_trace[0]) (void)trace_add(a.trace + 4 * trace_row, s_trace[0], s_trace[1]);
             }
-            const hln::dev::BarrierResult br = grid_barrier_or(a.bar, any, a.fault, a.wait_ticks);
+            const hln::dev::BarrierResult br =
+                gb.sync(any, PhaseEnd{&s_fr, ctrl, phase}, Decide{ctrl, m_arcs, a.direction, a.alpha, phase});
             if (!br.ok) return;
-            if (a.trace && trace_row < a.trace_cap && blockIdx.x == 0 && threadIdx.x == 0)
+            if (a.trace && trace_row < a.trace_cap && blockIdx.x == 0 && threadIdx.x == 0) {
                 a.trace[4 * trace_row] = static_cast<int64_t>(__builtin_amdgcn_s_memrealtime());
+                a.trace[4 * trace_row + 3] = push ? 1 : 0;
+            }
+            push = br.decision;
+            ++phase;
             ++trace_row;
             if (!br.any) {
                 // level d found nothing new: the batch's largest eccentricity is d - 1
@@ -526,7 +731,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                 pS[i] = s_S[i];
                 pR[i] = s_R[i];
             }
-            if (!grid_barrier(a.bar, a.fault, a.wait_ticks)) return;
+            if (!gb.wait()) return;
             for (long long i = tid; i < cnt; i += nthreads) {
                 int64_t sS = 0, sR = 0;
                 for (unsigned blk = 0; blk < gridDim.x; ++blk) {
@@ -545,7 +750,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
     if (a.cc) {
         // all-source mode: S and R were last written before the final level
         // barrier; listed sources: the last writes are the reduction above
-        if (PER_SOURCE && !grid_barrier(a.bar, a.fault, a.wait_ticks)) return;
+        if (PER_SOURCE && !gb.wait()) return;
         for (long long i = tid; i < a.n_src; i += nthreads) {
             const int64_t sv = a.S[i];
             const int32_t r = a.R[i];
@@ -666,7 +871,7 @@ size_t workspace_bytes(int32_t n, int64_t nnz, int nw, int grid_cap) {
     b += Arena::round(hln::dev::kBarrierWords * sizeof(unsigned long long));
     b += 4 * Arena::round(words * sizeof(uint64_t));            // A, B, vis, hacc
     b += 2 * Arena::round(static_cast<size_t>(n) * 4);          // word masks of A, B
-    b += Arena::round(static_cast<size_t>(n) * sizeof(int32_t)); // hcnt
+    b += 2 * Arena::round(static_cast<size_t>(n) * sizeof(int32_t)); // hcnt, seg_first
     b += Arena::round(seg_cap * sizeof(int4));
     b += Arena::round(static_cast<size_t>(grid_cap) * 2 * 64 * nw * sizeof(int64_t));  // per-source partials
     return b;
@@ -736,6 +941,7 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
     a.hcnt = ar.take<int32_t>(n);
     a.seg_cap = static_cast<long long>(n) + g->nnz / kSegLen + 1;
     a.seg = ar.take<int4>(static_cast<size_t>(a.seg_cap));
+    a.seg_first = ar.take<int32_t>(n);
     a.nnz_cap = g->nnz;
     a.part = ar.take<int64_t>(static_cast<size_t>(grid_cap) * 2 * 64 * nw);
     a.S = S;
@@ -749,9 +955,9 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
     a.trace = opts ? opts->trace : nullptr;
     a.trace_cap = opts ? opts->trace_cap : 0;
     a.seg_len = kSegLen;
-    a.alpha = 14;
-    a.beta = 24;
-    if (!a.ctrl || !a.bar || !a.part || !a.flagB) return fail(HLN_ENOMEM, "workspace carve failed");
+    a.alpha = 4;
+    if (const char* e = getenv("HLN_ALPHA")) a.alpha = std::max(1, atoi(e));
+    if (!a.ctrl || !a.bar || !a.part || !a.flagB || !a.seg_first) return fail(HLN_ENOMEM, "workspace carve failed");
 
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(k_zero_ctrl, dim3(1), dim3(256), 0, st, a.ctrl, a.bar);

@@ -24,9 +24,9 @@ def run_all(rp, ci, width, want_h2=True, direction=0):
     return {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
 
 
-def check_all(n, rp, ci, width, tag):
-    say(tag, "n=%d nnz=%d W=%d" % (n, len(ci), width))
-    got = run_all(rp, ci, width)
+def check_all(n, rp, ci, width, tag, direction=0):
+    say(tag, "n=%d nnz=%d W=%d direction=%d" % (n, len(ci), width, direction))
+    got = run_all(rp, ci, width, direction=direction)
     S, R, H2, _, _ = O.bfs_sums(rp, ci, extras=True)
     cc = O.closeness_wf(n, S, R)
     assert np.array_equal(got["S"], S), (tag, np.nonzero(got["S"] != S)[0][:10])
@@ -160,3 +160,58 @@ def test_levels_per_batch(width):
         _, _, _, ecc, _ = O.bfs_sums(rp, ci, extras=True)
         ref = [1 + int(ecc[b * width:(b + 1) * width].max()) for b in range(nb)]
         assert lv.cpu().numpy().tolist() == ref
+
+
+@pytest.mark.parametrize("width", [64, 256, 2048])
+@pytest.mark.parametrize("direction", [1, 2], ids=["top_down", "bottom_up"])
+def test_forced_direction(direction, width):
+    """Every level top-down (push) or every level bottom-up (pull)."""
+    for named in [("path", 300), ("star", 1000), ("complete", 150), ("bipartite", 70, 130)]:
+        n, eu, ev = G.named_graph(*named)
+        rp, ci = csr_np(n, *G.to_edges(n, eu, ev))
+        check_all(n, rp, ci, width, "named-%s" % (named,), direction)
+    rng = np.random.default_rng(500 + width + direction)
+    for trial in range(4):
+        n = int(rng.integers(2, 3000))
+        m = int(n * rng.choice([0.3, 1.0, 4.0]))
+        keys = G.take_distinct(G.er_draw(n), min(m, n * (n - 1) // 2), n, rng)
+        rp, ci = csr_np(n, *G.keys_to_edges(keys, n))
+        check_all(n, rp, ci, width, "random-%d" % trial, direction)
+    h = C.config2(scale=0.05)
+    rp, ci = csr_np(h.n, *h.layers[1])
+    check_all(h.n, rp, ci, width, "cfg2-scaled", direction)
+    # listed sources, with hubs among them
+    src = np.unique(np.concatenate([np.argsort(-np.diff(rp))[:20], rng.choice(h.n, 300, replace=False)]))
+    src = src.astype(np.int32)
+    g = graph_dev(P, rp, ci)
+    out = P.hln_closeness_layer(g, sources=to_dev(src), width_bits=width, direction=direction)
+    torch.cuda.synchronize()
+    P.device_status()
+    S, R = O.bfs_sums(rp, ci, sources=src)
+    assert np.array_equal(out["S"].cpu().numpy(), S)
+    assert np.array_equal(out["R"].cpu().numpy(), R)
+
+
+def test_auto_direction_takes_both():
+    """The automatic choice runs the first levels of a batch top-down (a few
+    sources' neighbourhoods) and the dense middle bottom-up; the trace
+    records each level's direction and new vertices."""
+    h = C.config2(scale=0.1)
+    rp, ci = csr_np(h.n, *h.layers[0])
+    g = graph_dev(P, rp, ci)
+    tr = torch.zeros((4096, 4), dtype=torch.int64, device="cuda")
+    lv = torch.zeros((h.n + 511) // 512, dtype=torch.int32, device="cuda")
+    out = P.hln_closeness_layer(g, width_bits=512, want_h2=True, levels=lv, trace=tr)
+    torch.cuda.synchronize()
+    P.device_status()
+    rows = int(lv.sum().item())
+    t = tr[:rows].cpu().numpy()
+    dirs = t[:, 3]
+    say("levels", rows, "top-down", int(dirs.sum()))
+    assert 0 < dirs.sum() < rows
+    S, R, H2, _, _ = O.bfs_sums(rp, ci, extras=True)
+    assert np.array_equal(out["S"].cpu().numpy(), S)
+    assert np.array_equal(out["h2"].cpu().numpy(), H2)
+    # the first level of a batch is top-down unless its sources hold hubs
+    starts = np.concatenate([[0], np.cumsum(lv.cpu().numpy())[:-1]])
+    assert np.mean(dirs[starts] == 1) >= 0.8
