@@ -33,7 +33,7 @@ if ROOT not in sys.path:
 METRIC = "GTEPS all-source BFS closeness (+% HBM roofline); top-K precision vs AND truth"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_closeness_cfg2_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2207_11662_amd", "csrc", "hln_msbfs.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_2207_11662_amd", "csrc", f) for f in ("hln_msbfs.hip", "hln_internal.hpp")]
 
 
 def log(*a):
@@ -63,8 +63,12 @@ def and_edges(n, layers):
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the closeness kernel's sources (kernel and grid barrier)."""
+    h = hashlib.sha256()
+    for p in KERNEL_SRC:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def calibrate_copy(nbytes: int):
