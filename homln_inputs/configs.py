@@ -118,13 +118,38 @@ def config3(count: int = 64, scale: float = 1.0) -> list:
     return [config3_homln(h, scale) for h in range(count)]
 
 
-def config4(scale: float = 1.0) -> HoMLN:
+def _rmat_private(n: int, l: int, m: int, base_sorted: np.ndarray) -> np.ndarray:
+    """Config 4's private edges of layer l (a process-pool task)."""
+    return G.take_distinct(G.rmat_draw(n), max(0, m - len(base_sorted)), n, G.rng_for(4, 0, l), exclude=base_sorted)
+
+
+def config4(scale: float = 1.0, workers: int = 1, progress=None) -> HoMLN:
+    """workers > 1 draws the six private edge streams in that many spawned
+    processes (each stream has its own seed, so the result is the same);
+    progress(str) is called after the base and after each layer."""
     n = max(256, int(round(1_000_000 * scale)))
     m = n * 16 // 2
-    draw = G.rmat_draw(n)
-    specs = [("stream", draw, m) for _ in range(6)]
-    return _shared_homln(4, 0, n, draw, int(math.ceil(0.25 * m)), specs, "cfg4-rmat-6x%d" % n,
-                         {"layers": 6, "family": "R-MAT", "avg_degree": 16, "shared": 0.25})
+    base = G.take_distinct(G.rmat_draw(n), int(math.ceil(0.25 * m)), n, G.rng_for(4, 0, 255))
+    base_sorted = np.sort(base)
+    if progress:
+        progress("config 4: base of %d edges drawn" % len(base))
+    priv = [None] * 6
+    if workers > 1:
+        import multiprocessing as mp
+        from concurrent.futures import ProcessPoolExecutor, as_completed
+        with ProcessPoolExecutor(max_workers=min(workers, 6), mp_context=mp.get_context("spawn")) as ex:
+            futs = {ex.submit(_rmat_private, n, l, m, base_sorted): l for l in range(6)}
+            for f in as_completed(futs):
+                priv[futs[f]] = f.result()
+                if progress:
+                    progress("config 4: layer %d drawn" % futs[f])
+    else:
+        for l in range(6):
+            priv[l] = _rmat_private(n, l, m, base_sorted)
+            if progress:
+                progress("config 4: layer %d drawn" % l)
+    return _assemble(4, 0, n, base, priv, "cfg4-rmat-6x%d" % n,
+                     {"layers": 6, "family": "R-MAT", "avg_degree": 16, "shared": 0.25})
 
 
 def config4_sources(g: int, deg: np.ndarray, count: int = 16384) -> np.ndarray:

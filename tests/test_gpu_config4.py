@@ -1,0 +1,58 @@
+"""Config 4 at full size: 6 R-MAT layers over 1,000,000 vertices and their
+AND graph, 16,384 seeded sources per graph, listed-source closeness at
+W = 512 (the launch configuration bench.py times).  Sampled sources are
+checked against one oracle BFS each (S, R bit-exact, closeness bit-exact);
+R of every source is checked against the connected components."""
+import numpy as np
+import pytest
+import torch
+
+from homln_inputs import configs as C
+from oracle import oracle as O
+from tests.gpu_common import csr_np, say, to_dev
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+P = pytest.importorskip("paper_2207_11662_amd")
+from paper_2207_11662_amd import proposer as PR  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def cfg4():
+    h = C.config4(workers=8, progress=lambda s: say(s))
+    layers = [csr_np(h.n, *e) for e in h.layers]
+    say("host CSR built")
+    A = O.compose("and", layers)
+    say("AND graph: %d arcs" % len(A[1]))
+    return h, layers + [A]
+
+
+@pytest.mark.timeout(1200)
+def test_config4_listed_sources_sampled(cfg4):
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    h, host = cfg4
+    n = h.n
+    dev_layers = PR.upload_homln(h)
+    g_and = P.hln_compose_and(dev_layers).trimmed()
+    graphs = dev_layers + [g_and]
+    rng = np.random.default_rng(44)
+    for gi, (g, (rp, ci)) in enumerate(zip(graphs, host)):
+        assert g.nnz == len(ci)
+        src = C.config4_sources(gi, np.diff(rp))
+        say("graph", gi, "sources", len(src))
+        out = P.hln_closeness_layer(g, sources=to_dev(src), width_bits=512)
+        torch.cuda.synchronize()
+        P.device_status()
+        S_g = out["S"].cpu().numpy()
+        R_g = out["R"].cpu().numpy()
+        cc_g = out["cc"].cpu().numpy()
+        pos = np.sort(rng.choice(len(src), size=24, replace=False))
+        S, R = O.bfs_sums(rp, ci, sources=src[pos])
+        cc = O.closeness_wf(n, S, R)
+        assert np.array_equal(S_g[pos], S), gi
+        assert np.array_equal(R_g[pos], R), gi
+        assert np.array_equal(cc_g[pos].view(np.int64), cc.view(np.int64)), gi
+        adj = sp.csr_matrix((np.ones(len(ci), np.int8), ci, rp), shape=(n, n))
+        _, lab = connected_components(adj, directed=False)
+        assert np.array_equal(R_g, np.bincount(lab)[lab[src]]), gi
