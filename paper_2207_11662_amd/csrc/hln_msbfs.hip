@@ -55,6 +55,9 @@ using hln::dev::shfl_xor_i32;
 using hln::dev::shfl_xor_u64;
 using hln::dev::store_agent_i32;
 
+// Eight zero words, never written: the source of a gather a lane does not need.
+__device__ uint64_t g_zero_words[8];
+
 // lanes per group (one segment at a time): 8, or NW when NW > 8
 template <int NW>
 constexpr int lpv() { return NW > 8 ? NW : 8; }
@@ -249,22 +252,43 @@ struct Gather {
         for (int h = 0; h < CH; ++h) msk[h] = cid[h] >= 0 ? flag_fr[cid[h]] : 0u;
     }
 
-    // only the words whose mask bit is set are gathered, and none when the
-    // lane's word is already saturated (skip: vis | OR so far is all ones,
-    // so no further gather can add a bit outside vis)
+    // Gathers go out in wave-uniform chunks of K with no branch inside a
+    // chunk, so a chunk's loads are all in flight before the first OR waits
+    // for one: a lane whose arc is absent, whose neighbour's word is zero or
+    // whose word is saturated (skip: vis | OR so far is all ones, so nothing
+    // outside vis can be added) reads a static zero word instead.  A chunk
+    // that no lane of the wave needs is skipped.  `cnt` is the number of
+    // arcs of this round that belong to the group's segment.
+    static constexpr int T = NW * CH;                    // (chunk, t) steps per round
+    static constexpr int K = T < 8 ? T : 8;
+
+    __device__ __forceinline__ static int steps_needed(int cnt) {
+        if (cnt <= 0) return 0;
+        return ((cnt - 1) / LPV) * NW + ((cnt - 1) % LPV) / NPAR + 1;
+    }
+
     __device__ __forceinline__ static uint64_t round_or(const uint64_t* __restrict__ fr, const int (&cid)[CH],
                                                         const uint32_t (&msk)[CH], int k, int sub, int gbase,
-                                                        bool skip) {
+                                                        bool skip, int cnt, const uint64_t* zero) {
         uint64_t x = 0;
+        const int need = steps_needed(cnt);
 #pragma unroll
-        for (int t = 0; t < NW; ++t) {
-            const int j = t * NPAR + sub;
+        for (int q0 = 0; q0 < T; q0 += K) {
+            if (!__any(q0 < need)) break;
+            uint64_t v[K];
 #pragma unroll
-            for (int h = 0; h < CH; ++h) {
+            for (int q = 0; q < K; ++q) {
+                const int h = (q0 + q) / NW;
+                const int t = (q0 + q) % NW;
+                const int j = t * NPAR + sub;
                 const int w = __shfl(cid[h], gbase + j, 64);
                 const uint32_t m = static_cast<uint32_t>(__shfl(static_cast<int>(msk[h]), gbase + j, 64));
-                if (((m >> k) & 1u) && !skip) x |= fr[static_cast<size_t>(w) * NW + k];
+                const bool ok = ((m >> k) & 1u) && !skip;
+                const uint64_t* src = ok ? fr + static_cast<size_t>(w) * NW + k : zero;
+                v[q] = *src;
             }
+#pragma unroll
+            for (int q = 0; q < K; ++q) x |= v[q];
         }
         return x;
     }
@@ -606,13 +630,15 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                     uint64_t acc = 0;
                     if (need) {
                         vis_v = a.vis[base];
-                        acc = Gather<NW>::round_or(fr, cur.cid, cur.fl, k, sub, gbase, vis_v == ~0ull);
+                        acc = Gather<NW>::round_or(fr, cur.cid, cur.fl, k, sub, gbase, vis_v == ~0ull,
+                                                   cur.sg.z - cur.sg.y, g_zero_words);
                         for (int c = cur.sg.y + Gather<NW>::ROUND; c < cur.sg.z; c += Gather<NW>::ROUND) {
                             int cid[Gather<NW>::CH];
                             uint32_t msk[Gather<NW>::CH];
                             Gather<NW>::load_ids(a.col_idx, c, cur.sg.z, gl, cid);
                             Gather<NW>::load_masks(flag_fr, cid, msk);
-                            acc |= Gather<NW>::round_or(fr, cid, msk, k, sub, gbase, (vis_v | acc) == ~0ull);
+                            acc |= Gather<NW>::round_or(fr, cid, msk, k, sub, gbase, (vis_v | acc) == ~0ull,
+                                                        cur.sg.z - c, g_zero_words);
                         }
                     }
 #pragma unroll
