@@ -55,8 +55,26 @@ using hln::dev::shfl_xor_i32;
 using hln::dev::shfl_xor_u64;
 using hln::dev::store_agent_i32;
 
-// Eight zero words, never written: the source of a gather a lane does not need.
-__device__ uint64_t g_zero_words[8];
+#ifndef HLN_GATHER_CHUNK
+#define HLN_GATHER_CHUNK 8     // frontier gathers in flight per lane and chunk
+#endif
+
+// Frontier gathers use raw buffer loads: 32-bit byte offsets (one VALU
+// operation per address) and an out-of-range offset for a lane that needs no
+// word, which returns zero without a memory access.  The host guarantees
+// that a bitset is smaller than 2^31 bytes.
+typedef unsigned int hln_u32x2 __attribute__((ext_vector_type(2)));
+constexpr uint32_t kNoWord = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t words_rsrc(const uint64_t* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint64_t*>(p), static_cast<short>(0), static_cast<int>(bytes),
+                                             0x00020000);
+}
+
+__device__ __forceinline__ uint64_t buf_word(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    const hln_u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    return (static_cast<uint64_t>(v.y) << 32) | v.x;
+}
 
 // lanes per group (one segment at a time): 8, or NW when NW > 8
 template <int NW>
@@ -256,20 +274,22 @@ struct Gather {
     // chunk, so a chunk's loads are all in flight before the first OR waits
     // for one: a lane whose arc is absent, whose neighbour's word is zero or
     // whose word is saturated (skip: vis | OR so far is all ones, so nothing
-    // outside vis can be added) reads a static zero word instead.  A chunk
-    // that no lane of the wave needs is skipped.  `cnt` is the number of
-    // arcs of this round that belong to the group's segment.
+    // outside vis can be added) loads from an out-of-range offset, which
+    // reads zero.  A chunk that no lane of the wave needs is skipped.  `cnt`
+    // is the number of arcs of this round that belong to the group's
+    // segment.
     static constexpr int T = NW * CH;                    // (chunk, t) steps per round
-    static constexpr int K = T < 8 ? T : 8;
+    static constexpr int KMAX = HLN_GATHER_CHUNK;
+    static constexpr int K = T < KMAX ? T : KMAX;
 
     __device__ __forceinline__ static int steps_needed(int cnt) {
         if (cnt <= 0) return 0;
         return ((cnt - 1) / LPV) * NW + ((cnt - 1) % LPV) / NPAR + 1;
     }
 
-    __device__ __forceinline__ static uint64_t round_or(const uint64_t* __restrict__ fr, const int (&cid)[CH],
+    __device__ __forceinline__ static uint64_t round_or(__amdgpu_buffer_rsrc_t fr, const int (&cid)[CH],
                                                         const uint32_t (&msk)[CH], int k, int sub, int gbase,
-                                                        bool skip, int cnt, const uint64_t* zero) {
+                                                        bool skip, int cnt) {
         uint64_t x = 0;
         const int need = steps_needed(cnt);
 #pragma unroll
@@ -284,8 +304,8 @@ struct Gather {
                 const int w = __shfl(cid[h], gbase + j, 64);
                 const uint32_t m = static_cast<uint32_t>(__shfl(static_cast<int>(msk[h]), gbase + j, 64));
                 const bool ok = ((m >> k) & 1u) && !skip;
-                const uint64_t* src = ok ? fr + static_cast<size_t>(w) * NW + k : zero;
-                v[q] = *src;
+                const uint32_t off = ok ? static_cast<uint32_t>(w) * (NW * 8u) + static_cast<uint32_t>(k) * 8u : kNoWord;
+                v[q] = buf_word(fr, off);
             }
 #pragma unroll
             for (int q = 0; q < K; ++q) x |= v[q];
@@ -598,6 +618,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                 }
             } else {
                 // ---- bottom-up over all segments
+                const __amdgpu_buffer_rsrc_t fr_rsrc = words_rsrc(fr, static_cast<uint32_t>(n) * (NW * 8u));
                 long long s = gid;
                 const int4 kNone = make_int4(0, 0, 0, 0);
                 SegPre<NW> cur, nxt;
@@ -630,15 +651,15 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                     uint64_t acc = 0;
                     if (need) {
                         vis_v = a.vis[base];
-                        acc = Gather<NW>::round_or(fr, cur.cid, cur.fl, k, sub, gbase, vis_v == ~0ull,
-                                                   cur.sg.z - cur.sg.y, g_zero_words);
+                        acc = Gather<NW>::round_or(fr_rsrc, cur.cid, cur.fl, k, sub, gbase, vis_v == ~0ull,
+                                                   cur.sg.z - cur.sg.y);
                         for (int c = cur.sg.y + Gather<NW>::ROUND; c < cur.sg.z; c += Gather<NW>::ROUND) {
                             int cid[Gather<NW>::CH];
                             uint32_t msk[Gather<NW>::CH];
                             Gather<NW>::load_ids(a.col_idx, c, cur.sg.z, gl, cid);
                             Gather<NW>::load_masks(flag_fr, cid, msk);
-                            acc |= Gather<NW>::round_or(fr, cid, msk, k, sub, gbase, (vis_v | acc) == ~0ull,
-                                                        cur.sg.z - c, g_zero_words);
+                            acc |= Gather<NW>::round_or(fr_rsrc, cid, msk, k, sub, gbase, (vis_v | acc) == ~0ull,
+                                                        cur.sg.z - c);
                         }
                     }
 #pragma unroll
@@ -935,6 +956,9 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
     if (opts && (opts->direction < 0 || opts->direction > 2)) return fail(HLN_EINVAL, "bad direction %d", opts->direction);
     const int nw = width_words(opts);
     if (nw == 0) return fail(HLN_EINVAL, "width_bits must be 64, 128, 256, 512, 1024 or 2048");
+    if (static_cast<long long>(g->n) * nw * 8 >= (1LL << 31))
+        return fail(HLN_EUNSUPPORTED, "n * width_bits / 8 must be below 2^31 bytes (n = %d, width %d): use a narrower width",
+                    g->n, nw * 64);
     if (!workspace) return fail(HLN_EINVAL, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(workspace) % hln::Arena::kAlign) return fail(HLN_EINVAL, "workspace not 256-byte aligned");
     const hln::DeviceInfo* di = hln::device_info();
