@@ -114,7 +114,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--width", type=int, default=None,
-                    help="sources per BFS batch (default 2048; 512 for cfg4, as that workload specifies)")
+                    help="sources per BFS batch (default 4096; 512 for cfg4, as that workload specifies)")
     ap.add_argument("--direction", type=int, default=0, choices=[0, 1, 2],
                     help="BFS level direction: 0 automatic, 1 top-down only, 2 bottom-up only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -146,7 +146,7 @@ def main():
         run_cfg4(args)
         return
     if args.width is None:
-        args.width = 2048
+        args.width = 4096
     if args.workload == "cfg5":
         run_cfg5(args)
         return

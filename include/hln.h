@@ -59,7 +59,8 @@ typedef struct {
 
 /* Source-batch width and traversal direction of the bit-parallel BFS. */
 typedef struct {
-    int32_t width_bits;   /* sources per batch: 64, 128, 256, 512, 1024 or 2048; 0 = library default (512) */
+    int32_t width_bits;   /* sources per batch: 64, 128, 256, 512, 1024, 2048 or 4096; 0 = library default
+                             (512); n * width_bits / 8 must be below 2^31 (HLN_EUNSUPPORTED otherwise) */
     int32_t direction;    /* 0 = automatic per level, 1 = top-down only, 2 = bottom-up only */
     int32_t flags;        /* reserved, must be 0 */
     int32_t* levels;      /* [dev] nullable: per batch of width_bits sources, the BFS levels run
@@ -173,15 +174,19 @@ hln_status hln_compose_cc_topk(int32_t mode, int32_t n, int32_t r, const int64_t
  * pinned staging for the per-call descriptors, and optionally one captured
  * hipGraph of a whole batch.  Plans are not thread-safe; destroy with
  * hln_plan_destroy (waits for its staging copies).
- * Graphs: n in [1, 65535] (tile graphs keep frontier and next bitsets of the
- * whole graph in LDS); larger graphs use hln_closeness_layer.
+ * Graphs with n <= 65535 can run as LDS tiles (one workgroup keeps the
+ * frontier, next and visited bitsets of the whole graph in LDS); larger
+ * graphs, and graphs the tuner assigns to it, run through the persistent
+ * kernel of hln_closeness_layer inside the same call.
  * S[g], R[g], cc[g], h2[g]: host arrays of n_graphs device pointers (n_g
  * entries each); cc and h2 (arrays or entries) nullable.  Every source of
  * every graph is used; outputs as hln_closeness_layer's all-source mode.
  * hln_plan_tune times, for each log2(n) class present, the class's largest
- * graph with every source width whose bitsets fit in LDS (64/32/16/8) and
- * keeps the fastest; it synchronises `stream` and overwrites that graph's
- * S and R.  hln_plan_width reports the width a graph of n vertices gets.
+ * graph with every LDS tile width that fits (64/32/16/8 bits per vertex)
+ * and with the persistent kernel at 1024, 2048 and 4096 sources, and keeps
+ * the fastest; it synchronises `stream` and overwrites that graph's S and
+ * R.  hln_plan_width reports the width a graph of n vertices gets (untuned:
+ * the widest fitting tile, else 4096).
  * hln_plan_capture records the whole batch (staging copy, preparation,
  * tile launches, closeness pass) into a hipGraph owned by the plan, which
  * hln_plan_replay launches on `stream`; the captured buffers must stay

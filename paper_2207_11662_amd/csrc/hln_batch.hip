@@ -36,7 +36,7 @@
 
 struct hln_plan {
     int device = -1;
-    // tuned source width per log2(n) class: 8..64 = LDS tiles, 512..2048 =
+    // tuned source width per log2(n) class: 8..64 = LDS tiles, 512..4096 =
     // the persistent cooperative kernel (hln_closeness_layer); 0 = untuned
     int width_for_class[32];
     void* pinned = nullptr;         // staging for per-call descriptors
@@ -281,12 +281,12 @@ struct Layout {
 int cls_of(int w) { return w == 64 ? 0 : w == 32 ? 1 : w == 16 ? 2 : 3; }
 
 // Source width of a graph of n vertices: the tuned choice of its size class,
-// else the widest LDS tile that fits, else the cooperative kernel at 2048.
+// else the widest LDS tile that fits, else the cooperative kernel at 4096.
 int chosen_width(const hln_plan* plan, int n, size_t budget) {
     const int fit = widest_fit(n, budget);
     int w = plan ? plan->width_for_class[log2_class(n)] : 0;
     if (w >= 512) return w;
-    if (!fit) return 2048;
+    if (!fit) return 4096;
     if (w <= 0 || w > fit) w = fit;
     return w;
 }
@@ -294,7 +294,7 @@ int chosen_width(const hln_plan* plan, int n, size_t budget) {
 bool is_coop(int w) { return w >= 512; }
 
 // Workspace layout.  Sizes are worst cases over every width a graph could be
-// tuned to (tiles of 8 sources, the cooperative kernel at 2048), so the
+// tuned to (tiles of 8 sources, the cooperative kernel at 4096), so the
 // workspace size does not change when the plan is tuned.
 hln_status plan_layout(const hln_plan* plan, const hln_csr* graphs, int32_t n_graphs, Layout& L) {
     using hln::fail;
@@ -308,7 +308,7 @@ hln_status plan_layout(const hln_plan* plan, const hln_csr* graphs, int32_t n_gr
         const hln_csr& c = graphs[g];
         if (c.n < 1 || c.nnz < 0 || !c.row_ptr || (c.nnz > 0 && !c.col_idx))
             return fail(HLN_EINVAL, "graph %d: bad descriptor", g);
-        hln_opts o{2048, 0, 0, nullptr, nullptr, 0};
+        hln_opts o{4096, 0, 0, nullptr, nullptr, 0};
         L.coop_bytes = std::max(L.coop_bytes, hln_closeness_workspace_size(c.n, c.nnz, c.n, &o));
         if (widest_fit(c.n, budget)) {
             max_tiles += (c.n + 7) / 8;
@@ -630,12 +630,13 @@ hln_status hln_plan_tune(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs
         const int g = rep[c];
         const int fit = widest_fit(graphs[g].n, budget);
         float best = 1e30f;
-        int best_w = fit ? fit : 2048;
-        int cands[8];
+        int best_w = fit ? fit : 4096;
+        int cands[10];
         int nc = 0;
         for (int w = fit; w >= 8 && fit; w >>= 1) cands[nc++] = w;
         cands[nc++] = 1024;
         cands[nc++] = 2048;
+        cands[nc++] = 4096;
         for (int ci = 0; ci < nc && result == HLN_OK; ++ci) {
             const int w = cands[ci];
             plan->width_for_class[c] = w;

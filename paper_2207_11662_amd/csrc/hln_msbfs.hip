@@ -45,6 +45,7 @@
 #include "hln_internal.hpp"
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdio>
 #include <cstdlib>
 
@@ -76,6 +77,22 @@ __device__ __forceinline__ uint64_t buf_word(__amdgpu_buffer_rsrc_t r, uint32_t 
     return (static_cast<uint64_t>(v.y) << 32) | v.x;
 }
 
+// Word masks of a frontier buffer: bit k set when word k of a vertex may be
+// nonzero (32-bit for up to 32 words, 64-bit for 64).
+template <int NW>
+using MaskT = typename std::conditional<(NW > 32), unsigned long long, uint32_t>::type;
+
+template <class M>
+__device__ __forceinline__ M shfl_mask(M x, int lane) {
+    if constexpr (sizeof(M) == 8) {
+        const int lo = __shfl(static_cast<int>(static_cast<uint32_t>(x)), lane, 64);
+        const int hi = __shfl(static_cast<int>(static_cast<uint32_t>(x >> 32)), lane, 64);
+        return (static_cast<M>(static_cast<uint32_t>(hi)) << 32) | static_cast<uint32_t>(lo);
+    } else {
+        return static_cast<M>(__shfl(static_cast<int>(x), lane, 64));
+    }
+}
+
 // lanes per group (one segment at a time): 8, or NW when NW > 8
 template <int NW>
 constexpr int lpv() { return NW > 8 ? NW : 8; }
@@ -105,8 +122,8 @@ struct BfsArgs {
     const int32_t* sources;           // nullptr: all vertices, per-vertex accumulation
     uint64_t* bufA;                   // n*NW
     uint64_t* bufB;                   // n*NW
-    uint32_t* flagA;                  // n word masks: bit k clear implies bufA word k of v is zero
-    uint32_t* flagB;                  // n: the same for bufB
+    void* flagA;                      // n word masks (MaskT<NW>): bit k clear implies bufA word k of v is zero
+    void* flagB;                      // n: the same for bufB
     uint64_t* vis;                    // n*NW
     uint64_t* hacc;                   // n*NW partial ORs of multi-segment rows (kept zero)
     int32_t* hcnt;                    // n finished-segment counters (kept zero)
@@ -206,15 +223,16 @@ __device__ __forceinline__ int trace_add(int64_t* row, int verts, long long pair
 // (sub, k) holds word k; only sub == 0 lanes write).  Returns the number of
 // new bits and the number of words holding them.
 template <int NW, bool PER_SOURCE>
-__device__ __forceinline__ int2 finalize_vertex(const BfsArgs& a, uint64_t* nx, uint32_t* flag_nx, int v, int d, int k,
+__device__ __forceinline__ int2 finalize_vertex(const BfsArgs& a, uint64_t* nx, MaskT<NW>* flag_nx, int v, int d, int k,
                                                int sub, int gl, int gbase, uint64_t acc, uint64_t vis_v,
-                                               int32_t* s_cnt, int64_t s_old, int32_t r_old, uint32_t flag_old) {
+                                               int32_t* s_cnt, int64_t s_old, int32_t r_old, MaskT<NW> flag_old) {
+    using Mask = MaskT<NW>;
     constexpr int LPV = lpv<NW>();
-    constexpr uint32_t kWordMask = NW >= 32 ? 0xffffffffu : ((1u << NW) - 1u);
+    constexpr Mask kWordMask = NW >= 64 ? ~0ull : (NW == 32 ? 0xffffffffu : static_cast<Mask>((1ull << NW) - 1ull));
     const size_t base = static_cast<size_t>(v) * NW + k;
     const uint64_t nw = acc & ~vis_v;
     // lanes with sub == 0 hold word k at group lane k
-    const uint32_t nmask = static_cast<uint32_t>((__ballot(sub == 0 && nw != 0) >> gbase) & kWordMask);
+    const Mask nmask = static_cast<Mask>((__ballot(sub == 0 && nw != 0) >> gbase) & kWordMask);
     int c = sub == 0 ? __popcll(nw) : 0;
 #pragma unroll
     for (int off = 1; off < LPV; off <<= 1) c += shfl_xor_i32(c, off);
@@ -242,7 +260,7 @@ __device__ __forceinline__ int2 finalize_vertex(const BfsArgs& a, uint64_t* nx, 
             if (d == 2 && a.H2) a.H2[v] += c;
         }
     }
-    return make_int2(c, __popc(nmask));
+    return make_int2(c, __popcll(static_cast<unsigned long long>(nmask)));
 }
 
 // Gathering the frontier over a segment [lo, hi) for the word k of this
@@ -264,8 +282,9 @@ struct Gather {
     }
 
     // word masks of the neighbours' frontier slots (0 for no neighbour)
-    __device__ __forceinline__ static void load_masks(const uint32_t* __restrict__ flag_fr, const int (&cid)[CH],
-                                                      uint32_t (&msk)[CH]) {
+    using Mask = MaskT<NW>;
+    __device__ __forceinline__ static void load_masks(const Mask* __restrict__ flag_fr, const int (&cid)[CH],
+                                                      Mask (&msk)[CH]) {
 #pragma unroll
         for (int h = 0; h < CH; ++h) msk[h] = cid[h] >= 0 ? flag_fr[cid[h]] : 0u;
     }
@@ -288,7 +307,7 @@ struct Gather {
     }
 
     __device__ __forceinline__ static uint64_t round_or(__amdgpu_buffer_rsrc_t fr, const int (&cid)[CH],
-                                                        const uint32_t (&msk)[CH], int k, int sub, int gbase,
+                                                        const Mask (&msk)[CH], int k, int sub, int gbase,
                                                         bool skip, int cnt) {
         uint64_t x = 0;
         const int need = steps_needed(cnt);
@@ -302,7 +321,7 @@ struct Gather {
                 const int t = (q0 + q) % NW;
                 const int j = t * NPAR + sub;
                 const int w = __shfl(cid[h], gbase + j, 64);
-                const uint32_t m = static_cast<uint32_t>(__shfl(static_cast<int>(msk[h]), gbase + j, 64));
+                const Mask m = shfl_mask(msk[h], gbase + j);
                 const bool ok = ((m >> k) & 1u) && !skip;
                 const uint32_t off = ok ? static_cast<uint32_t>(w) * (NW * 8u) + static_cast<uint32_t>(k) * 8u : kNoWord;
                 v[q] = buf_word(fr, off);
@@ -324,14 +343,14 @@ template <int NW>
 struct SegPre {
     int4 sg;
     int cid[Gather<NW>::CH];
-    uint32_t fl[Gather<NW>::CH]; // frontier word masks of the neighbours in cid
+    MaskT<NW> fl[Gather<NW>::CH]; // frontier word masks of the neighbours in cid
     int64_t s_old;
     int32_t r_old;
-    uint32_t flag_old;           // word mask of the vertex's next-frontier slot
+    MaskT<NW> flag_old;          // word mask of the vertex's next-frontier slot
 };
 
 template <int NW, bool PER_SOURCE>
-__device__ __forceinline__ void seg_prefetch(const BfsArgs& a, const uint32_t* flag_nx, const int4 sg, bool valid,
+__device__ __forceinline__ void seg_prefetch(const BfsArgs& a, const MaskT<NW>* flag_nx, const int4 sg, bool valid,
                                              int gl, SegPre<NW>& p) {
     p.sg = sg;
     p.s_old = 0;
@@ -352,7 +371,7 @@ __device__ __forceinline__ void seg_prefetch(const BfsArgs& a, const uint32_t* f
 }
 
 template <int NW>
-__device__ __forceinline__ void seg_flags(const uint32_t* __restrict__ flag_fr, SegPre<NW>& p) {
+__device__ __forceinline__ void seg_flags(const MaskT<NW>* __restrict__ flag_fr, SegPre<NW>& p) {
     Gather<NW>::load_masks(flag_fr, p.cid, p.fl);
 }
 
@@ -360,6 +379,7 @@ template <int NW, int BLOCK, bool PER_SOURCE>
 __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
     constexpr int kLpv = lpv<NW>();
     constexpr int W = 64 * NW;
+    using Mask = MaskT<NW>;
     const int n = a.n;
     const int lane = threadIdx.x & 63;
     const int gl = lane & (kLpv - 1);
@@ -423,8 +443,8 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
         a.bufB[i] = 0;
     }
     for (long long v = tid; v < n; v += nthreads) {
-        a.flagA[v] = 0;
-        a.flagB[v] = 0;
+        static_cast<Mask*>(a.flagA)[v] = 0;
+        static_cast<Mask*>(a.flagB)[v] = 0;
     }
     __syncthreads();
     if (threadIdx.x < kClasses && s_bins[threadIdx.x]) atomicAdd(&ctrl->bins[threadIdx.x], s_bins[threadIdx.x]);
@@ -490,7 +510,8 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                     a.bufA[i] = w0;
                 }
                 for (long long v = tid; v < n; v += nthreads)
-                    a.flagA[v] = (v >= src0 && v < src0 + cnt) ? (1u << ((v - src0) >> 6)) : 0u;
+                    static_cast<Mask*>(a.flagA)[v] =
+                        (v >= src0 && v < src0 + cnt) ? static_cast<Mask>(static_cast<Mask>(1) << ((v - src0) >> 6)) : Mask(0);
                 for (long long i = tid_x; i < cnt; i += nthreads) {
                     const int3 sg = vertex_segments(a, static_cast<int>(src0 + i));
                     if (sg.y > 0) frontier_note(s_fr, par, sg.x, sg.y, sg.z);
@@ -500,7 +521,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                     a.vis[i] = 0;
                     a.bufA[i] = 0;
                 }
-                for (long long v = tid; v < n; v += nthreads) a.flagA[v] = 0;
+                for (long long v = tid; v < n; v += nthreads) static_cast<Mask*>(a.flagA)[v] = 0;
                 for (int i = threadIdx.x; i < W; i += BLOCK) {
                     s_cnt[i] = 0;
                     s_S[i] = 0;
@@ -514,7 +535,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                     atomicOr(reinterpret_cast<unsigned long long*>(&a.bufA[w]), 1ull << (i & 63));
                     // the first source bit on a vertex lists it (once, even if
                     // the vertex is listed as a source more than once)
-                    if (atomicOr(&a.flagA[s], 1u << (i >> 6)) == 0u) {
+                    if (atomicOr(&static_cast<Mask*>(a.flagA)[s], static_cast<Mask>(static_cast<Mask>(1) << (i >> 6))) == 0) {
                         const int3 sg = vertex_segments(a, s);
                         if (sg.y > 0) frontier_note(s_fr, par, sg.x, sg.y, sg.z);
                     }
@@ -531,8 +552,8 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
         // vertex got a new bit, which ends this batch's BFS
         uint64_t* fr = a.bufA;
         uint64_t* nx = a.bufB;
-        uint32_t* flag_fr = a.flagA;
-        uint32_t* flag_nx = a.flagB;
+        Mask* flag_fr = static_cast<Mask*>(a.flagA);
+        Mask* flag_nx = static_cast<Mask*>(a.flagB);
         for (int d = 1;; ++d) {
             const int par = phase & 1;                   // this phase's list; the previous one is par ^ 1
             if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -552,7 +573,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                 for (int i = static_cast<int>(threadIdx.x) / kLpv; i < flen; i += BLOCK / kLpv) {
                     const int4 sg = a.seg[s_fr.fl[par ^ 1][i]];
                     const int u = sg.x;
-                    const uint32_t fm = flag_fr[u];
+                    const Mask fm = flag_fr[u];
                     const uint64_t x = ((fm >> k) & 1u) ? fr[static_cast<size_t>(u) * NW + k] : 0ull;
                     for (int c = sg.y; c < sg.z; c += kLpv) {
                         const int wl = (c + gl < sg.z) ? a.col_idx[c + gl] : -1;
@@ -573,7 +594,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                 for (long long v0 = gid_x * kLpv; v0 < n; v0 += ngroups * kLpv) {
                     const long long vl = v0 + gl;
                     int touched = 0;
-                    uint32_t fo = 0;
+                    Mask fo = 0;
                     if (vl < n) {
                         touched = load_agent_i32(&a.hcnt[vl]);
                         fo = flag_nx[vl];
@@ -584,7 +605,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                         ball &= ball - 1;
                         const int v = static_cast<int>(v0 + j);
                         const int tj = __shfl(touched, gbase + j, 64);
-                        const uint32_t foj = static_cast<uint32_t>(__shfl(static_cast<int>(fo), gbase + j, 64));
+                        const Mask foj = shfl_mask(fo, gbase + j);
                         const size_t base = static_cast<size_t>(v) * NW + k;
                         uint64_t acc = 0, vis_v = 0;
                         int64_t s_old = 0;
@@ -655,7 +676,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                                                    cur.sg.z - cur.sg.y);
                         for (int c = cur.sg.y + Gather<NW>::ROUND; c < cur.sg.z; c += Gather<NW>::ROUND) {
                             int cid[Gather<NW>::CH];
-                            uint32_t msk[Gather<NW>::CH];
+                            Mask msk[Gather<NW>::CH];
                             Gather<NW>::load_ids(a.col_idx, c, cur.sg.z, gl, cid);
                             Gather<NW>::load_masks(flag_fr, cid, msk);
                             acc |= Gather<NW>::round_or(fr_rsrc, cid, msk, k, sub, gbase, (vis_v | acc) == ~0ull,
@@ -698,7 +719,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                             for (int off = NW; off < kLpv; off <<= 1) full |= shfl_xor_u64(full, off);
                             int64_t s_old = 0;
                             int32_t r_old = 0;
-                            const uint32_t flag_old = flag_nx[v];
+                            const Mask flag_old = flag_nx[v];
                             if (gl == 0) {
                                 store_agent_i32(&a.hcnt[v], 0);
                                 if (!PER_SOURCE) {
@@ -766,7 +787,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
             uint64_t* t = fr;
             fr = nx;
             nx = t;
-            uint32_t* tf = flag_fr;
+            Mask* tf = flag_fr;
             flag_fr = flag_nx;
             flag_nx = tf;
         }
@@ -903,6 +924,7 @@ int width_words(const hln_opts* o) {
         case 512: return 8;
         case 1024: return 16;
         case 2048: return 32;
+        case 4096: return 64;
         default: return 0;
     }
 }
@@ -917,7 +939,7 @@ size_t workspace_bytes(int32_t n, int64_t nnz, int nw, int grid_cap) {
     b += Arena::round(sizeof(Ctrl));
     b += Arena::round(hln::dev::kBarrierWords * sizeof(unsigned long long));
     b += 4 * Arena::round(words * sizeof(uint64_t));            // A, B, vis, hacc
-    b += 2 * Arena::round(static_cast<size_t>(n) * 4);          // word masks of A, B
+    b += 2 * Arena::round(static_cast<size_t>(n) * 8);          // word masks of A, B
     b += 2 * Arena::round(static_cast<size_t>(n) * sizeof(int32_t)); // hcnt, seg_first
     b += Arena::round(seg_cap * sizeof(int4));
     b += Arena::round(static_cast<size_t>(grid_cap) * 2 * 64 * nw * sizeof(int64_t));  // per-source partials
@@ -955,7 +977,7 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
     if (opts && opts->flags != 0) return fail(HLN_EINVAL, "opts->flags must be 0");
     if (opts && (opts->direction < 0 || opts->direction > 2)) return fail(HLN_EINVAL, "bad direction %d", opts->direction);
     const int nw = width_words(opts);
-    if (nw == 0) return fail(HLN_EINVAL, "width_bits must be 64, 128, 256, 512, 1024 or 2048");
+    if (nw == 0) return fail(HLN_EINVAL, "width_bits must be 64, 128, 256, 512, 1024, 2048 or 4096");
     if (static_cast<long long>(g->n) * nw * 8 >= (1LL << 31))
         return fail(HLN_EUNSUPPORTED, "n * width_bits / 8 must be below 2^31 bytes (n = %d, width %d): use a narrower width",
                     g->n, nw * 64);
@@ -986,8 +1008,8 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
     a.bufB = ar.take<uint64_t>(words);
     a.vis = ar.take<uint64_t>(words);
     a.hacc = ar.take<uint64_t>(words);
-    a.flagA = ar.take<uint32_t>(n);
-    a.flagB = ar.take<uint32_t>(n);
+    a.flagA = ar.take<uint64_t>(n);
+    a.flagB = ar.take<uint64_t>(n);
     a.hcnt = ar.take<int32_t>(n);
     a.seg_cap = static_cast<long long>(n) + g->nnz / kSegLen + 1;
     a.seg = ar.take<int4>(static_cast<size_t>(a.seg_cap));
@@ -1023,6 +1045,7 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
         case 8: return dispatch_block<8>(a, ps, want_threads, grid_cap, di->cus, st);
         case 16: return dispatch_block<16>(a, ps, want_threads, grid_cap, di->cus, st);
         case 32: return dispatch_block<32>(a, ps, want_threads, grid_cap, di->cus, st);
+        case 64: return dispatch_block<64>(a, ps, want_threads, grid_cap, di->cus, st);
         default: return fail(HLN_EINVAL, "unsupported width");
     }
 }

@@ -100,7 +100,7 @@ class Query:
     features -> MLP scores -> top `n_cand` -> exact per-source BFS on the
     AND graph -> top `k` by exact closeness."""
 
-    def __init__(self, g_and: L.Graph, n_cand: int, k: int, width_bits: int = 2048):
+    def __init__(self, g_and: L.Graph, n_cand: int, k: int, width_bits: int = 4096):
         dev = g_and.row_ptr.device
         n = g_and.n
         self.g, self.n_cand, self.k, self.width = g_and, n_cand, k, width_bits

@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 P = pytest.importorskip("paper_2207_11662_amd")
 
-WIDTHS = [64, 128, 256, 512, 1024, 2048]
+WIDTHS = [64, 128, 256, 512, 1024, 2048, 4096]
 
 
 def run_all(rp, ci, width, want_h2=True, direction=0):
@@ -145,7 +145,7 @@ def test_config2_full_size_sampled():
         assert np.array_equal(got["R"], sizes[lab])
 
 
-@pytest.mark.parametrize("width", [64, 512, 2048])
+@pytest.mark.parametrize("width", [64, 512, 2048, 4096])
 def test_levels_per_batch(width):
     """The kernel's per-batch level count is 1 + the largest eccentricity of
     the batch's sources (the L_b of the byte model), from the oracle."""
@@ -162,7 +162,7 @@ def test_levels_per_batch(width):
         assert lv.cpu().numpy().tolist() == ref
 
 
-@pytest.mark.parametrize("width", [64, 256, 2048])
+@pytest.mark.parametrize("width", [64, 256, 2048, 4096])
 @pytest.mark.parametrize("direction", [1, 2], ids=["top_down", "bottom_up"])
 def test_forced_direction(direction, width):
     """Every level top-down (push) or every level bottom-up (pull)."""
