@@ -225,7 +225,7 @@ __device__ __forceinline__ int trace_add(int64_t* row, int verts, long long pair
 template <int NW, bool PER_SOURCE>
 __device__ __forceinline__ int2 finalize_vertex(const BfsArgs& a, uint64_t* nx, MaskT<NW>* flag_nx, int v, int d, int k,
                                                int sub, int gl, int gbase, uint64_t acc, uint64_t vis_v,
-                                               int32_t* s_cnt, int64_t s_old, int32_t r_old, MaskT<NW> flag_old) {
+                                               int32_t* s_cnt, MaskT<NW> flag_old) {
     using Mask = MaskT<NW>;
     constexpr int LPV = lpv<NW>();
     constexpr Mask kWordMask = NW >= 64 ? ~0ull : (NW == 32 ? 0xffffffffu : static_cast<Mask>((1ull << NW) - 1ull));
@@ -255,9 +255,14 @@ __device__ __forceinline__ int2 finalize_vertex(const BfsArgs& a, uint64_t* nx, 
     if (gl == 0) {
         if (nmask != flag_old) flag_nx[v] = nmask;
         if (!PER_SOURCE && c) {
-            a.S[v] = s_old + static_cast<int64_t>(d) * c;
-            a.R[v] = r_old + c;
-            if (d == 2 && a.H2) a.H2[v] += c;
+            // one finaliser per vertex and level: plain read-modify-write
+            // would need the old values in flight; non-returning atomic adds
+            // need nothing
+            __hip_atomic_fetch_add(reinterpret_cast<unsigned long long*>(&a.S[v]),
+                                   static_cast<unsigned long long>(static_cast<int64_t>(d) * c), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&a.R[v], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (d == 2 && a.H2) __hip_atomic_fetch_add(&a.H2[v], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
     return make_int2(c, __popcll(static_cast<unsigned long long>(nmask)));
@@ -306,28 +311,63 @@ struct Gather {
         return ((cnt - 1) / LPV) * NW + ((cnt - 1) % LPV) / NPAR + 1;
     }
 
+    static constexpr int K0 = K;                         // the first chunk (issued with the visited word)
+
+    // one chunk of KK gathers, starting at step q0, into v[] (no wait)
+    template <int KK>
+    __device__ __forceinline__ static void issue_chunk(__amdgpu_buffer_rsrc_t fr, const int (&cid)[CH],
+                                                       const Mask (&msk)[CH], int k, int sub, int gbase, bool skip,
+                                                       int need, int q0, uint64_t (&v)[KK]) {
+#pragma unroll
+        for (int q = 0; q < KK; ++q) {
+            const int h = (q0 + q) / NW;
+            const int t = (q0 + q) % NW;
+            const int j = t * NPAR + sub;
+            const int w = __shfl(cid[h], gbase + j, 64);
+            const Mask m = shfl_mask(msk[h], gbase + j);
+            const bool ok = ((m >> k) & 1u) && !skip && (q0 + q) < need;
+            const uint32_t off = ok ? static_cast<uint32_t>(w) * (NW * 8u) + static_cast<uint32_t>(k) * 8u : kNoWord;
+            v[q] = buf_word(fr, off);
+        }
+    }
+
+    template <int KK>
+    __device__ __forceinline__ static uint64_t or_all(const uint64_t (&v)[KK]) {
+        uint64_t x = 0;
+#pragma unroll
+        for (int q = 0; q < KK; ++q) x |= v[q];
+        return x;
+    }
+
+    // the chunks after the first (steps K0 ...); skip as in round_or, from
+    // the OR so far
+    __device__ __forceinline__ static uint64_t rest_or(__amdgpu_buffer_rsrc_t fr, const int (&cid)[CH],
+                                                       const Mask (&msk)[CH], int k, int sub, int gbase,
+                                                       uint64_t vis_or_acc, int need) {
+        uint64_t x = 0;
+#pragma unroll
+        for (int q0 = K0; q0 < T; q0 += K) {
+            if (!__any(q0 < need)) break;
+            uint64_t v[K];
+            issue_chunk<K>(fr, cid, msk, k, sub, gbase, (vis_or_acc | x) == ~0ull, need, q0, v);
+            x |= or_all<K>(v);
+        }
+        return x;
+    }
+
+    // skip: no gather at all in this round; later chunks also stop once
+    // prior | OR so far is all ones
     __device__ __forceinline__ static uint64_t round_or(__amdgpu_buffer_rsrc_t fr, const int (&cid)[CH],
                                                         const Mask (&msk)[CH], int k, int sub, int gbase,
-                                                        bool skip, int cnt) {
-        uint64_t x = 0;
+                                                        bool skip, int cnt, uint64_t prior) {
         const int need = steps_needed(cnt);
+        uint64_t x = 0;
 #pragma unroll
         for (int q0 = 0; q0 < T; q0 += K) {
             if (!__any(q0 < need)) break;
             uint64_t v[K];
-#pragma unroll
-            for (int q = 0; q < K; ++q) {
-                const int h = (q0 + q) / NW;
-                const int t = (q0 + q) % NW;
-                const int j = t * NPAR + sub;
-                const int w = __shfl(cid[h], gbase + j, 64);
-                const Mask m = shfl_mask(msk[h], gbase + j);
-                const bool ok = ((m >> k) & 1u) && !skip;
-                const uint32_t off = ok ? static_cast<uint32_t>(w) * (NW * 8u) + static_cast<uint32_t>(k) * 8u : kNoWord;
-                v[q] = buf_word(fr, off);
-            }
-#pragma unroll
-            for (int q = 0; q < K; ++q) x |= v[q];
+            issue_chunk<K>(fr, cid, msk, k, sub, gbase, skip || (q0 > 0 && (prior | x) == ~0ull), need, q0, v);
+            x |= or_all<K>(v);
         }
         return x;
     }
@@ -344,8 +384,6 @@ struct SegPre {
     int4 sg;
     int cid[Gather<NW>::CH];
     MaskT<NW> fl[Gather<NW>::CH]; // frontier word masks of the neighbours in cid
-    int64_t s_old;
-    int32_t r_old;
     MaskT<NW> flag_old;          // word mask of the vertex's next-frontier slot
 };
 
@@ -353,8 +391,6 @@ template <int NW, bool PER_SOURCE>
 __device__ __forceinline__ void seg_prefetch(const BfsArgs& a, const MaskT<NW>* flag_nx, const int4 sg, bool valid,
                                              int gl, SegPre<NW>& p) {
     p.sg = sg;
-    p.s_old = 0;
-    p.r_old = 0;
     p.flag_old = 0;
 #pragma unroll
     for (int h = 0; h < Gather<NW>::CH; ++h) {
@@ -364,10 +400,6 @@ __device__ __forceinline__ void seg_prefetch(const BfsArgs& a, const MaskT<NW>* 
     if (!valid) return;
     Gather<NW>::load_ids(a.col_idx, sg.y, sg.z, gl, p.cid);
     if (sg.w == 1) p.flag_old = flag_nx[sg.x];
-    if (!PER_SOURCE && gl == 0 && sg.w == 1) {
-        p.s_old = a.S[sg.x];
-        p.r_old = a.R[sg.x];
-    }
 }
 
 template <int NW>
@@ -608,24 +640,16 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                         const Mask foj = shfl_mask(fo, gbase + j);
                         const size_t base = static_cast<size_t>(v) * NW + k;
                         uint64_t acc = 0, vis_v = 0;
-                        int64_t s_old = 0;
-                        int32_t r_old = 0;
                         if (tj) {
                             if (sub == 0) {
                                 acc = __hip_atomic_exchange(reinterpret_cast<unsigned long long*>(&a.hacc[base]), 0ull,
                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                                 vis_v = a.vis[base];
                             }
-                            if (gl == 0) {
-                                store_agent_i32(&a.hcnt[v], 0);
-                                if (!PER_SOURCE) {
-                                    s_old = a.S[v];
-                                    r_old = a.R[v];
-                                }
-                            }
+                            if (gl == 0) store_agent_i32(&a.hcnt[v], 0);
                         }
                         const int2 cw = finalize_vertex<NW, PER_SOURCE>(a, nx, flag_nx, v, d, k, sub, gl, gbase, acc,
-                                                                        vis_v, s_cnt, s_old, r_old, foj);
+                                                                        vis_v, s_cnt, foj);
                         if (cw.x) {
                             any = 1;
                             t_pairs += cw.x;
@@ -671,23 +695,25 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                     uint64_t vis_v = 0;
                     uint64_t acc = 0;
                     if (need) {
+                        // the first chunk does not wait for the visited word (no
+                        // saturation test); later chunks and rounds use it
                         vis_v = a.vis[base];
-                        acc = Gather<NW>::round_or(fr_rsrc, cur.cid, cur.fl, k, sub, gbase, vis_v == ~0ull,
-                                                   cur.sg.z - cur.sg.y);
+                        acc = Gather<NW>::round_or(fr_rsrc, cur.cid, cur.fl, k, sub, gbase, false, cur.sg.z - cur.sg.y,
+                                                   vis_v);
                         for (int c = cur.sg.y + Gather<NW>::ROUND; c < cur.sg.z; c += Gather<NW>::ROUND) {
                             int cid[Gather<NW>::CH];
                             Mask msk[Gather<NW>::CH];
                             Gather<NW>::load_ids(a.col_idx, c, cur.sg.z, gl, cid);
                             Gather<NW>::load_masks(flag_fr, cid, msk);
                             acc |= Gather<NW>::round_or(fr_rsrc, cid, msk, k, sub, gbase, (vis_v | acc) == ~0ull,
-                                                        cur.sg.z - c);
+                                                        cur.sg.z - c, vis_v | acc);
                         }
                     }
 #pragma unroll
                     for (int off = NW; off < kLpv; off <<= 1) acc |= shfl_xor_u64(acc, off);
                     if (nseg == 1) {
                         const int2 cw = finalize_vertex<NW, PER_SOURCE>(a, nx, flag_nx, v, d, k, sub, gl, gbase, acc,
-                                                                        vis_v, s_cnt, cur.s_old, cur.r_old, cur.flag_old);
+                                                                        vis_v, s_cnt, cur.flag_old);
                         if (cw.x) {
                             any = 1;
                             t_pairs += cw.x;
@@ -717,18 +743,10 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
                             for (int off = NW; off < kLpv; off <<= 1) full |= shfl_xor_u64(full, off);
-                            int64_t s_old = 0;
-                            int32_t r_old = 0;
                             const Mask flag_old = flag_nx[v];
-                            if (gl == 0) {
-                                store_agent_i32(&a.hcnt[v], 0);
-                                if (!PER_SOURCE) {
-                                    s_old = a.S[v];
-                                    r_old = a.R[v];
-                                }
-                            }
+                            if (gl == 0) store_agent_i32(&a.hcnt[v], 0);
                             const int2 cw = finalize_vertex<NW, PER_SOURCE>(a, nx, flag_nx, v, d, k, sub, gl, gbase,
-                                                                            full, vis_v, s_cnt, s_old, r_old, flag_old);
+                                                                            full, vis_v, s_cnt, flag_old);
                             if (cw.x) {
                                 any = 1;
                                 t_pairs += cw.x;
