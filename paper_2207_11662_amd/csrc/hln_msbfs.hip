@@ -72,6 +72,14 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t words_rsrc(const uint64_t* p, 
                                              0x00020000);
 }
 
+// Per-lane select by a wave-wide lane mask (bit i of `lanes` picks lane i):
+// one v_cndmask with the mask in an SGPR pair.
+__device__ __forceinline__ uint32_t select_lanes(uint64_t lanes, uint32_t if_set, uint32_t if_clear) {
+    uint32_t r;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(if_clear), "v"(if_set), "s"(lanes));
+    return r;
+}
+
 __device__ __forceinline__ uint64_t buf_word(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     const hln_u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
     return (static_cast<uint64_t>(v.y) << 32) | v.x;
@@ -318,6 +326,25 @@ struct Gather {
     __device__ __forceinline__ static void issue_chunk(__amdgpu_buffer_rsrc_t fr, const int (&cid)[CH],
                                                        const Mask (&msk)[CH], int k, int sub, int gbase, bool skip,
                                                        int need, int q0, uint64_t (&v)[KK]) {
+        if constexpr (NW == 64) {
+            // one group is the whole wave, so step t's neighbour id and mask are
+            // wave-uniform: read them into scalar registers (no LDS round trip)
+            // and select each lane's word by the mask directly
+            const uint64_t allowed = __ballot(!skip);
+            const uint32_t koff = static_cast<uint32_t>(k) * 8u;
+            const int need_w = __builtin_amdgcn_readfirstlane(need);   // uniform: one group per wave
+#pragma unroll
+            for (int q = 0; q < KK; ++q) {
+                const int t = q0 + q;
+                const int w = __builtin_amdgcn_readlane(cid[0], t);
+                const uint32_t mlo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(msk[0])), t));
+                const uint32_t mhi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(msk[0] >> 32)), t));
+                const uint64_t lanes = t < need_w ? (((static_cast<uint64_t>(mhi) << 32) | mlo) & allowed) : 0ull;
+                const uint32_t rowoff = static_cast<uint32_t>(w < 0 ? 0 : w) * (NW * 8u);
+                v[q] = buf_word(fr, select_lanes(lanes, rowoff + koff, kNoWord));
+            }
+            return;
+        }
 #pragma unroll
         for (int q = 0; q < KK; ++q) {
             const int h = (q0 + q) / NW;
