@@ -72,6 +72,31 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t words_rsrc(const uint64_t* p, 
                                              0x00020000);
 }
 
+__device__ __forceinline__ uint32_t buf_u32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+
+__device__ __forceinline__ int4 buf_i4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    return make_int4(static_cast<int>(x.x), static_cast<int>(x.y), static_cast<int>(x.z), static_cast<int>(x.w));
+}
+
+__device__ __forceinline__ void buf_store_u64(uint64_t x, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    hln_u32x2 v;
+    v.x = static_cast<uint32_t>(x);
+    v.y = static_cast<uint32_t>(x >> 32);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+}
+
+__device__ __forceinline__ void buf_store_u32(uint32_t x, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b32(x, r, off, 0, 0);
+}
+
+__device__ __forceinline__ void buf_add_u32(uint32_t x, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    (void)__builtin_amdgcn_raw_ptr_buffer_atomic_add_i32(static_cast<int>(x), r, off, 0, 0);
+}
+
 // Per-lane select by a wave-wide lane mask (bit i of `lanes` picks lane i):
 // one v_cndmask with the mask in an SGPR pair.
 __device__ __forceinline__ uint32_t select_lanes(uint64_t lanes, uint32_t if_set, uint32_t if_clear) {
@@ -99,6 +124,18 @@ __device__ __forceinline__ M shfl_mask(M x, int lane) {
     } else {
         return static_cast<M>(__shfl(static_cast<int>(x), lane, 64));
     }
+}
+
+template <class M>
+__device__ __forceinline__ M buf_mask(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    if constexpr (sizeof(M) == 8) return buf_word(r, off);
+    else return buf_u32(r, off);
+}
+
+template <class M>
+__device__ __forceinline__ void buf_store_mask(M x, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    if constexpr (sizeof(M) == 8) buf_store_u64(x, r, off);
+    else buf_store_u32(x, r, off);
 }
 
 // lanes per group (one segment at a time): 8, or NW when NW > 8
@@ -141,6 +178,7 @@ struct BfsArgs {
     int32_t* seg_first;               // n: index of the vertex's first segment
     int64_t* part;                    // per-source mode: [grid][2][W] block partials
     int64_t* S;
+    uint32_t* S32;                    // n: this batch's distance sums (levels below kS32Levels), folded into S
     int32_t* R;
     int32_t* H2;
     double* cc;
@@ -154,6 +192,21 @@ struct BfsArgs {
     int32_t trace_cap;
     int32_t seg_len;                  // SEG
     int32_t alpha;                    // top-down when alpha * frontier arc-words < arcs of the graph
+    int32_t s32_levels;               // depth from which distance sums go to S with 64-bit atomics
+};
+
+// Levels from this depth on add to S directly (64-bit atomics): below it a
+// batch's sum per vertex is at most W * depth < 2^32.  (HLN_S32_LEVELS
+// lowers it, so that tests reach the 64-bit path on small graphs.)
+constexpr int kS32Levels = 1 << 18;
+
+// Buffer resources of one level.  Loads and stores of the pull loop and the
+// finaliser go through them with an out-of-range offset for lanes that need
+// no access: such a load reads zero and such a store or atomic is dropped,
+// so every instruction issues on every path and the loop's memory counter
+// waits stay exact (stores count in the same in-order counter as loads).
+struct LevelBufs {
+    __amdgpu_buffer_rsrc_t nx, vis, flag_nx, flag_fr, s32, r, h2, col, seg;
 };
 
 // A block's frontier lists in LDS, double-buffered by phase parity: the
@@ -231,47 +284,48 @@ __device__ __forceinline__ int trace_add(int64_t* row, int verts, long long pair
 // (sub, k) holds word k; only sub == 0 lanes write).  Returns the number of
 // new bits and the number of words holding them.
 template <int NW, bool PER_SOURCE>
-__device__ __forceinline__ int2 finalize_vertex(const BfsArgs& a, uint64_t* nx, MaskT<NW>* flag_nx, int v, int d, int k,
-                                               int sub, int gl, int gbase, uint64_t acc, uint64_t vis_v,
-                                               int32_t* s_cnt, MaskT<NW> flag_old) {
+__device__ __forceinline__ int2 finalize_vertex(const BfsArgs& a, const LevelBufs& B, int v, int d, int k, int sub,
+                                                int gl, int gbase, uint64_t acc, uint64_t vis_v, int32_t* s_cnt,
+                                                MaskT<NW> flag_old) {
     using Mask = MaskT<NW>;
     constexpr int LPV = lpv<NW>();
-    constexpr Mask kWordMask = NW >= 64 ? ~0ull : (NW == 32 ? 0xffffffffu : static_cast<Mask>((1ull << NW) - 1ull));
-    const size_t base = static_cast<size_t>(v) * NW + k;
+    constexpr Mask kWordMask = static_cast<Mask>(NW >= 64 ? ~0ull : ((1ull << (NW & 63)) - 1ull));
+    const uint32_t woff = (static_cast<uint32_t>(v) * NW + static_cast<uint32_t>(k)) * 8u;
     const uint64_t nw = acc & ~vis_v;
     // lanes with sub == 0 hold word k at group lane k
     const Mask nmask = static_cast<Mask>((__ballot(sub == 0 && nw != 0) >> gbase) & kWordMask);
     int c = sub == 0 ? __popcll(nw) : 0;
 #pragma unroll
     for (int off = 1; off < LPV; off <<= 1) c += shfl_xor_i32(c, off);
-    if (sub == 0) {
-        // new bits go to the next frontier; a word that held an older
-        // frontier and has nothing new is cleared; other words stay zero
-        if (nw != 0 || ((flag_old >> k) & 1u)) nx[base] = nw;
-        if (nw) {
-            a.vis[base] = vis_v | nw;
-            if (PER_SOURCE) {
-                uint64_t b = nw;
-                while (b) {
-                    const int bit = __ffsll(static_cast<long long>(b)) - 1;
-                    b &= b - 1;
-                    atomicAdd(&s_cnt[k * 64 + bit], 1);
-                }
-            }
+    // new bits go to the next frontier; a word that held an older frontier
+    // and has nothing new is cleared; other words stay zero
+    const bool st_nx = sub == 0 && (nw != 0 || ((flag_old >> k) & 1u));
+    buf_store_u64(nw, B.nx, st_nx ? woff : kNoWord);
+    buf_store_u64(vis_v | nw, B.vis, (sub == 0 && nw != 0) ? woff : kNoWord);
+    if (PER_SOURCE && sub == 0 && nw) {
+        uint64_t b = nw;
+        while (b) {
+            const int bit = __ffsll(static_cast<long long>(b)) - 1;
+            b &= b - 1;
+            atomicAdd(&s_cnt[k * 64 + bit], 1);
         }
     }
-    if (gl == 0) {
-        if (nmask != flag_old) flag_nx[v] = nmask;
-        if (!PER_SOURCE && c) {
-            // one finaliser per vertex and level: plain read-modify-write
-            // would need the old values in flight; non-returning atomic adds
-            // need nothing
+    const uint32_t voff = static_cast<uint32_t>(v);
+    buf_store_mask<Mask>(nmask, B.flag_nx, (gl == 0 && nmask != flag_old) ? voff * static_cast<uint32_t>(sizeof(Mask))
+                                                                          : kNoWord);
+    if (!PER_SOURCE) {
+        // one finaliser per vertex and level: non-returning adds need no old
+        // values in flight
+        const uint32_t aoff = (gl == 0 && c != 0) ? voff * 4u : kNoWord;
+        if (d < a.s32_levels) {
+            buf_add_u32(static_cast<uint32_t>(d) * static_cast<uint32_t>(c), B.s32, aoff);
+        } else if (gl == 0 && c != 0) {
             __hip_atomic_fetch_add(reinterpret_cast<unsigned long long*>(&a.S[v]),
                                    static_cast<unsigned long long>(static_cast<int64_t>(d) * c), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&a.R[v], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (d == 2 && a.H2) __hip_atomic_fetch_add(&a.H2[v], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+        buf_add_u32(static_cast<uint32_t>(c), B.r, aoff);
+        if (d == 2 && a.H2) buf_add_u32(static_cast<uint32_t>(c), B.h2, aoff);
     }
     return make_int2(c, __popcll(static_cast<unsigned long long>(nmask)));
 }
@@ -288,18 +342,24 @@ struct Gather {
     static constexpr int CH = NW >= 16 ? 1 : 2;     // chunks of LPV arcs per round
     static constexpr int ROUND = CH * LPV;
 
-    __device__ __forceinline__ static void load_ids(const int32_t* __restrict__ col_idx, int c, int hi, int gl,
+    __device__ __forceinline__ static void load_ids(__amdgpu_buffer_rsrc_t col, int c, int hi, int gl,
                                                     int (&cid)[CH]) {
 #pragma unroll
-        for (int h = 0; h < CH; ++h) cid[h] = (c + h * LPV + gl < hi) ? col_idx[c + h * LPV + gl] : -1;
+        for (int h = 0; h < CH; ++h) {
+            const int e = c + h * LPV + gl;
+            const uint32_t x = buf_u32(col, e < hi ? static_cast<uint32_t>(e) * 4u : kNoWord);
+            cid[h] = e < hi ? static_cast<int>(x) : -1;
+        }
     }
 
     // word masks of the neighbours' frontier slots (0 for no neighbour)
     using Mask = MaskT<NW>;
-    __device__ __forceinline__ static void load_masks(const Mask* __restrict__ flag_fr, const int (&cid)[CH],
+    __device__ __forceinline__ static void load_masks(__amdgpu_buffer_rsrc_t flag_fr, const int (&cid)[CH],
                                                       Mask (&msk)[CH]) {
 #pragma unroll
-        for (int h = 0; h < CH; ++h) msk[h] = cid[h] >= 0 ? flag_fr[cid[h]] : 0u;
+        for (int h = 0; h < CH; ++h)
+            msk[h] = buf_mask<Mask>(flag_fr, cid[h] >= 0 ? static_cast<uint32_t>(cid[h]) * static_cast<uint32_t>(sizeof(Mask))
+                                                         : kNoWord);
     }
 
     // Gathers go out in wave-uniform chunks of K with no branch inside a
@@ -415,23 +475,36 @@ struct SegPre {
 };
 
 template <int NW, bool PER_SOURCE>
-__device__ __forceinline__ void seg_prefetch(const BfsArgs& a, const MaskT<NW>* flag_nx, const int4 sg, bool valid,
-                                             int gl, SegPre<NW>& p) {
+__device__ __forceinline__ void seg_prefetch(const LevelBufs& B, const int4 sg, bool valid, int gl, SegPre<NW>& p) {
+    using Mask = MaskT<NW>;
     p.sg = sg;
-    p.flag_old = 0;
+    Gather<NW>::load_ids(B.col, sg.y, valid ? sg.z : sg.y, gl, p.cid);
+    p.flag_old = buf_mask<Mask>(B.flag_nx, (valid && sg.w == 1) ? static_cast<uint32_t>(sg.x) * static_cast<uint32_t>(sizeof(Mask))
+                                                              : kNoWord);
 #pragma unroll
-    for (int h = 0; h < Gather<NW>::CH; ++h) {
-        p.cid[h] = -1;
-        p.fl[h] = 0;
-    }
-    if (!valid) return;
-    Gather<NW>::load_ids(a.col_idx, sg.y, sg.z, gl, p.cid);
-    if (sg.w == 1) p.flag_old = flag_nx[sg.x];
+    for (int h = 0; h < Gather<NW>::CH; ++h) p.fl[h] = 0;
 }
 
 template <int NW>
-__device__ __forceinline__ void seg_flags(const MaskT<NW>* __restrict__ flag_fr, SegPre<NW>& p) {
-    Gather<NW>::load_masks(flag_fr, p.cid, p.fl);
+__device__ __forceinline__ void seg_flags(const LevelBufs& B, SegPre<NW>& p) {
+    Gather<NW>::load_masks(B.flag_fr, p.cid, p.fl);
+}
+
+template <int NW>
+__device__ __forceinline__ LevelBufs level_bufs(const BfsArgs& a, const uint64_t* nx, const MaskT<NW>* flag_nx,
+                                                const MaskT<NW>* flag_fr) {
+    const uint32_t n = static_cast<uint32_t>(a.n);
+    LevelBufs B;
+    B.nx = words_rsrc(nx, n * (NW * 8u));
+    B.vis = words_rsrc(a.vis, n * (NW * 8u));
+    B.flag_nx = __builtin_amdgcn_make_buffer_rsrc(const_cast<MaskT<NW>*>(flag_nx), 0, static_cast<int>(n * sizeof(MaskT<NW>)), 0x00020000);
+    B.flag_fr = __builtin_amdgcn_make_buffer_rsrc(const_cast<MaskT<NW>*>(flag_fr), 0, static_cast<int>(n * sizeof(MaskT<NW>)), 0x00020000);
+    B.s32 = __builtin_amdgcn_make_buffer_rsrc(a.S32, 0, a.S32 ? static_cast<int>(n * 4u) : 0, 0x00020000);
+    B.r = __builtin_amdgcn_make_buffer_rsrc(a.R, 0, static_cast<int>(n * 4u), 0x00020000);
+    B.h2 = __builtin_amdgcn_make_buffer_rsrc(a.H2, 0, a.H2 ? static_cast<int>(n * 4u) : 0, 0x00020000);
+    B.col = __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t*>(a.col_idx), 0, static_cast<int>(a.nnz_cap * 4), 0x00020000);
+    B.seg = __builtin_amdgcn_make_buffer_rsrc(a.seg, 0, static_cast<int>(a.seg_cap * 16), 0x00020000);
+    return B;
 }
 
 template <int NW, int BLOCK, bool PER_SOURCE>
@@ -479,6 +552,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
     for (long long v = tid; v < n; v += nthreads) {
         if (!PER_SOURCE) {
             a.S[v] = 0;
+            a.S32[v] = 0;
             a.R[v] = 1;                                      // the vertex itself (d = 0)
             if (a.H2) a.H2[v] = 0;
         }
@@ -568,9 +642,16 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                     a.vis[i] = w0;
                     a.bufA[i] = w0;
                 }
-                for (long long v = tid; v < n; v += nthreads)
+                for (long long v = tid; v < n; v += nthreads) {
                     static_cast<Mask*>(a.flagA)[v] =
                         (v >= src0 && v < src0 + cnt) ? static_cast<Mask>(static_cast<Mask>(1) << ((v - src0) >> 6)) : Mask(0);
+                    // the previous batch's 32-bit sums into S
+                    const uint32_t x = a.S32[v];
+                    if (x) {
+                        a.S[v] += x;
+                        a.S32[v] = 0;
+                    }
+                }
                 for (long long i = tid_x; i < cnt; i += nthreads) {
                     const int3 sg = vertex_segments(a, static_cast<int>(src0 + i));
                     if (sg.y > 0) frontier_note(s_fr, par, sg.x, sg.y, sg.z);
@@ -623,6 +704,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
             int any = 0;
             long long t_pairs = 0;
             int t_verts = 0;
+            const LevelBufs B = level_bufs<NW>(a, nx, flag_nx, flag_fr);
             if (push) {
                 // ---- top-down, part 1: each block ORs the frontier words of
                 // the segments on its own list into their neighbours'
@@ -675,8 +757,8 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                             }
                             if (gl == 0) store_agent_i32(&a.hcnt[v], 0);
                         }
-                        const int2 cw = finalize_vertex<NW, PER_SOURCE>(a, nx, flag_nx, v, d, k, sub, gl, gbase, acc,
-                                                                        vis_v, s_cnt, foj);
+                        const int2 cw = finalize_vertex<NW, PER_SOURCE>(a, B, v, d, k, sub, gl, gbase, acc, vis_v,
+                                                                        s_cnt, foj);
                         if (cw.x) {
                             any = 1;
                             t_pairs += cw.x;
@@ -692,21 +774,22 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                 // ---- bottom-up over all segments
                 const __amdgpu_buffer_rsrc_t fr_rsrc = words_rsrc(fr, static_cast<uint32_t>(n) * (NW * 8u));
                 long long s = gid;
-                const int4 kNone = make_int4(0, 0, 0, 0);
                 SegPre<NW> cur, nxt;
-                seg_prefetch<NW, PER_SOURCE>(a, flag_nx, s < n_seg ? a.seg[s] : kNone, s < n_seg, gl, cur);
-                seg_prefetch<NW, PER_SOURCE>(a, flag_nx, s + ngroups < n_seg ? a.seg[s + ngroups] : kNone,
-                                             s + ngroups < n_seg, gl, nxt);
-                seg_flags<NW>(flag_fr, cur);
-                int4 rec2 = s + 2 * ngroups < n_seg ? a.seg[s + 2 * ngroups] : kNone;
+                auto rec_at = [&](long long i) {
+                    return buf_i4(B.seg, i < n_seg ? static_cast<uint32_t>(i) * 16u : kNoWord);
+                };
+                seg_prefetch<NW, PER_SOURCE>(B, rec_at(s), s < n_seg, gl, cur);
+                seg_prefetch<NW, PER_SOURCE>(B, rec_at(s + ngroups), s + ngroups < n_seg, gl, nxt);
+                seg_flags<NW>(B, cur);
+                int4 rec2 = rec_at(s + 2 * ngroups);
                 while (s < n_seg) {
                     const long long s1 = s + ngroups;
                     const long long s2 = s1 + ngroups;
                     const long long s3 = s2 + ngroups;
-                    const int4 rec3 = s3 < n_seg ? a.seg[s3] : kNone;                  // record, 3 ahead
+                    const int4 rec3 = rec_at(s3);                                      // record, 3 ahead
                     SegPre<NW> nn;
-                    seg_prefetch<NW, PER_SOURCE>(a, flag_nx, rec2, s2 < n_seg, gl, nn);  // ids, 2 ahead
-                    seg_flags<NW>(flag_fr, nxt);                                        // flags, 1 ahead
+                    seg_prefetch<NW, PER_SOURCE>(B, rec2, s2 < n_seg, gl, nn);          // ids, 2 ahead
+                    seg_flags<NW>(B, nxt);                                             // flags, 1 ahead
 
                     const int v = cur.sg.x;
                     const int nseg = cur.sg.w;
@@ -730,8 +813,8 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                         for (int c = cur.sg.y + Gather<NW>::ROUND; c < cur.sg.z; c += Gather<NW>::ROUND) {
                             int cid[Gather<NW>::CH];
                             Mask msk[Gather<NW>::CH];
-                            Gather<NW>::load_ids(a.col_idx, c, cur.sg.z, gl, cid);
-                            Gather<NW>::load_masks(flag_fr, cid, msk);
+                            Gather<NW>::load_ids(B.col, c, cur.sg.z, gl, cid);
+                            Gather<NW>::load_masks(B.flag_fr, cid, msk);
                             acc |= Gather<NW>::round_or(fr_rsrc, cid, msk, k, sub, gbase, (vis_v | acc) == ~0ull,
                                                         cur.sg.z - c, vis_v | acc);
                         }
@@ -739,8 +822,8 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
 #pragma unroll
                     for (int off = NW; off < kLpv; off <<= 1) acc |= shfl_xor_u64(acc, off);
                     if (nseg == 1) {
-                        const int2 cw = finalize_vertex<NW, PER_SOURCE>(a, nx, flag_nx, v, d, k, sub, gl, gbase, acc,
-                                                                        vis_v, s_cnt, cur.flag_old);
+                        const int2 cw = finalize_vertex<NW, PER_SOURCE>(a, B, v, d, k, sub, gl, gbase, acc, vis_v,
+                                                                        s_cnt, cur.flag_old);
                         if (cw.x) {
                             any = 1;
                             t_pairs += cw.x;
@@ -772,8 +855,8 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                             for (int off = NW; off < kLpv; off <<= 1) full |= shfl_xor_u64(full, off);
                             const Mask flag_old = flag_nx[v];
                             if (gl == 0) store_agent_i32(&a.hcnt[v], 0);
-                            const int2 cw = finalize_vertex<NW, PER_SOURCE>(a, nx, flag_nx, v, d, k, sub, gl, gbase,
-                                                                            full, vis_v, s_cnt, flag_old);
+                            const int2 cw = finalize_vertex<NW, PER_SOURCE>(a, B, v, d, k, sub, gl, gbase, full, vis_v,
+                                                                            s_cnt, flag_old);
                             if (cw.x) {
                                 any = 1;
                                 t_pairs += cw.x;
@@ -859,22 +942,33 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
         }
     }
 
-    // ---- closeness (Eq. 1, Wasserman-Faust form, fixed operation order)
-    if (a.cc) {
-        // all-source mode: S and R were last written before the final level
-        // barrier; listed sources: the last writes are the reduction above
-        if (PER_SOURCE && !gb.wait()) return;
+    // ---- closeness (Eq. 1, Wasserman-Faust form, fixed operation order);
+    // all-source mode first folds the last batch's 32-bit sums into S (the
+    // same thread reads and writes each vertex, after the final level
+    // barrier)
+    if (PER_SOURCE) {
+        // listed sources: the last writes of S and R are the reduction above
+        if (a.cc && !gb.wait()) return;
+    }
+    if (!PER_SOURCE || a.cc) {
         for (long long i = tid; i < a.n_src; i += nthreads) {
-            const int64_t sv = a.S[i];
-            const int32_t r = a.R[i];
-            double c = 0.0;
-            if (r > 1 && sv > 0 && n > 1) {
-                const double reach = static_cast<double>(r - 1);
-                const double q1 = reach / static_cast<double>(sv);
-                const double q2 = reach / static_cast<double>(n - 1);
-                c = q1 * q2;
+            int64_t sv = a.S[i];
+            if (!PER_SOURCE) {
+                sv += a.S32[i];
+                a.S[i] = sv;
+                a.S32[i] = 0;
             }
-            a.cc[i] = c;
+            if (a.cc) {
+                const int32_t r = a.R[i];
+                double c = 0.0;
+                if (r > 1 && sv > 0 && n > 1) {
+                    const double reach = static_cast<double>(r - 1);
+                    const double q1 = reach / static_cast<double>(sv);
+                    const double q2 = reach / static_cast<double>(n - 1);
+                    c = q1 * q2;
+                }
+                a.cc[i] = c;
+            }
         }
     }
 }
@@ -985,7 +1079,7 @@ size_t workspace_bytes(int32_t n, int64_t nnz, int nw, int grid_cap) {
     b += Arena::round(hln::dev::kBarrierWords * sizeof(unsigned long long));
     b += 4 * Arena::round(words * sizeof(uint64_t));            // A, B, vis, hacc
     b += 2 * Arena::round(static_cast<size_t>(n) * 8);          // word masks of A, B
-    b += 2 * Arena::round(static_cast<size_t>(n) * sizeof(int32_t)); // hcnt, seg_first
+    b += 3 * Arena::round(static_cast<size_t>(n) * sizeof(int32_t)); // hcnt, seg_first, S32
     b += Arena::round(seg_cap * sizeof(int4));
     b += Arena::round(static_cast<size_t>(grid_cap) * 2 * 64 * nw * sizeof(int64_t));  // per-source partials
     return b;
@@ -1023,6 +1117,8 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
     if (opts && (opts->direction < 0 || opts->direction > 2)) return fail(HLN_EINVAL, "bad direction %d", opts->direction);
     const int nw = width_words(opts);
     if (nw == 0) return fail(HLN_EINVAL, "width_bits must be 64, 128, 256, 512, 1024, 2048 or 4096");
+    if (g->nnz >= (1LL << 29) || static_cast<long long>(g->n) + g->nnz / kSegLen + 1 >= (1LL << 27))
+        return fail(HLN_EUNSUPPORTED, "graph too large for 32-bit buffer offsets (nnz %lld)", (long long)g->nnz);
     if (static_cast<long long>(g->n) * nw * 8 >= (1LL << 31))
         return fail(HLN_EUNSUPPORTED, "n * width_bits / 8 must be below 2^31 bytes (n = %d, width %d): use a narrower width",
                     g->n, nw * 64);
@@ -1059,6 +1155,7 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
     a.seg_cap = static_cast<long long>(n) + g->nnz / kSegLen + 1;
     a.seg = ar.take<int4>(static_cast<size_t>(a.seg_cap));
     a.seg_first = ar.take<int32_t>(n);
+    a.S32 = ar.take<uint32_t>(n);
     a.nnz_cap = g->nnz;
     a.part = ar.take<int64_t>(static_cast<size_t>(grid_cap) * 2 * 64 * nw);
     a.S = S;
@@ -1074,7 +1171,9 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
     a.seg_len = kSegLen;
     a.alpha = 4;
     if (const char* e = getenv("HLN_ALPHA")) a.alpha = std::max(1, atoi(e));
-    if (!a.ctrl || !a.bar || !a.part || !a.flagB || !a.seg_first) return fail(HLN_ENOMEM, "workspace carve failed");
+    a.s32_levels = kS32Levels;
+    if (const char* e = getenv("HLN_S32_LEVELS")) a.s32_levels = std::min(kS32Levels, std::max(1, atoi(e)));
+    if (!a.ctrl || !a.bar || !a.part || !a.flagB || !a.seg_first || !a.S32) return fail(HLN_ENOMEM, "workspace carve failed");
 
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(k_zero_ctrl, dim3(1), dim3(256), 0, st, a.ctrl, a.bar);

@@ -215,3 +215,18 @@ def test_auto_direction_takes_both():
     # the first level of a batch is top-down unless its sources hold hubs
     starts = np.concatenate([[0], np.cumsum(lv.cpu().numpy())[:-1]])
     assert np.mean(dirs[starts] == 1) >= 0.8
+
+
+@pytest.mark.parametrize("width", [64, 4096])
+def test_distance_sums_past_the_32_bit_window(width, monkeypatch):
+    """Levels from HLN_S32_LEVELS on add to S with 64-bit atomics instead of
+    the per-batch 32-bit sums; forcing it from level 3 runs both paths in
+    one BFS (long paths and a random graph)."""
+    monkeypatch.setenv("HLN_S32_LEVELS", "3")
+    for named in [("path", 700), ("cycle", 513)]:
+        n, eu, ev = G.named_graph(*named)
+        rp, ci = csr_np(n, *G.to_edges(n, eu, ev))
+        check_all(n, rp, ci, width, "s64-%s" % (named,))
+    h = C.config2(scale=0.03)
+    rp, ci = csr_np(h.n, *h.layers[0])
+    check_all(h.n, rp, ci, width, "s64-cfg2-scaled")
