@@ -120,10 +120,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
-    ap.add_argument("--workload", choices=["cfg2", "cfg3", "cfg4", "cfg5"], default="cfg2",
+    ap.add_argument("--workload", choices=["cfg2", "cfg3", "cfg4", "cfg5", "accuracy", "subsets"], default="cfg2",
                     help="cfg2 (default): the benchmark line; cfg3: the batched path on 64 HoMLNs; cfg4: 6 R-MAT "
                          "layers over 10^6 vertices from 16,384 sampled sources per graph; cfg5: the learned "
-                         "candidate proposer against exhaustive AND closeness")
+                         "candidate proposer against exhaustive AND closeness; accuracy: CC2 and naive "
+                         "composition against the AND ground truth; subsets: Psi once against per-subset ground "
+                         "truth over every layer subset")
     ap.add_argument("--train-steps", type=int, default=3000, help="cfg5: proposer training steps")
     args = ap.parse_args()
 
@@ -144,6 +146,9 @@ def main():
         return
     if args.workload == "cfg4":
         run_cfg4(args)
+        return
+    if args.workload in ("accuracy", "subsets"):
+        run_composition(args)
         return
     if args.width is None:
         args.width = 4096
@@ -454,6 +459,47 @@ def run_cfg4(args):
                         "algorithmic_bytes_per_launch": bytes_per_launch,
                         "levels_per_launch": [int(x.sum()) for x in lv]}}
     print(json.dumps(rec), flush=True)
+
+
+def run_composition(args):
+    """accuracy: Jaccard / precision / recall / F1 of CC2 and naive CC-node
+    sets (above-average and top-10%) against the AND ground truth, for every
+    HoMLN's full layer set and layer pairs (configs 1, 2, the first 16 HoMLNs
+    of config 3, config 5).  subsets: Psi once, then every subset of >= 2
+    layers of configs 2 and 5: per-subset AND and OR ground truth against
+    per-subset CC2 (times from HIP events)."""
+    import torch
+    from paper_2207_11662_amd import composition as CM
+    from homln_inputs import configs as C
+    torch.cuda.set_device(0)
+    if args.workload == "accuracy":
+        out = {}
+        plan = None
+        for name, hs in [("config1", [C.config1()]), ("config2", [C.config2()]),
+                         ("config3[0:16]", [C.config3_homln(i) for i in range(16)]), ("config5", [C.config5()])]:
+            t0 = time.perf_counter()
+            recs = []
+            for h in hs:
+                recs += CM.study_homln(h, k_frac=0.1, pairs=True)
+            out[name] = CM.summarise(recs)
+            out[name]["whole_homln_only"] = CM.summarise([r for i, r in enumerate(recs)
+                                                          if len(r["subset"]) == max(len(x["subset"]) for x in recs)])
+            log("%s: %d subsets in %.1fs" % (name, len(recs), time.perf_counter() - t0))
+        print(json.dumps({"metric": "CC-node set accuracy of CC2 and naive composition vs AND ground truth",
+                          "unit": "Jaccard/precision/recall/F1 (means over subsets)", "data": "synthetic",
+                          "k": "top 10% (ceil)", "results": out}), flush=True)
+        return
+    for name, h in [("config2", C.config2()), ("config5", C.config5())]:
+        t0 = time.perf_counter()
+        res = CM.subsets_sweep(h, k_frac=0.01, width_bits=args.width or 4096, with_or=True)
+        log("%s: %d subsets in %.1fs" % (name, res["subsets"], time.perf_counter() - t0))
+        recs = res.pop("records")
+        res["per_subset"] = [{"subset": r["subset"], "t_and_gt_ms": round(r["t_and_gt_ms"], 3),
+                              "t_or_gt_ms": round(r.get("t_or_gt_ms", 0.0), 3), "t_theta_ms": round(r["t_theta_ms"], 3),
+                              "cc2_topk_jaccard": round(r["cc2_topk"]["jaccard"], 4),
+                              "cc2_topk_precision": round(r["cc2_topk"]["precision"], 4)} for r in recs]
+        print(json.dumps({"metric": "decoupled (Psi once + Theta per subset) vs per-subset AND ground truth",
+                          "workload": name, "n": h.n, "data": "synthetic", **res}), flush=True)
 
 
 def run_cfg5(args):
