@@ -603,7 +603,8 @@ def run_cfg5(args):
            "dtype": "f32 (MLP), i64/f64 (BFS, closeness)", "data": "synthetic",
            "config": {"workload": "5 Chung-Lu layers x 200,000 vertices (config 5); AND graph; candidates 5%, answer 1%",
                       "n": n, "and_arcs": int(g_and.nnz), "candidates": n_cand, "k": k,
-                      "train_vertices": int(sum(t.n for t in train)), "train_steps": args.train_steps},
+                      "train_vertices": int(sum(t.n for t in train)), "train_steps": args.train_steps,
+                      "features": 12},
            "exhaustive_ms": round(t_ex, 3), "proposer_ms": round(t_q, 3),
            "precision_at_k": p_learned[0], "precision_at_k_ties": p_learned[1],
            "cc2_same_budget_precision": p_cc2[0], "cc2_same_budget_precision_ties": p_cc2[1],

@@ -216,16 +216,15 @@ hln_status hln_plan_replay(hln_plan* plan, void* stream);
  * step's per-layer outputs: degree, closeness and 2-hop count, echoing
  * CC1's degree bound, Sec. 5.1, and CC2's per-layer sums, Sec. 5.2).
  * ------------------------------------------------------------------------
- * hln_proposer_features: X [dev] float[n][16]; for each of four per-layer
+ * hln_proposer_features: X [dev] float[n][12]; for each of three per-layer
  *   quantities -- log1p(deg / mean degree of the layer), the closeness
- *   ((R-1)/S)((R-1)/(n-1)), log1p(h2 / mean degree^2) and the penalised
- *   closeness (n-1)/(S + n(n-R)) (its minimum over the layers is CC2's
- *   score) -- the min, max, mean and standard deviation over the r layers.
- *   row_ptr, S, R, h2: [host] arrays of r device pointers (n+1, n, n, n
- *   entries; S, R, h2 as hln_closeness_layer's all-source outputs); nnz
- *   [host] r exact arc counts.  1 <= r <= 64.
- * The MLP is 16 -> 64 (ReLU) -> 64 (ReLU) -> 1 in FP32 with
- *   hln_mlp_param_count() parameters in the order W1[16][64], b1[64],
+ *   ((R-1)/S)((R-1)/(n-1)) and log1p(h2 / mean degree^2) -- the min, max,
+ *   mean and standard deviation over the r layers.  row_ptr, S, R, h2:
+ *   [host] arrays of r device pointers (n+1, n, n, n entries; S, R, h2 as
+ *   hln_closeness_layer's all-source outputs); nnz [host] r exact arc
+ *   counts.  1 <= r <= 64.
+ * The MLP is 12 -> 64 (ReLU) -> 64 (ReLU) -> 1 in FP32 with
+ *   hln_mlp_param_count() parameters in the order W1[12][64], b1[64],
  *   W2[64][64], b2[64], w3[64], b3 (params [dev] float).
  * hln_mlp_init: Glorot-uniform weights from a counter-based generator
  *   (splitmix64 of seed and index), zero biases; zeroes adam_m / adam_v

@@ -389,12 +389,12 @@ def mlp_param_count() -> int:
 
 
 def hln_proposer_features(graphs, S_list, R_list, h2s, X=None, stream=None) -> torch.Tensor:
-    """16 features per vertex from r layers' CSR and all-source S, R, h2.
+    """12 features per vertex from r layers' CSR and all-source S, R, h2.
     Each Graph's nnz must be its exact arc count (it sets the mean degree)."""
     n = graphs[0].n
     r = len(graphs)
     if X is None:
-        X = torch.empty((n, 16), dtype=torch.float32, device=graphs[0].row_ptr.device)
+        X = torch.empty((n, 12), dtype=torch.float32, device=graphs[0].row_ptr.device)
     nnz = (ctypes.c_int64 * r)(*[g.nnz for g in graphs])
     check(lib().hln_proposer_features(n, r, _ptr_array([g.row_ptr for g in graphs]), _ptr_array(S_list),
                                       _ptr_array(R_list), _ptr_array(h2s), ctypes.cast(nnz, ctypes.c_void_p),

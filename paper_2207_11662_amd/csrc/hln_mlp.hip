@@ -7,8 +7,8 @@
 // (Not in the paper: the features echo CC1's degree bound, Sec. 5.1, and
 // CC2's per-layer distance sums, Sec. 5.2.)
 //
-// Model: 16 features -> 64 ReLU -> 64 ReLU -> 1, FP32.  Parameters, in
-// order: W1[16][64], b1[64], W2[64][64], b2[64], w3[64], b3.
+// Model: 12 features -> 64 ReLU -> 64 ReLU -> 1, FP32.  Parameters, in
+// order: W1[12][64], b1[64], W2[64][64], b2[64], w3[64], b3.
 // Training step (mean squared error): a block takes 64 vertices, runs the
 // forward and backward passes with activations in LDS, and writes its
 // partial gradient; one kernel then sums the partials over blocks in block
@@ -21,8 +21,8 @@
 
 namespace {
 
-constexpr int F = 16;
-constexpr int NQ = 4;                          // per-layer quantities
+constexpr int F = 12;
+constexpr int NQ = 3;                          // per-layer quantities
 constexpr int H = 64;
 constexpr int OFF_W1 = 0;
 constexpr int OFF_B1 = OFF_W1 + F * H;
@@ -30,7 +30,7 @@ constexpr int OFF_W2 = OFF_B1 + H;
 constexpr int OFF_B2 = OFF_W2 + H * H;
 constexpr int OFF_W3 = OFF_B2 + H;
 constexpr int OFF_B3 = OFF_W3 + H;
-constexpr int NPARAM = OFF_B3 + 1;            // 5313
+constexpr int NPARAM = OFF_B3 + 1;            // 5057
 constexpr int TB = 64;                         // vertices per training block
 constexpr int BLK = 256;
 constexpr int kMaxLayers = 64;
@@ -45,9 +45,8 @@ struct Layers {
 };
 
 // Per layer and vertex: log1p(deg / mean degree); the Wasserman-Faust
-// closeness ((R-1)/S)((R-1)/(n-1)); log1p(h2 / mean degree^2); and the
-// penalised closeness (n-1) / (S + n(n-R)), unreachable vertices at
-// distance n, whose minimum over the layers is CC2's score (Sec. 5.1-5.2).
+// closeness ((R-1)/S)((R-1)/(n-1)) (Sec. 4, Eq. 1); log1p(h2 / mean
+// degree^2).
 __device__ __forceinline__ void layer_values(const Layers& L, int l, int u, int n, float v[NQ]) {
     const float deg = static_cast<float>(L.rp[l][u + 1] - L.rp[l][u]);
     const double S = static_cast<double>(L.S[l][u]);
@@ -56,10 +55,9 @@ __device__ __forceinline__ void layer_values(const Layers& L, int l, int u, int 
     v[0] = log1pf(deg * L.inv_mean_deg[l]);
     v[1] = (R > 1.0 && n > 1) ? static_cast<float>(((R - 1.0) / S) * ((R - 1.0) / nm1)) : 0.f;
     v[2] = log1pf(static_cast<float>(L.h2[l][u]) * L.inv_mean_deg[l] * L.inv_mean_deg[l]);
-    v[3] = n > 1 ? static_cast<float>(nm1 / (S + static_cast<double>(n) * (static_cast<double>(n) - R))) : 0.f;
 }
 
-// 16 features per vertex: min, max, mean and standard deviation of each
+// 12 features per vertex: min, max, mean and standard deviation of each
 // quantity over the r layers (two passes, so that the deviation does not
 // cancel against the mean).
 __global__ void k_features(int n, Layers L, float* X) {

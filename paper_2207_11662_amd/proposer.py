@@ -2,8 +2,8 @@
 
 The exact answer needs one BFS per vertex of the AND graph (Sec. 4).  The
 proposer ranks vertices with a small FP32 MLP over per-layer quantities the
-Psi step has already produced (degree, closeness, 2-hop count and the
-penalised closeness: the signals CC1 and CC2 use, Sec. 5.1-5.2), keeps the best `budget` fraction as
+Psi step has already produced (degree, closeness and 2-hop count: the
+signals CC1 and CC2 build on, Sec. 5.1-5.2), keeps the best `budget` fraction as
 candidates, runs exact per-source BFS on the AND graph for those only, and
 returns the best of them by exact closeness.  Every step is a kernel of
 ``libhln.so``; this module only sequences the calls.  The method itself is
@@ -46,7 +46,7 @@ def features(layers, psi_outs, X=None, stream=None):
 
 
 def training_example(plan: L.Plan, h, stream=None):
-    """(X [n, 16] float32, label [n] float32) of one HoMLN."""
+    """(X [n, 12] float32, label [n] float32) of one HoMLN."""
     layers = upload_homln(h, stream)
     g_and = L.hln_compose_and(layers, stream=stream).trimmed()
     outs = psi(plan, layers + [g_and], stream)
@@ -104,7 +104,7 @@ class Query:
         dev = g_and.row_ptr.device
         n = g_and.n
         self.g, self.n_cand, self.k, self.width = g_and, n_cand, k, width_bits
-        self.X = torch.empty((n, 16), dtype=torch.float32, device=dev)
+        self.X = torch.empty((n, 12), dtype=torch.float32, device=dev)
         self.y = torch.empty(n, dtype=torch.float32, device=dev)
         self.cand = torch.empty(max(n_cand, 1), dtype=torch.int32, device=dev)
         self.pos = torch.empty(max(k, 1), dtype=torch.int32, device=dev)

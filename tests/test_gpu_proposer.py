@@ -32,7 +32,7 @@ def test_training_labels_are_oracle_ranks():
     g = h.n - np.searchsorted(np.sort(cc), cc, side="right")
     exp = (np.log((h.n + 1.0) / (g + 1.0)) / np.log(h.n + 1.0)).astype(np.float32)
     assert np.all(np.abs(lab.cpu().numpy().view(np.int32) - exp.view(np.int32)) <= 1)
-    assert X.shape == (h.n, 16) and torch.isfinite(X).all()
+    assert X.shape == (h.n, 12) and torch.isfinite(X).all()
 
 
 def test_query_returns_exact_values_of_its_candidates():
