@@ -127,6 +127,8 @@ def main():
                          "composition against the AND ground truth; subsets: Psi once against per-subset ground "
                          "truth over every layer subset")
     ap.add_argument("--train-steps", type=int, default=3000, help="cfg5: proposer training steps")
+    ap.add_argument("--budget", type=float, default=0.05, help="cfg5: candidate fraction (the answer is the top 1%%)")
+    ap.add_argument("--cand-width", type=int, default=None, help="cfg5: source batch of the candidate BFS")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -549,12 +551,12 @@ def run_cfg5(args):
     g_and = P.hln_compose_and(layers).trimmed()
     torch.cuda.synchronize()
     t_psi = time.perf_counter() - t0
-    n_cand, k = n // 20, n // 100
+    n_cand, k = int(round(args.budget * n)), n // 100
     ex = {"S": torch.empty(n, dtype=torch.int64, device=dev), "R": torch.empty(n, dtype=torch.int32, device=dev),
           "cc": torch.empty(n, dtype=torch.float64, device=dev), "h2": None}
     ex_ws = P.workspace(P.closeness_workspace_size(n, g_and.nnz, n, args.width), dev)
     ex_ids = torch.empty(k, dtype=torch.int32, device=dev)
-    q = PR.Query(g_and, n_cand, k, width_bits=args.width)
+    q = PR.Query(g_and, n_cand, k, width_bits=args.cand_width or args.width)
 
     def exhaustive():
         P.hln_closeness_layer(g_and, None, width_bits=args.width, out=ex, ws=ex_ws)
@@ -601,10 +603,11 @@ def run_cfg5(args):
            "value": round(speed, 3), "unit": "x", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(t_q, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32 (MLP), i64/f64 (BFS, closeness)", "data": "synthetic",
-           "config": {"workload": "5 Chung-Lu layers x 200,000 vertices (config 5); AND graph; candidates 5%, answer 1%",
+           "config": {"workload": "5 Chung-Lu layers x 200,000 vertices (config 5); AND graph; candidates %g%%, answer 1%%"
+                                  % (100 * args.budget),
                       "n": n, "and_arcs": int(g_and.nnz), "candidates": n_cand, "k": k,
                       "train_vertices": int(sum(t.n for t in train)), "train_steps": args.train_steps,
-                      "features": 12},
+                      "features": 12, "candidate_width": args.cand_width or args.width},
            "exhaustive_ms": round(t_ex, 3), "proposer_ms": round(t_q, 3),
            "precision_at_k": p_learned[0], "precision_at_k_ties": p_learned[1],
            "cc2_same_budget_precision": p_cc2[0], "cc2_same_budget_precision_ties": p_cc2[1],
