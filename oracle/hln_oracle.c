@@ -379,3 +379,103 @@ int32_t oracle_naive(int32_t n, int32_t r, const double* const* cc, int32_t* ids
     free(in); free(tmp);
     return c;
 }
+
+/* ------------------------------------------------------------------ */
+/* Closeness of every vertex estimated from a sample of sources (after  */
+/* Eppstein and Wang's sampling estimator of closeness, the linear-time */
+/* approximation the paper cites among related work, Sec. 2).           */
+/* ------------------------------------------------------------------ */
+
+/* Sample sums, source by source: for every vertex v, SQ[v] = sum of d(s, v)
+ * over the k listed sources s that reach v, RQ[v] = how many listed sources
+ * reach v (v itself when it is listed).  One FIFO BFS per source.  Returns
+ * 0, -1 on a bad source id, -2 on allocation failure. */
+int oracle_sample_sums(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, int32_t k,
+                       const int32_t* sources, int64_t* SQ, int32_t* RQ) {
+    for (int32_t i = 0; i < k; ++i)
+        if (sources[i] < 0 || sources[i] >= n) return -1;
+    int32_t* dist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!dist || !queue) { free(dist); free(queue); return -2; }
+    for (int32_t v = 0; v < n; ++v) { dist[v] = -1; SQ[v] = 0; RQ[v] = 0; }
+    for (int32_t i = 0; i < k; ++i) {
+        int32_t s = sources[i], head = 0, tail = 0;
+        dist[s] = 0;
+        queue[tail++] = s;
+        while (head < tail) {
+            int32_t u = queue[head++];
+            SQ[u] += dist[u];
+            RQ[u] += 1;
+            for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                int32_t w = col_idx[e];
+                if (dist[w] < 0) {
+                    dist[w] = 1 + dist[u];
+                    queue[tail++] = w;
+                }
+            }
+        }
+        for (int32_t j = 0; j < tail; ++j) dist[queue[j]] = -1;
+    }
+    free(dist); free(queue);
+    return 0;
+}
+
+/* The same sums for listed vertices only, vertex by vertex: one BFS from v
+ * and the distances to the sampled sources added up (the graph is
+ * undirected, so d(s, v) = d(v, s)).  in_sample[u] != 0 marks the sample. */
+int oracle_sample_sums_at(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const uint8_t* in_sample,
+                          int32_t count, const int32_t* verts, int64_t* SQ, int32_t* RQ) {
+    int32_t* dist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!dist || !queue) { free(dist); free(queue); return -2; }
+    for (int32_t v = 0; v < n; ++v) dist[v] = -1;
+    for (int32_t i = 0; i < count; ++i) {
+        int32_t v = verts[i], head = 0, tail = 0;
+        if (v < 0 || v >= n) { free(dist); free(queue); return -1; }
+        int64_t sum = 0;
+        int32_t reached = 0;
+        dist[v] = 0;
+        queue[tail++] = v;
+        while (head < tail) {
+            int32_t u = queue[head++];
+            if (in_sample[u]) { sum += dist[u]; ++reached; }
+            for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                int32_t w = col_idx[e];
+                if (dist[w] < 0) {
+                    dist[w] = dist[u] + (int32_t)1;
+                    queue[tail++] = w;
+                }
+            }
+        }
+        for (int32_t j = 0; j < tail; ++j) dist[queue[j]] = -1;
+        SQ[i] = sum;
+        RQ[i] = reached;
+    }
+    free(dist); free(queue);
+    return 0;
+}
+
+/* Estimated closeness in the Wasserman-Faust form from sample sums: with
+ * q = RQ[v] - [v in sample] (sampled sources other than v reaching v) and
+ * k' = k - [v in sample],
+ *   mean distance ~ SQ / q, reach fraction ~ q / k',
+ *   cc_est = (q / SQ) * (q / k') * ((n_pop - 1) / (n - 1)),
+ * where n_pop is the size of the vertex set the sample was drawn from
+ * (every vertex outside it reaches nothing).  0 when q == 0 or n <= 1.
+ * With the sample equal to all n vertices this is the exact closeness. */
+void oracle_sample_estimate(int32_t n, int32_t n_pop, int32_t k, const uint8_t* in_sample, const int64_t* SQ,
+                            const int32_t* RQ, double* cc) {
+    for (int32_t v = 0; v < n; ++v) {
+        int32_t self = in_sample[v] ? 1 : 0;
+        int32_t q = RQ[v] - self;
+        int32_t kp = k - self;
+        if (q > 0 && SQ[v] > 0 && kp > 0 && n > 1) {
+            double a = (double)q / (double)SQ[v];
+            double b = (double)q / (double)kp;
+            double c = (double)(n_pop - 1) / (double)(n - 1);
+            cc[v] = (a * b) * c;
+        } else {
+            cc[v] = 0.0;
+        }
+    }
+}

@@ -66,6 +66,12 @@ def _bind(path: str):
     L.oracle_cc2_score.restype = None
     L.oracle_naive.argtypes = [i32, i32, P, P]
     L.oracle_naive.restype = i32
+    L.oracle_sample_sums.argtypes = [i32, P, P, i32, P, P, P]
+    L.oracle_sample_sums.restype = ctypes.c_int
+    L.oracle_sample_sums_at.argtypes = [i32, P, P, P, i32, P, P, P]
+    L.oracle_sample_sums_at.restype = ctypes.c_int
+    L.oracle_sample_estimate.argtypes = [i32, i32, i32, P, P, P, P]
+    L.oracle_sample_estimate.restype = None
     return L
 
 
@@ -258,6 +264,53 @@ def naive(n: int, cc_list):
     if c < 0:
         raise ValueError("oracle_naive failed")
     return ids[:c].copy()
+
+
+def sample_mask(n: int, sources) -> np.ndarray:
+    m = np.zeros(max(n, 1), np.uint8)
+    m[np.asarray(sources, np.int64)] = 1
+    return m[:n]
+
+
+def sample_sums(row_ptr, col_idx, sources):
+    """Per vertex: (SQ, RQ) = sum of distances from, and count of, the listed
+    sources that reach it (one BFS per source)."""
+    L = _load()
+    row_ptr = _c(row_ptr, np.int32)
+    col_idx = _c(col_idx, np.int32) if len(col_idx) else np.zeros(1, np.int32)
+    n = len(row_ptr) - 1
+    src = _c(sources, np.int32)
+    SQ = np.zeros(max(n, 1), np.int64)
+    RQ = np.zeros(max(n, 1), np.int32)
+    if L.oracle_sample_sums(n, _p(row_ptr), _p(col_idx), len(src), _p(src), _p(SQ), _p(RQ)) != 0:
+        raise ValueError("oracle_sample_sums failed")
+    return SQ[:n], RQ[:n]
+
+
+def sample_sums_at(row_ptr, col_idx, sources, verts):
+    """(SQ, RQ) of the listed vertices only, one BFS from each vertex."""
+    L = _load()
+    row_ptr = _c(row_ptr, np.int32)
+    col_idx = _c(col_idx, np.int32) if len(col_idx) else np.zeros(1, np.int32)
+    n = len(row_ptr) - 1
+    mask = sample_mask(n, sources)
+    vv = _c(verts, np.int32)
+    SQ = np.zeros(max(len(vv), 1), np.int64)
+    RQ = np.zeros(max(len(vv), 1), np.int32)
+    if L.oracle_sample_sums_at(n, _p(row_ptr), _p(col_idx), _p(mask), len(vv), _p(vv), _p(SQ), _p(RQ)) != 0:
+        raise ValueError("oracle_sample_sums_at failed")
+    return SQ[:len(vv)], RQ[:len(vv)]
+
+
+def sample_estimate(n: int, n_pop: int, sources, SQ, RQ):
+    """Estimated closeness of every vertex from sample sums (WF form)."""
+    L = _load()
+    mask = sample_mask(n, sources)
+    SQ = _c(SQ, np.int64)
+    RQ = _c(RQ, np.int32)
+    cc = np.zeros(max(n, 1), np.float64)
+    L.oracle_sample_estimate(n, n_pop, len(sources), _p(mask), _p(SQ), _p(RQ), _p(cc))
+    return cc[:n]
 
 
 # --------------------------------------------------------------------------

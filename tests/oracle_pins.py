@@ -373,6 +373,88 @@ def pin_naive(o):
         assert o.naive(n, [ccs[0], ccs[0]]).tolist() == o.above_mean(ccs[0]).tolist()
 
 
+def pin_sample_sums(o):
+    """Sample sums against Floyd-Warshall (sum and count over the sampled
+    rows of each column), both the per-source and the per-vertex routes."""
+    rng = np.random.default_rng(2004)
+    for trial in range(30):
+        n = int(rng.integers(2, 48))
+        eu, ev = random_graph(rng, n, float(rng.choice([0.03, 0.08, 0.3])))
+        adj = adjacency_sets(n, eu, ev)
+        D = floyd_warshall(n, adj)
+        k = int(rng.integers(1, n + 1))
+        src = np.sort(rng.choice(n, size=k, replace=False)).astype(np.int32)
+        fin = np.isfinite(D[src])
+        SQ_ref = np.where(fin, D[src], 0).sum(0).astype(np.int64)
+        RQ_ref = fin.sum(0)
+        rp, ci = csr_of(o, n, eu, ev)
+        SQ, RQ = o.sample_sums(rp, ci, src)
+        assert np.array_equal(SQ, SQ_ref), trial
+        assert np.array_equal(RQ, RQ_ref), trial
+        verts = rng.choice(n, size=min(n, 7), replace=False).astype(np.int32)
+        S2, R2 = o.sample_sums_at(rp, ci, src, verts)
+        assert np.array_equal(S2, SQ_ref[verts]) and np.array_equal(R2, RQ_ref[verts]), trial
+
+
+def pin_sample_estimate_full_sample(o):
+    """With every vertex sampled the estimate is the exact closeness, bit for
+    bit (Floyd-Warshall sums through the closed form of Sec. 4, Eq. 1 in the
+    Wasserman-Faust form), on connected and disconnected graphs."""
+    rng = np.random.default_rng(7)
+    for trial in range(25):
+        n = int(rng.integers(2, 40))
+        eu, ev = random_graph(rng, n, float(rng.choice([0.03, 0.1, 0.4])))
+        adj = adjacency_sets(n, eu, ev)
+        D = floyd_warshall(n, adj)
+        fin = np.isfinite(D)
+        S = np.where(fin, D, 0).sum(1)
+        R = fin.sum(1)
+        exact = np.array([((R[v] - 1) / S[v]) * ((R[v] - 1) / (n - 1)) if R[v] > 1 else 0.0 for v in range(n)])
+        rp, ci = csr_of(o, n, eu, ev)
+        src = np.arange(n, dtype=np.int32)
+        SQ, RQ = o.sample_sums(rp, ci, src)
+        est = o.sample_estimate(n, n, src, SQ, RQ)
+        assert np.array_equal(est.view(np.int64), exact.view(np.int64)), trial
+        # isolated vertices outside the population: sampling every vertex of
+        # degree >= 1 (n_pop of them) still gives the exact closeness
+        deg = np.array([len(a) for a in adj])
+        pop = np.flatnonzero(deg > 0).astype(np.int32)
+        if 1 < len(pop) < n:
+            SQ, RQ = o.sample_sums(rp, ci, pop)
+            est = o.sample_estimate(n, len(pop), pop, SQ, RQ)
+            assert np.allclose(est, exact, rtol=1e-13, atol=0), trial
+
+
+def pin_sample_estimate_bound(o):
+    """Mean-distance estimate within Hoeffding's bound on a connected graph:
+    |SQ/q - S/(n-1)| <= diam * sqrt(ln(2n/delta) / (2k)) for every vertex,
+    delta = 1e-3 (k sources sampled uniformly without replacement), and the
+    estimated closeness is then the exact one scaled by at most that error."""
+    rng = np.random.default_rng(2211)
+    n, k = 600, 150
+    eu, ev = random_graph(rng, n, 0.004)
+    eu = np.concatenate([eu, np.arange(n - 1)])            # a path keeps it connected
+    ev = np.concatenate([ev, np.arange(1, n)])
+    adj = adjacency_sets(n, eu, ev)
+    D = floyd_warshall(n, adj)
+    diam = D.max()
+    src = np.sort(rng.choice(n, size=k, replace=False)).astype(np.int32)
+    rp, ci = csr_of(o, n, eu, ev)
+    SQ, RQ = o.sample_sums(rp, ci, src)
+    mask = np.zeros(n, bool)
+    mask[src] = True
+    q = RQ - mask
+    mean_est = SQ / q
+    mean_true = D.sum(1) / (n - 1)
+    eps = diam * math.sqrt(math.log(2 * n / 1e-3) / (2 * k))
+    assert np.all(np.abs(mean_est - mean_true) <= eps)
+    est = o.sample_estimate(n, n, src, SQ, RQ)
+    exact = 1.0 / mean_true                                   # connected: WF factor 1
+    assert np.allclose(est, (1.0 / mean_est) * (q / (k - mask)), rtol=1e-12)
+    assert np.all(np.abs(1.0 / est - 1.0 / exact) <= eps + 1e-9)
+
+
 PINS = [pin_closed_forms, pin_disjoint_union, pin_floyd_warshall, pin_networkx, pin_networkx_printed,
         pin_wiener_tree, pin_csr_normalisation, pin_compose_sets, pin_mean_exact, pin_above_mean,
-        pin_topk, pin_cc2_worked_example, pin_cc2_bounds, pin_naive]
+        pin_topk, pin_cc2_worked_example, pin_cc2_bounds, pin_naive, pin_sample_sums,
+        pin_sample_estimate_full_sample, pin_sample_estimate_bound]

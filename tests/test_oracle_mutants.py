@@ -35,6 +35,9 @@ MUTANTS = [
     ("cc2-min", "if (l == 0 || p > best) best = p;", "if (l == 0 || p < best) best = p;"),
     ("cc2-unpenalised", "int64_t p = S[l][u] + (int64_t)n * (int64_t)(n - R[l][u]);", "int64_t p = S[l][u];"),
     ("naive-union", "in[u] = in[u] && keep[u];", "in[u] = (l == 0) ? keep[u] : (in[u] || keep[u]);"),
+    ("sample-self-counted", "int32_t q = RQ[v] - self;", "int32_t q = RQ[v];"),
+    ("sample-population-n", "double c = (double)(n_pop - 1) / (double)(n - 1);", "double c = 1.0;"),
+    ("sample-sums-off-by-one", "SQ[u] += dist[u];", "SQ[u] += dist[u] + 1;"),
 ]
 
 
