@@ -120,9 +120,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES")
-    ap.add_argument("--workload", choices=["cfg2", "cfg3", "cfg4", "cfg5", "accuracy", "subsets"], default="cfg2",
+    ap.add_argument("--workload", choices=["cfg2", "cfg3", "cfg4", "cfg4est", "cfg5", "accuracy", "subsets"],
+                    default="cfg2",
                     help="cfg2 (default): the benchmark line; cfg3: the batched path on 64 HoMLNs; cfg4: 6 R-MAT "
-                         "layers over 10^6 vertices from 16,384 sampled sources per graph; cfg5: the learned "
+                         "layers over 10^6 vertices from 16,384 sampled sources per graph; cfg4est: the sampling "
+                         "estimate of every vertex's closeness from the same samples; cfg5: the learned "
                          "candidate proposer against exhaustive AND closeness; accuracy: CC2 and naive "
                          "composition against the AND ground truth; subsets: Psi once against per-subset ground "
                          "truth over every layer subset")
@@ -148,6 +150,9 @@ def main():
         return
     if args.workload == "cfg4":
         run_cfg4(args)
+        return
+    if args.workload == "cfg4est":
+        run_cfg4est(args)
         return
     if args.workload in ("accuracy", "subsets"):
         run_composition(args)
@@ -383,6 +388,134 @@ def source_edge_sum(n, eu, ev, src):
     return int(edges[lab[src]].sum())
 
 
+def cfg4_setup():
+    """Config 4 on the device: (HoMLN, n, AND edge sources, device graphs
+    (6 layers + AND), per-graph seeded samples, per-graph TEPS edge counts,
+    per-graph populations (vertices of degree >= 1))."""
+    import torch
+    import paper_2207_11662_amd as P
+    from paper_2207_11662_amd import proposer as PR
+    from homln_inputs import configs as C
+    t_gen = time.perf_counter()
+    h = C.config4(workers=8, progress=lambda s: log("%s (%.0fs)" % (s, time.perf_counter() - t_gen)))
+    n = h.n
+    A_eu, A_ev = and_edges(n, h.layers)
+    edges = list(h.layers) + [(A_eu, A_ev)]
+    degs = [np.bincount(np.concatenate([eu, ev]), minlength=n) for eu, ev in edges]
+    srcs = [C.config4_sources(gi, d) for gi, d in enumerate(degs)]
+    teps_den = [source_edge_sum(n, eu, ev, s) for (eu, ev), s in zip(edges, srcs)]
+    log("generated config 4 in %.0fs; AND graph %d edges" % (time.perf_counter() - t_gen, len(A_eu)))
+    torch.cuda.set_device(torch.device("cuda", 0))
+    layers = PR.upload_homln(h)
+    g_and = P.hln_compose_and(layers).trimmed()
+    return h, n, A_eu, layers + [g_and], srcs, teps_den, [int((d > 0).sum()) for d in degs]
+
+
+def run_cfg4est(args):
+    """Sampling estimate of every vertex's closeness on config 4: per graph
+    (6 R-MAT layers over 1,000,000 vertices + AND graph), per-vertex sums
+    over its 16,384 seeded sources (one persistent BFS launch, listed
+    sources, per-vertex accumulation) and the FP64 estimate for all 10^6
+    vertices.  One step = the 7 graphs.  After the timed steps, on the AND
+    graph: the exact all-source closeness, and against it the estimate's
+    relative error and the precision of its top 1%, alone and after exact
+    refinement of its top 2% (listed-source closeness of those candidates)."""
+    import torch
+    import paper_2207_11662_amd as P
+    W = args.width or 4096
+    h, n, A_eu, graphs, srcs, teps_den, pops = cfg4_setup()
+    dev = torch.device("cuda", 0)
+    G = len(graphs)
+    dsrc = [torch.from_numpy(s).to(dev) for s in srcs]
+    ns = [len(s) for s in srcs]
+    nb = [(k + W - 1) // W for k in ns]
+    outs = [{"S": torch.empty(n, dtype=torch.int64, device=dev), "R": torch.empty(n, dtype=torch.int32, device=dev),
+             "cc": None, "h2": None} for _ in graphs]
+    ccs = [torch.empty(n, dtype=torch.float64, device=dev) for _ in graphs]
+    levels = [torch.zeros(b, dtype=torch.int32, device=dev) for b in nb]
+    ws = P.workspace(max(P.closeness_workspace_size(n, g.nnz, k, W) for g, k in zip(graphs, ns)), dev)
+    stream = torch.cuda.current_stream()
+
+    def step(events=None):
+        for gi, g in enumerate(graphs):
+            if events is not None:
+                events[gi][0].record(stream)
+            P.hln_closeness_layer(g, sources=dsrc[gi], width_bits=W, out=outs[gi], ws=ws, levels=levels[gi],
+                                  direction=args.direction, per_vertex=True)
+            if events is not None:
+                events[gi][1].record(stream)
+            P.hln_closeness_estimate(n, pops[gi], dsrc[gi], outs[gi]["S"], outs[gi]["R"], cc=ccs[gi])
+            if events is not None:
+                events[gi][2].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    P.device_status()
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    events = [[(ev(), ev(), ev()) for _ in range(G)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(events[s])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    P.device_status()
+    lv = [x.cpu().numpy().astype(np.int64) for x in levels]
+    nnz = [g.nnz for g in graphs]
+    bytes_per_launch = [int(lv[gi].sum()) * (4 * (n + 1) + 4 * nnz[gi] + 4 * n * W // 8) + 20 * n for gi in range(G)]
+    d_bfs = [[events[s][gi][0].elapsed_time(events[s][gi][1]) / 1e3 for gi in range(G)] for s in range(args.steps)]
+    d_est = [[events[s][gi][1].elapsed_time(events[s][gi][2]) / 1e3 for gi in range(G)] for s in range(args.steps)]
+    bfs_total = sum(sum(d) for d in d_bfs)
+    est_total = sum(sum(d) for d in d_est)
+    achieved = sum(bytes_per_launch) * args.steps / bfs_total / 1e9
+
+    # accuracy on the AND graph against its exact closeness (outside the timed region)
+    gi = G - 1
+    g = graphs[gi]
+    t_ex = time.perf_counter()
+    ex = P.hln_closeness_layer(g, width_bits=4096 if n * 512 < 2 ** 31 else 2048, want_cc=True)
+    torch.cuda.synchronize()
+    t_ex = time.perf_counter() - t_ex
+    exact = ex["cc"].cpu().numpy()
+    est = ccs[gi].cpu().numpy()
+    pos = exact > 0
+    rel = np.abs(est[pos] - exact[pos]) / exact[pos]
+    k = max(1, int(np.ceil(0.01 * pops[gi])))
+    truth = np.lexsort((np.arange(n), -exact))[:k]
+    thr = exact[truth[-1]]
+    top_est = np.lexsort((np.arange(n), -est))[:k]
+    n_cand = max(k, int(np.ceil(0.02 * pops[gi])))
+    cand = np.lexsort((np.arange(n), -est))[:n_cand].astype(np.int32)
+    ref = P.hln_closeness_layer(g, sources=torch.from_numpy(cand).to(dev), width_bits=W)
+    torch.cuda.synchronize()
+    cc_c = ref["cc"].cpu().numpy()
+    refined = cand[np.lexsort((np.arange(n_cand), -cc_c))[:k]]
+    acc = {"graph": "AND", "population": pops[gi], "sample": ns[gi], "exact_all_source_s": round(t_ex, 2),
+           "rel_err_median": float(np.median(rel)), "rel_err_p99": float(np.quantile(rel, 0.99)),
+           "rel_err_max": float(rel.max()), "top1pct_k": k,
+           "top1pct_precision_estimate": float(np.mean(exact[top_est] >= thr)),
+           "top1pct_precision_refined_2pct": float(np.mean(exact[refined] >= thr))}
+    log("accuracy", acc)
+    rec = {"metric": METRIC, "value": round(sum(teps_den) * args.steps / elapsed / 1e9, 3), "unit": "GTEPS",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(elapsed * 1000 / args.steps, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "i64", "data": "synthetic",
+           "config": {"workload": "6 R-MAT layers (n=1,000,000, m=8,000,000 each, 25% shared) + AND graph: sampling "
+                                  "estimate of every vertex's closeness from 16,384 seeded sources per graph", "n": n,
+                      "source_batch": W, "graphs": G, "sources_per_graph": ns, "populations": pops,
+                      "teps_edges_per_step": int(sum(teps_den))},
+           "estimate_ms_per_graph": round(est_total / (G * args.steps) * 1e3, 4),
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": "k_closeness (persistent multi-source BFS, listed sources, per-vertex sums)",
+                        "avg_launch_ms": round(bfs_total / (G * args.steps) * 1e3, 3),
+                        "algorithmic_bytes_per_launch": bytes_per_launch,
+                        "levels_per_launch": [int(x.sum()) for x in lv]},
+           "accuracy": acc}
+    print(json.dumps(rec), flush=True)
+
+
 def run_cfg4(args):
     """6 R-MAT layers over 1,000,000 vertices (avg degree 16, 25% shared) and
     their AND graph; exact closeness from 16,384 seeded sources per graph
@@ -390,22 +523,9 @@ def run_cfg4(args):
     7 graphs from their sources (CSR built once, outside the timed region)."""
     import torch
     import paper_2207_11662_amd as P
-    from paper_2207_11662_amd import proposer as PR
-    from homln_inputs import configs as C
     W = args.width or 512
-    t_gen = time.perf_counter()
-    h = C.config4(workers=8, progress=lambda s: log("%s (%.0fs)" % (s, time.perf_counter() - t_gen)))
-    n = h.n
-    A_eu, A_ev = and_edges(n, h.layers)
-    edges = list(h.layers) + [(A_eu, A_ev)]
-    srcs = [C.config4_sources(gi, np.bincount(np.concatenate([eu, ev]), minlength=n)) for gi, (eu, ev) in enumerate(edges)]
-    teps_den = [source_edge_sum(n, eu, ev, s) for (eu, ev), s in zip(edges, srcs)]
-    log("generated config 4 in %.0fs; AND graph %d edges" % (time.perf_counter() - t_gen, len(A_eu)))
+    h, n, A_eu, graphs, srcs, teps_den, _ = cfg4_setup()
     dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
-    layers = PR.upload_homln(h)
-    g_and = P.hln_compose_and(layers).trimmed()
-    graphs = layers + [g_and]
     G = len(graphs)
     dsrc = [torch.from_numpy(s).to(dev) for s in srcs]
     ns = [len(s) for s in srcs]

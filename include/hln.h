@@ -57,12 +57,16 @@ typedef struct {
     const int32_t* col_idx;   /* [dev] nnz */
 } hln_csr;
 
+/* hln_opts.flags: listed sources, sums accumulated per vertex (sampling
+ * estimate of closeness, hln_closeness_estimate). */
+#define HLN_FLAG_PER_VERTEX 1
+
 /* Source-batch width and traversal direction of the bit-parallel BFS. */
 typedef struct {
     int32_t width_bits;   /* sources per batch: 64, 128, 256, 512, 1024, 2048 or 4096; 0 = library default
                              (512); n * width_bits / 8 must be below 2^31 (HLN_EUNSUPPORTED otherwise) */
     int32_t direction;    /* 0 = automatic per level, 1 = top-down only, 2 = bottom-up only */
-    int32_t flags;        /* reserved, must be 0 */
+    int32_t flags;        /* 0 or HLN_FLAG_PER_VERTEX (see hln_closeness_layer) */
     int32_t* levels;      /* [dev] nullable: per batch of width_bits sources, the BFS levels run
                              (1 + the largest eccentricity among the batch's sources) */
     int64_t* trace;       /* [dev] nullable, zero-filled by the caller: per level run (in order, over
@@ -132,12 +136,41 @@ hln_status hln_compose_or(const hln_csr* layers, int32_t r, int32_t* out_row_ptr
  * R  [dev] int32: number of reachable vertices, the source included.
  * cc [dev] double, nullable: ((R-1)/S) * ((R-1)/(n-1)) rounded in that
  *   order (IEEE division), 0 when R <= 1 or n <= 1.
- * h2 [dev] int32, nullable: vertices at distance exactly 2.
- * opts [host] nullable (defaults).  0 <= n_src; n >= 1. */
+ * h2 [dev] int32, nullable: vertices at distance exactly 2 (all-source
+ *   mode only; HLN_EUNSUPPORTED with listed sources).
+ * opts [host] nullable (defaults).  0 <= n_src; n >= 1.
+ * opts->flags = HLN_FLAG_PER_VERTEX (listed sources only; cc and h2 must be
+ *   NULL): the outputs are indexed by vertex (n entries) and hold sums over
+ *   the listed sources, S[v] = sum of d(s, v) over listed s reaching v and
+ *   R[v] = how many listed s reach v (v itself when listed; a repeated id
+ *   counts each time).  n_src = 0 writes zeros (sources may then be NULL).
+ *   These are the sample sums
+ *   hln_closeness_estimate takes. */
 size_t hln_closeness_workspace_size(int32_t n, int64_t nnz, int32_t n_src, const hln_opts* opts);
 hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t n_src, const hln_opts* opts,
                                int64_t* S, int32_t* R, double* cc, int32_t* h2,
                                void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Sampling estimate of every vertex's closeness (Sec. 2: the sampling
+ * approximations of closeness it cites, Eppstein-Wang and Cohen et al.).
+ * ------------------------------------------------------------------------
+ * S, R [dev] n entries: the per-vertex sums of a sample of k distinct
+ *   sources (hln_closeness_layer with HLN_FLAG_PER_VERTEX over the same
+ *   list); sources [dev] k ids, the sample, drawn uniformly from a
+ *   population of n_pop vertices (vertices outside it are taken to reach
+ *   none of it).
+ * cc [dev] double, n entries, output.  With q = R[v] - [v sampled] and
+ *   k' = k - [v sampled]:
+ *     cc[v] = (q / S[v]) * (q / k') * ((n_pop - 1) / (n - 1)),
+ *   rounded in that order (IEEE division), 0 when q = 0, S[v] = 0, k' = 0
+ *   or n = 1.  A sample of every vertex (k = n_pop = n) gives the exact
+ *   closeness of hln_closeness_layer bit for bit.
+ * 1 <= n, 1 <= n_pop <= n, 0 <= k <= n_pop, else HLN_EINVAL.  A sample id
+ * outside [0, n) is a device-side fault (HLN_EDEVICE at hln_device_status).
+ * No workspace; cc may not alias S or R. */
+hln_status hln_closeness_estimate(int32_t n, int32_t n_pop, const int32_t* sources, int32_t k,
+                                  const int64_t* S, const int32_t* R, double* cc, void* stream);
 
 /* ------------------------------------------------------------------------
  * CC-node selection and composition (Theta step).

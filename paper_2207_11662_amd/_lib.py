@@ -23,7 +23,7 @@ EXPORTS = [
     "hln_last_error", "hln_version", "hln_device_cu_count", "hln_device_status",
     "hln_csr_from_edges_workspace_size", "hln_csr_from_edges", "hln_csr_validate",
     "hln_compose_workspace_size", "hln_compose_and", "hln_compose_or",
-    "hln_closeness_workspace_size", "hln_closeness_layer",
+    "hln_closeness_workspace_size", "hln_closeness_layer", "hln_closeness_estimate",
     "hln_compose_cc_topk_workspace_size", "hln_compose_cc_topk",
     "hln_plan_create", "hln_plan_destroy", "hln_plan_width", "hln_closeness_batch_workspace_size",
     "hln_closeness_batch", "hln_plan_tune", "hln_plan_capture", "hln_plan_replay", "hln_plan_reserve",
@@ -32,6 +32,7 @@ EXPORTS = [
 ]
 
 HLN_RANK_WF, HLN_RANK_CC2, HLN_RANK_NAIVE = 0, 1, 2
+HLN_FLAG_PER_VERTEX = 1
 
 
 class HlnError(RuntimeError):
@@ -78,6 +79,7 @@ def lib():
         "hln_compose_or": ([csr_p, i32, P, P, i64, P, sz, P], st),
         "hln_closeness_workspace_size": ([i32, i64, i32, opts_p], sz),
         "hln_closeness_layer": ([csr_p, P, i32, opts_p, P, P, P, P, P, sz, P], st),
+        "hln_closeness_estimate": ([i32, i32, P, i32, P, P, P, P], st),
         "hln_compose_cc_topk_workspace_size": ([i32], sz),
         "hln_compose_cc_topk": ([i32, i32, i32, P, P, i32, P, P, P, P, sz, P], st),
         "hln_plan_create": ([ctypes.POINTER(ctypes.c_void_p)], st),
@@ -176,21 +178,27 @@ def closeness_workspace_size(n: int, nnz: int, n_src: int, width_bits: int = 512
 def hln_closeness_layer(g: Graph, sources: torch.Tensor | None = None, width_bits: int = 512,
                         direction: int = 0, want_cc: bool = True, want_h2: bool = False,
                         out=None, ws: torch.Tensor | None = None, stream=None, levels: torch.Tensor | None = None,
-                        trace: torch.Tensor | None = None):
+                        trace: torch.Tensor | None = None, per_vertex: bool = False):
     """Returns dict(S int64, R int32, cc float64 | None, h2 int32 | None).
     `levels` (int32, ceil(n_src / width_bits) entries) receives the BFS levels
     run per source batch; `trace` (int64 [levels, 4], zero-filled) the
-    per-level trace described in include/hln.h."""
+    per-level trace described in include/hln.h.  `per_vertex` (listed
+    sources only, no cc): S and R per vertex, summed over the sources
+    (HLN_FLAG_PER_VERTEX)."""
     dev = g.row_ptr.device
     n_src = g.n if sources is None else int(sources.numel())
     if sources is not None:
         assert sources.dtype == torch.int32 and sources.is_cuda and sources.is_contiguous()
+    n_out = g.n if per_vertex else n_src
+    if per_vertex:
+        want_cc = False
     if out is None:
-        out = {"S": torch.empty(max(n_src, 1), dtype=torch.int64, device=dev),
-               "R": torch.empty(max(n_src, 1), dtype=torch.int32, device=dev),
-               "cc": torch.empty(max(n_src, 1), dtype=torch.float64, device=dev) if want_cc else None,
-               "h2": torch.empty(max(n_src, 1), dtype=torch.int32, device=dev) if want_h2 else None}
-    o = hln_opts(width_bits, direction, 0, None if levels is None else levels.data_ptr(),
+        out = {"S": torch.empty(max(n_out, 1), dtype=torch.int64, device=dev),
+               "R": torch.empty(max(n_out, 1), dtype=torch.int32, device=dev),
+               "cc": torch.empty(max(n_out, 1), dtype=torch.float64, device=dev) if want_cc else None,
+               "h2": torch.empty(max(n_out, 1), dtype=torch.int32, device=dev) if want_h2 else None}
+    o = hln_opts(width_bits, direction, HLN_FLAG_PER_VERTEX if per_vertex else 0,
+                 None if levels is None else levels.data_ptr(),
                  None if trace is None else trace.data_ptr(), 0 if trace is None else trace.shape[0])
     need = int(lib().hln_closeness_workspace_size(g.n, g.nnz, n_src, ctypes.byref(o)))
     if ws is None or ws.numel() < need:
@@ -199,7 +207,21 @@ def hln_closeness_layer(g: Graph, sources: torch.Tensor | None = None, width_bit
     check(lib().hln_closeness_layer(ctypes.byref(gc), _ptr(sources), n_src, ctypes.byref(o),
                                     _ptr(out["S"]), _ptr(out["R"]), _ptr(out["cc"]), _ptr(out["h2"]),
                                     _ptr(ws), ws.numel(), _stream(stream)))
-    return {k: (v[:n_src] if v is not None else None) for k, v in out.items()}
+    return {k: (v[:n_out] if v is not None else None) for k, v in out.items()}
+
+
+def hln_closeness_estimate(n: int, n_pop: int, sources: torch.Tensor, S: torch.Tensor, R: torch.Tensor,
+                           cc: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Sampling estimate of every vertex's closeness from per-vertex sample
+    sums (hln_closeness_layer(..., per_vertex=True) over `sources`)."""
+    assert sources.dtype == torch.int32 and sources.is_contiguous()
+    assert S.dtype == torch.int64 and R.dtype == torch.int32 and S.numel() >= n and R.numel() >= n
+    if cc is None:
+        cc = torch.empty(max(n, 1), dtype=torch.float64, device=S.device)
+    assert cc.dtype == torch.float64 and cc.numel() >= n
+    check(lib().hln_closeness_estimate(n, n_pop, _ptr(sources), int(sources.numel()), _ptr(S), _ptr(R), _ptr(cc),
+                                       _stream(stream)))
+    return cc[:n]
 
 
 # ---------------------------------------------------------------------------

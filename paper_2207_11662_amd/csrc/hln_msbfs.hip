@@ -30,6 +30,10 @@
 //     counts the new bits at d = 2.
 //   listed sources: per-source counts c_i(d) = #{v : bit i new at d} are
 //     gathered per block in LDS and reduced over blocks at the batch end.
+//   listed sources, per-vertex sums (HLN_FLAG_PER_VERTEX): as for all
+//     sources, so S[v] and R[v] sum over the listed sources only (the sums
+//     a sampling estimator of closeness needs); R[v] starts at 0 and every
+//     listed occurrence of v adds 1.
 //
 // Execution: one cooperative persistent launch per call.  All batches and
 // levels run inside it, separated by grid barriers with bounded waits; the
@@ -165,6 +169,7 @@ struct BfsArgs {
     const int32_t* row_ptr;
     const int32_t* col_idx;
     const int32_t* sources;           // nullptr: all vertices, per-vertex accumulation
+    int listed;                       // sources come from the list (it may be empty)
     uint64_t* bufA;                   // n*NW
     uint64_t* bufB;                   // n*NW
     void* flagA;                      // n word masks (MaskT<NW>): bit k clear implies bufA word k of v is zero
@@ -553,7 +558,9 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
         if (!PER_SOURCE) {
             a.S[v] = 0;
             a.S32[v] = 0;
-            a.R[v] = 1;                                      // the vertex itself (d = 0)
+            // the vertex itself (d = 0); with listed sources each listed
+            // occurrence adds its own 1 at batch init
+            a.R[v] = a.listed ? 0 : 1;
             if (a.H2) a.H2[v] = 0;
         }
         a.hcnt[v] = 0;
@@ -567,7 +574,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
         const int deg = e1 - e0;
         if (deg > 0) atomicAdd(&s_bins[seg_class(deg, seg_len)], (deg + seg_len - 1) / seg_len);
     }
-    if (PER_SOURCE)
+    if (a.listed)
         for (long long i = tid; i < a.n_src; i += nthreads)
             bad |= static_cast<unsigned>(a.sources[i]) >= static_cast<unsigned>(n);
     if (bad) store_agent_i32(a.fault, 2);
@@ -632,7 +639,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                 store_agent_i32(&ctrl->fbad[nx_slot], 0);
                 __hip_atomic_store(&ctrl->farcs[nx_slot], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            if (!PER_SOURCE) {
+            if (!PER_SOURCE && !a.listed) {
                 for (long long i = tid; i < static_cast<long long>(n) * NW; i += nthreads) {
                     const long long v = i / NW;
                     const int kk = static_cast<int>(i % NW);
@@ -661,18 +668,30 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                     a.vis[i] = 0;
                     a.bufA[i] = 0;
                 }
-                for (long long v = tid; v < n; v += nthreads) static_cast<Mask*>(a.flagA)[v] = 0;
-                for (int i = threadIdx.x; i < W; i += BLOCK) {
-                    s_cnt[i] = 0;
-                    s_S[i] = 0;
-                    s_R[i] = 0;
+                for (long long v = tid; v < n; v += nthreads) {
+                    static_cast<Mask*>(a.flagA)[v] = 0;
+                    if (!PER_SOURCE) {
+                        // per-vertex sums: the previous batch's 32-bit sums into S
+                        const uint32_t x = a.S32[v];
+                        if (x) {
+                            a.S[v] += x;
+                            a.S32[v] = 0;
+                        }
+                    }
                 }
+                if (PER_SOURCE)
+                    for (int i = threadIdx.x; i < W; i += BLOCK) {
+                        s_cnt[i] = 0;
+                        s_S[i] = 0;
+                        s_R[i] = 0;
+                    }
                 if (!gb.wait()) return;
                 for (long long i = tid_x; i < cnt; i += nthreads) {
                     const int s = a.sources[src0 + i];
                     const size_t w = static_cast<size_t>(s) * NW + (i >> 6);
                     atomicOr(reinterpret_cast<unsigned long long*>(&a.vis[w]), 1ull << (i & 63));
                     atomicOr(reinterpret_cast<unsigned long long*>(&a.bufA[w]), 1ull << (i & 63));
+                    if (!PER_SOURCE) atomicAdd(&a.R[s], 1);      // per-vertex sums: the source reaches itself
                     // the first source bit on a vertex lists it (once, even if
                     // the vertex is listed as a source more than once)
                     if (atomicOr(&static_cast<Mask*>(a.flagA)[s], static_cast<Mask>(static_cast<Mask>(1) << (i >> 6))) == 0) {
@@ -943,15 +962,16 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
     }
 
     // ---- closeness (Eq. 1, Wasserman-Faust form, fixed operation order);
-    // all-source mode first folds the last batch's 32-bit sums into S (the
-    // same thread reads and writes each vertex, after the final level
-    // barrier)
+    // per-vertex sums (all-source or listed) first fold the last batch's
+    // 32-bit sums into S (the same thread reads and writes each vertex, after
+    // the final level barrier)
     if (PER_SOURCE) {
         // listed sources: the last writes of S and R are the reduction above
         if (a.cc && !gb.wait()) return;
     }
     if (!PER_SOURCE || a.cc) {
-        for (long long i = tid; i < a.n_src; i += nthreads) {
+        const long long n_out = PER_SOURCE ? a.n_src : n;
+        for (long long i = tid; i < n_out; i += nthreads) {
             int64_t sv = a.S[i];
             if (!PER_SOURCE) {
                 sv += a.S32[i];
@@ -1110,10 +1130,16 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
     if (g->nnz < 0 || g->nnz > 0x7fffffffLL) return fail(HLN_EINVAL, "nnz out of range (%lld)", (long long)g->nnz);
     if (!g->row_ptr || (g->nnz > 0 && !g->col_idx)) return fail(HLN_EINVAL, "graph arrays are NULL");
     if (!S || !R) return fail(HLN_EINVAL, "S and R outputs are required");
-    if (!sources && n_src != g->n) return fail(HLN_EINVAL, "all-source mode needs n_src == n (%d != %d)", n_src, g->n);
+    const int32_t flags = opts ? opts->flags : 0;
+    if (flags & ~HLN_FLAG_PER_VERTEX) return fail(HLN_EINVAL, "unknown opts->flags bits 0x%x", flags);
+    const bool per_vertex = (flags & HLN_FLAG_PER_VERTEX) != 0;
     if (n_src < 0) return fail(HLN_EINVAL, "n_src < 0");
-    if (sources && h2) return fail(HLN_EUNSUPPORTED, "h2 is produced in all-source mode only");
-    if (opts && opts->flags != 0) return fail(HLN_EINVAL, "opts->flags must be 0");
+    // per-vertex sums always take a list; an empty one may be NULL
+    if (per_vertex && !sources && n_src > 0) return fail(HLN_EINVAL, "HLN_FLAG_PER_VERTEX needs listed sources");
+    if (!sources && !per_vertex && n_src != g->n)
+        return fail(HLN_EINVAL, "all-source mode needs n_src == n (%d != %d)", n_src, g->n);
+    if ((sources || per_vertex) && h2) return fail(HLN_EUNSUPPORTED, "h2 is produced in all-source mode only");
+    if (per_vertex && cc) return fail(HLN_EINVAL, "HLN_FLAG_PER_VERTEX gives sums only: cc must be NULL");
     if (opts && (opts->direction < 0 || opts->direction > 2)) return fail(HLN_EINVAL, "bad direction %d", opts->direction);
     const int nw = width_words(opts);
     if (nw == 0) return fail(HLN_EINVAL, "width_bits must be 64, 128, 256, 512, 1024, 2048 or 4096");
@@ -1130,7 +1156,7 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
     const size_t need = workspace_bytes(g->n, g->nnz, nw, grid_cap);
     if (workspace_bytes_in < need)
         return fail(HLN_ENOMEM, "workspace too small: %zu < %zu bytes", workspace_bytes_in, need);
-    if (n_src == 0) return HLN_OK;
+    if (n_src == 0 && !per_vertex) return HLN_OK;    // per-vertex mode still writes zero sums
     int* fault = hln::fault_word();
     if (!fault) return HLN_EDEVICE;
 
@@ -1143,6 +1169,7 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
     a.row_ptr = g->row_ptr;
     a.col_idx = g->col_idx;
     a.sources = sources;
+    a.listed = (sources != nullptr || per_vertex) ? 1 : 0;
     a.ctrl = ar.take<Ctrl>(1);
     a.bar = ar.take<unsigned long long>(hln::dev::kBarrierWords);
     a.bufA = ar.take<uint64_t>(words);
@@ -1181,7 +1208,7 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
 
     // enough groups to cover the segments, capped by co-residency
     const long long want_threads = (static_cast<long long>(n) + g->nnz / kSegLen + 1) * std::max(8, nw);
-    const bool ps = sources != nullptr;
+    const bool ps = sources != nullptr && !per_vertex;
     switch (nw) {
         case 1: return dispatch_block<1>(a, ps, want_threads, grid_cap, di->cus, st);
         case 2: return dispatch_block<2>(a, ps, want_threads, grid_cap, di->cus, st);

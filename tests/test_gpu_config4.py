@@ -56,3 +56,43 @@ def test_config4_listed_sources_sampled(cfg4):
         adj = sp.csr_matrix((np.ones(len(ci), np.int8), ci, rp), shape=(n, n))
         _, lab = connected_components(adj, directed=False)
         assert np.array_equal(R_g, np.bincount(lab)[lab[src]]), gi
+
+
+@pytest.mark.timeout(1200)
+def test_config4_sample_estimate_sampled(cfg4):
+    """Per-vertex sums over each graph's 16,384-source sample and the
+    estimate for all 1,000,000 vertices: sampled vertices against one oracle
+    BFS each (sums bit-exact, estimate bit-exact through the oracle's
+    estimator); over all vertices, the sums add up to the per-source sums of
+    the listed-source mode."""
+    h, host = cfg4
+    n = h.n
+    dev_layers = PR.upload_homln(h)
+    g_and = P.hln_compose_and(dev_layers).trimmed()
+    graphs = dev_layers + [g_and]
+    rng = np.random.default_rng(45)
+    for gi in (0, 3, 6):
+        g, (rp, ci) = graphs[gi], host[gi]
+        deg = np.diff(rp)
+        src = C.config4_sources(gi, deg)
+        n_pop = int((deg > 0).sum())
+        say("graph", gi, "sample", len(src), "population", n_pop)
+        dsrc = to_dev(src)
+        pv = P.hln_closeness_layer(g, sources=dsrc, width_bits=512, per_vertex=True)
+        cc = P.hln_closeness_estimate(n, n_pop, dsrc, pv["S"], pv["R"])
+        ps = P.hln_closeness_layer(g, sources=dsrc, width_bits=512, want_cc=False)
+        torch.cuda.synchronize()
+        P.device_status()
+        S_g, R_g, cc_g = pv["S"].cpu().numpy(), pv["R"].cpu().numpy(), cc.cpu().numpy()
+        assert int(S_g.sum()) == int(ps["S"].sum().item()), gi
+        assert int(R_g.sum()) == int(ps["R"].to(torch.int64).sum().item()), gi
+        assert R_g.max() <= len(src)
+        verts = np.sort(np.concatenate([rng.choice(n, size=20, replace=False), src[:4]])).astype(np.int32)
+        SQ, RQ = O.sample_sums_at(rp, ci, src, verts)
+        assert np.array_equal(S_g[verts], SQ), gi
+        assert np.array_equal(R_g[verts], RQ), gi
+        SQf = np.zeros(n, np.int64)
+        RQf = np.zeros(n, np.int32)
+        SQf[verts], RQf[verts] = SQ, RQ
+        exp = O.sample_estimate(n, n_pop, src, SQf, RQf)
+        assert np.array_equal(cc_g[verts].view(np.int64), exp[verts].view(np.int64)), gi
