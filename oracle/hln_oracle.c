@@ -479,3 +479,119 @@ void oracle_sample_estimate(int32_t n, int32_t n_pop, int32_t k, const uint8_t* 
         }
     }
 }
+
+/* ------------------------------------------------------------------ */
+/* Heuristic CC1 (Sec. 5.1, Eq. 2-3).  The paper describes it in words  */
+/* and does not print the algorithm; the readings taken here:           */
+/*   - sumDist is the penalised sum P = S + n(n - R) (unreachable at    */
+/*     distance n, Sec. 5.1);                                           */
+/*   - Eq. 2 with r layers: ratio_l(u) = P_l(u) / m(u), m(u) = the      */
+/*     smallest degree of u over the layers (the AND graph's degree     */
+/*     bound); a vertex with m(u) = 0 has no ratio: it is never central */
+/*     and is left out of the average;                                  */
+/*   - avg_l = mean of ratio_l over the vertices with m > 0, summed in  */
+/*     the fixed shape of oracle_mean_fixed_shape; Eq. 3: the AND       */
+/*     graph's average = the largest avg_l;                             */
+/*   - central: ratio strictly below that average;                      */
+/*   - CH_l = the above-average closeness set of layer l (Sec. 4);      */
+/*   - a common CC node c (in every CH_l) is kept when its central      */
+/*     neighbour sets C_l(c) overlap significantly: with I = the        */
+/*     intersection of the C_l(c) and s = the smallest |C_l(c)|,        */
+/*     s > 0 and |I| / s >= tau = tau_num / tau_den (compared as        */
+/*     |I| * tau_den >= tau_num * s in integers).                       */
+/* ------------------------------------------------------------------ */
+
+/* central: a ratio exists (m > 0) and lies strictly below the average */
+static int cc1_central(int32_t m, double ratio, double avg) {
+    return m > 0 && ratio < avg;
+}
+
+static int in_row(const int32_t* row_ptr, const int32_t* col_idx, int32_t u, int32_t v) {
+    for (int32_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e)
+        if (col_idx[e] == v) return 1;
+    return 0;
+}
+
+/* ids ascending of the CC1 nodes; returns how many, -1 on bad arguments,
+ * -2 on allocation failure.  avg_out (nullable) receives Eq. 3's value. */
+int32_t oracle_cc1(int32_t n, int32_t r, const int32_t* const* row_ptr, const int32_t* const* col_idx,
+                   const int64_t* const* S, const int32_t* const* R, int32_t tau_num, int32_t tau_den,
+                   int32_t* ids, double* avg_out) {
+    if (n < 1 || r < 1 || tau_num < 0 || tau_den < 1) return -1;
+    int32_t* m = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    double* ratio = (double*)malloc(sizeof(double) * (size_t)n * (size_t)r);
+    double* cc = (double*)malloc(sizeof(double) * (size_t)n);
+    int32_t* tmp = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    char* common = (char*)malloc((size_t)n);
+    char* keep = (char*)malloc((size_t)n);
+    if (!m || !ratio || !cc || !tmp || !common || !keep) {
+        free(m); free(ratio); free(cc); free(tmp); free(common); free(keep);
+        return -2;
+    }
+    /* the AND graph's degree bound */
+    for (int32_t u = 0; u < n; ++u) {
+        int32_t best = 0;
+        for (int32_t l = 0; l < r; ++l) {
+            int32_t d = row_ptr[l][u + 1] - row_ptr[l][u];
+            if (l == 0 || d < best) best = d;
+        }
+        m[u] = best;
+    }
+    /* Eq. 2 per layer, and its average over vertices with a ratio */
+    double avg = 0.0;
+    for (int32_t l = 0; l < r; ++l) {
+        double* x = ratio + (size_t)l * (size_t)n;
+        int32_t valid = 0;
+        for (int32_t u = 0; u < n; ++u) {
+            int64_t P = S[l][u] + (int64_t)n * (int64_t)(n - R[l][u]);
+            x[u] = m[u] > 0 ? (double)P / (double)m[u] : 0.0;
+            valid += m[u] > 0;
+        }
+        double total = 0.0;
+        for (int32_t c = 0; c < n; c += 1024) {
+            double part = 0.0;
+            int32_t end = c + 1024 < n ? c + 1024 : n;
+            for (int32_t u = c; u < end; ++u)
+                if (m[u] > 0) part += x[u];
+            total += part;
+        }
+        double avg_l = valid > 0 ? total / (double)valid : 0.0;
+        if (l == 0 || avg_l > avg) avg = avg_l;       /* Eq. 3: the larger average */
+    }
+    if (avg_out) *avg_out = avg;
+    /* common CC nodes */
+    for (int32_t u = 0; u < n; ++u) common[u] = 1;
+    for (int32_t l = 0; l < r; ++l) {
+        oracle_closeness_wf(n, n, S[l], R[l], cc);
+        int32_t c = oracle_above_mean(n, cc, tmp);
+        for (int32_t u = 0; u < n; ++u) keep[u] = 0;
+        for (int32_t i = 0; i < c; ++i) keep[tmp[i]] = 1;
+        for (int32_t u = 0; u < n; ++u) common[u] = common[u] && keep[u];
+    }
+    /* overlap of the central neighbour sets */
+    int32_t count = 0;
+    for (int32_t c = 0; c < n; ++c) {
+        if (!common[c]) continue;
+        int64_t smallest = -1;
+        for (int32_t l = 0; l < r; ++l) {
+            const double* x = ratio + (size_t)l * (size_t)n;
+            int64_t size = 0;
+            for (int32_t e = row_ptr[l][c]; e < row_ptr[l][c + 1]; ++e) {
+                int32_t v = col_idx[l][e];
+                size += cc1_central(m[v], x[v], avg);
+            }
+            if (smallest < 0 || size < smallest) smallest = size;
+        }
+        int64_t inter = 0;
+        for (int32_t e = row_ptr[0][c]; e < row_ptr[0][c + 1]; ++e) {
+            int32_t v = col_idx[0][e];
+            int all = 1;
+            for (int32_t l = 0; l < r && all; ++l)
+                all = in_row(row_ptr[l], col_idx[l], c, v) && cc1_central(m[v], ratio[(size_t)l * (size_t)n + v], avg);
+            inter += all;
+        }
+        if (smallest > 0 && inter * (int64_t)tau_den >= (int64_t)tau_num * smallest) ids[count++] = c;
+    }
+    free(m); free(ratio); free(cc); free(tmp); free(common); free(keep);
+    return count;
+}

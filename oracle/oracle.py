@@ -72,6 +72,8 @@ def _bind(path: str):
     L.oracle_sample_sums_at.restype = ctypes.c_int
     L.oracle_sample_estimate.argtypes = [i32, i32, i32, P, P, P, P]
     L.oracle_sample_estimate.restype = None
+    L.oracle_cc1.argtypes = [i32, i32, P, P, P, P, i32, i32, P, P]
+    L.oracle_cc1.restype = i32
     return L
 
 
@@ -264,6 +266,26 @@ def naive(n: int, cc_list):
     if c < 0:
         raise ValueError("oracle_naive failed")
     return ids[:c].copy()
+
+
+def cc1(n: int, layers, S_list, R_list, tau=(1, 2), with_avg: bool = False):
+    """CC1 nodes (ids ascending) of the layers' AND graph from the layers'
+    CSR (row_ptr, col_idx) and all-source S, R; tau = (num, den) is the
+    overlap threshold.  With `with_avg`, also Eq. 3's average."""
+    L = _load()
+    r = len(layers)
+    rps = [_c(rp, np.int32) for rp, _ in layers]
+    cis = [_c(ci, np.int32) if len(ci) else np.zeros(1, np.int32) for _, ci in layers]
+    Ss = [_c(S, np.int64) for S in S_list]
+    Rs = [_c(R, np.int32) for R in R_list]
+    arr = lambda xs: ctypes.cast((ctypes.c_void_p * r)(*[a.ctypes.data for a in xs]), ctypes.c_void_p)  # noqa: E731
+    ids = np.zeros(max(n, 1), np.int32)
+    avg = np.zeros(1, np.float64)
+    c = L.oracle_cc1(n, r, arr(rps), arr(cis), arr(Ss), arr(Rs), int(tau[0]), int(tau[1]), _p(ids), _p(avg))
+    if c < 0:
+        raise ValueError("oracle_cc1 failed (%d)" % c)
+    out = ids[:c].copy()
+    return (out, float(avg[0])) if with_avg else out
 
 
 def sample_mask(n: int, sources) -> np.ndarray:

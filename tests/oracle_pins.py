@@ -454,7 +454,115 @@ def pin_sample_estimate_bound(o):
     assert np.all(np.abs(1.0 / est - 1.0 / exact) <= eps + 1e-9)
 
 
+def cc1_brute(n, adjs, tau):
+    """CC1 from the definitions in Sec. 5.1 (Eq. 2-3) with exact rationals:
+    distances from Floyd-Warshall, sets as Python sets.  Returns (ids, tie)
+    where tie says some comparison sat within 1e-9 of its threshold (the
+    FP64 result may then round the other way)."""
+    r = len(adjs)
+    Ds = [floyd_warshall(n, a) for a in adjs]
+    m = [min(len(a[u]) for a in adjs) for u in range(n)]
+    ratios, avgs, ch = [], [], []
+    tie = False
+    for D, a in zip(Ds, adjs):
+        P = [int(sum(d if np.isfinite(d) else n for j, d in enumerate(D[u]) if j != u)) for u in range(n)]
+        ratio = [Fraction(P[u], m[u]) if m[u] > 0 else None for u in range(n)]
+        valid = [x for x in ratio if x is not None]
+        avgs.append(sum(valid, Fraction(0)) / len(valid) if valid else Fraction(0))
+        ratios.append(ratio)
+        reach = [int(np.isfinite(D[u]).sum()) for u in range(n)]
+        S = [int(sum(d for d in D[u] if np.isfinite(d))) for u in range(n)]
+        cc = [Fraction((reach[u] - 1) ** 2, S[u] * (n - 1)) if reach[u] > 1 and S[u] > 0 and n > 1 else Fraction(0)
+              for u in range(n)]
+        mean = sum(cc, Fraction(0)) / n
+        tie |= any(x != mean and abs(x - mean) <= mean * Fraction(1, 10 ** 9) for x in cc)
+        ch.append({u for u in range(n) if cc[u] >= mean})
+    avg = max(avgs)
+    central = [{u for u in range(n) if ratios[l][u] is not None and ratios[l][u] < avg} for l in range(r)]
+    tie |= any(x is not None and x != avg and abs(x - avg) <= avg * Fraction(1, 10 ** 9) for rl in ratios for x in rl)
+    out = []
+    for c in sorted(set.intersection(*ch)):
+        sets = [adjs[l][c] & central[l] for l in range(r)]
+        small = min(len(x) for x in sets)
+        inter = len(set.intersection(*sets))
+        if small > 0 and Fraction(inter, small) >= Fraction(*tau):
+            out.append(c)
+    return out, tie
+
+
+def pin_cc1_brute_force(o):
+    """CC1 (Sec. 5.1) on small random HoMLNs of 2-3 layers (shared base plus
+    private edges, often disconnected) against the definitions with exact
+    rationals, for several overlap thresholds."""
+    rng = np.random.default_rng(31)
+    checked = 0
+    for trial in range(40):
+        n = int(rng.integers(8, 40))
+        r = int(rng.integers(2, 4))
+        bu, bv = random_graph(rng, n, 0.08)
+        edges = []
+        for _l in range(r):
+            u, v = random_graph(rng, n, 0.07)
+            edges.append((np.concatenate([u, bu]), np.concatenate([v, bv])))
+        adjs = [adjacency_sets(n, u, v) for u, v in edges]
+        layers = [csr_of(o, n, u, v) for u, v in edges]
+        sums = [o.bfs_sums(*g) for g in layers]
+        for tau in ((1, 2), (0, 1), (1, 3), (1, 1)):
+            want, tie = cc1_brute(n, adjs, tau)
+            if tie:
+                continue
+            got = o.cc1(n, layers, [x[0] for x in sums], [x[1] for x in sums], tau)
+            assert got.tolist() == want, (trial, tau)
+            checked += 1
+    assert checked >= 100
+
+
+def pin_cc1_vertex_transitive(o):
+    """Two identical cycles: every vertex has the same ratio, which is then
+    the average itself (exact in FP64 here), so no neighbour lies strictly
+    below it and CC1 is empty at every threshold, 0 included."""
+    for n in (8, 16, 32):
+        u = np.arange(n)
+        g = csr_of(o, n, u, (u + 1) % n)
+        S, R = o.bfs_sums(*g)
+        for tau in ((0, 1), (1, 2), (1, 1)):
+            ids, avg = o.cc1(n, [g, g], [S, S], [R, R], tau, with_avg=True)
+            assert avg == n * n / 8.0
+            assert len(ids) == 0
+
+
+def pin_cc1_properties(o):
+    """CC1 keeps only common CC nodes (a subset of the naive composition,
+    Sec. 4); raising the threshold never adds a node; the overlap is at most
+    1, so a threshold above 1 keeps nothing; identical layers overlap fully,
+    so every threshold up to 1 keeps the same set."""
+    rng = np.random.default_rng(37)
+    for trial in range(15):
+        n = int(rng.integers(10, 60))
+        bu, bv = random_graph(rng, n, 0.1)
+        edges = []
+        for _l in range(2):
+            u, v = random_graph(rng, n, 0.06)
+            edges.append((np.concatenate([u, bu]), np.concatenate([v, bv])))
+        layers = [csr_of(o, n, u, v) for u, v in edges]
+        sums = [o.bfs_sums(*g) for g in layers]
+        Ss, Rs = [x[0] for x in sums], [x[1] for x in sums]
+        naive = set(o.naive(n, [o.closeness_wf(n, S, R) for S, R in zip(Ss, Rs)]).tolist())
+        prev = None
+        for tau in ((0, 1), (1, 4), (1, 2), (3, 4), (1, 1), (5, 4)):
+            got = set(o.cc1(n, layers, Ss, Rs, tau).tolist())
+            assert got <= naive
+            if prev is not None:
+                assert got <= prev
+            prev = got
+        assert not prev
+        same = [set(o.cc1(n, [layers[0]] * 2, [Ss[0]] * 2, [Rs[0]] * 2, tau).tolist())
+                for tau in ((0, 1), (1, 2), (1, 1))]
+        assert same[0] == same[1] == same[2]
+
+
 PINS = [pin_closed_forms, pin_disjoint_union, pin_floyd_warshall, pin_networkx, pin_networkx_printed,
         pin_wiener_tree, pin_csr_normalisation, pin_compose_sets, pin_mean_exact, pin_above_mean,
         pin_topk, pin_cc2_worked_example, pin_cc2_bounds, pin_naive, pin_sample_sums,
-        pin_sample_estimate_full_sample, pin_sample_estimate_bound]
+        pin_sample_estimate_full_sample, pin_sample_estimate_bound, pin_cc1_brute_force, pin_cc1_vertex_transitive,
+        pin_cc1_properties]

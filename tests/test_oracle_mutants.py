@@ -38,6 +38,13 @@ MUTANTS = [
     ("sample-self-counted", "int32_t q = RQ[v] - self;", "int32_t q = RQ[v];"),
     ("sample-population-n", "double c = (double)(n_pop - 1) / (double)(n - 1);", "double c = 1.0;"),
     ("sample-sums-off-by-one", "SQ[u] += dist[u];", "SQ[u] += dist[u] + 1;"),
+    ("cc1-degree-max", "if (l == 0 || d < best) best = d;", "if (l == 0 || d > best) best = d;"),
+    ("cc1-eq3-min", "if (l == 0 || avg_l > avg) avg = avg_l;", "if (l == 0 || avg_l < avg) avg = avg_l;"),
+    ("cc1-central-not-strict", "return m > 0 && ratio < avg;", "return m > 0 && ratio <= avg;"),
+    ("cc1-unreachable-zero", "int64_t P = S[l][u] + (int64_t)n * (int64_t)(n - R[l][u]);", "int64_t P = S[l][u];"),
+    ("cc1-overlap-over-largest", "if (smallest < 0 || size < smallest) smallest = size;",
+     "if (smallest < 0 || size > smallest) smallest = size;"),
+    ("cc1-any-layer-cc", "common[u] = common[u] && keep[u];", "common[u] = common[u] || keep[u];"),
 ]
 
 
