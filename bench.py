@@ -584,8 +584,9 @@ def run_cfg4(args):
 
 
 def run_composition(args):
-    """accuracy: Jaccard / precision / recall / F1 of CC2 and naive CC-node
-    sets (above-average and top-10%) against the AND ground truth, for every
+    """accuracy: Jaccard / precision / recall / F1 of CC2, CC1 (tau = 1/2)
+    and naive CC-node sets (above-average, and top-10% for CC2 and naive)
+    against the AND ground truth, for every
     HoMLN's full layer set and layer pairs (configs 1, 2, the first 16 HoMLNs
     of config 3, config 5).  subsets: Psi once, then every subset of >= 2
     layers of configs 2 and 5: per-subset AND and OR ground truth against
@@ -607,7 +608,7 @@ def run_composition(args):
             out[name]["whole_homln_only"] = CM.summarise([r for i, r in enumerate(recs)
                                                           if len(r["subset"]) == max(len(x["subset"]) for x in recs)])
             log("%s: %d subsets in %.1fs" % (name, len(recs), time.perf_counter() - t0))
-        print(json.dumps({"metric": "CC-node set accuracy of CC2 and naive composition vs AND ground truth",
+        print(json.dumps({"metric": "CC-node set accuracy of CC2, CC1 and naive composition vs AND ground truth",
                           "unit": "Jaccard/precision/recall/F1 (means over subsets)", "data": "synthetic",
                           "k": "top 10% (ceil)", "results": out}), flush=True)
         return
@@ -618,6 +619,8 @@ def run_composition(args):
         recs = res.pop("records")
         res["per_subset"] = [{"subset": r["subset"], "t_and_gt_ms": round(r["t_and_gt_ms"], 3),
                               "t_or_gt_ms": round(r.get("t_or_gt_ms", 0.0), 3), "t_theta_ms": round(r["t_theta_ms"], 3),
+                              "t_theta_cc1_ms": round(r["t_theta_cc1_ms"], 3),
+                              "cc1_above_jaccard": round(r["cc1_above"]["jaccard"], 4),
                               "cc2_topk_jaccard": round(r["cc2_topk"]["jaccard"], 4),
                               "cc2_topk_precision": round(r["cc2_topk"]["precision"], 4)} for r in recs]
         print(json.dumps({"metric": "decoupled (Psi once + Theta per subset) vs per-subset AND ground truth",

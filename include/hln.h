@@ -199,6 +199,31 @@ hln_status hln_compose_cc_topk(int32_t mode, int32_t n, int32_t r, const int64_t
                                void* workspace, size_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Heuristic CC1 (Sec. 5.1, Eq. 2-3): CC nodes of the AND aggregate of r
+ * layers from per-layer degrees, penalised distance sums and neighbour
+ * lists.  The paper describes CC1 in words; readings:
+ *   ratio_l(u) = (S_l + n(n - R_l))(u) / m(u), m(u) = smallest degree of u
+ *     over the layers (Eq. 2); no ratio when m(u) = 0;
+ *   avg_l = mean of ratio_l over the vertices with m > 0 (fixed summation
+ *     shape: chunks of 1024 ids, chunk sums in order); avg = max_l avg_l
+ *     (Eq. 3);
+ *   v is central in layer l when m(v) > 0 and ratio_l(v) < avg;
+ *   a vertex c in every layer's above-average closeness set (Sec. 4) is kept
+ *     when, with C_l(c) = central neighbours of c in layer l, I = their
+ *     intersection and s = min_l |C_l(c)|: s > 0 and
+ *     |I| * tau_den >= tau_num * s ("significant overlap"; the paper gives
+ *     no threshold, tau = 1/2 is this library's default in the bindings).
+ * layers [host] r graphs with equal n (CSR conventions); S, R [host] arrays
+ * of r device pointers to the layers' all-source outputs of
+ * hln_closeness_layer.  ids [dev] room for n entries, written ascending;
+ * count [dev] int32; avg [dev, nullable] double: Eq. 3's value.
+ * 1 <= r <= 64, tau_num >= 0, tau_den >= 1, else HLN_EINVAL. */
+size_t hln_compose_cc1_workspace_size(int32_t n, int32_t r);   /* 0 on bad arguments */
+hln_status hln_compose_cc1(const hln_csr* layers, int32_t r, const int64_t* const* S, const int32_t* const* R,
+                           int32_t tau_num, int32_t tau_den, int32_t* ids, int32_t* count, double* avg,
+                           void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched closeness of many graphs (Sec. 3: every layer is analysed
  * independently and in parallel; the layers and AND / OR aggregates of many
  * HoMLNs in one persistent launch per source-width class).

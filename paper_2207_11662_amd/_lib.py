@@ -24,7 +24,7 @@ EXPORTS = [
     "hln_csr_from_edges_workspace_size", "hln_csr_from_edges", "hln_csr_validate",
     "hln_compose_workspace_size", "hln_compose_and", "hln_compose_or",
     "hln_closeness_workspace_size", "hln_closeness_layer", "hln_closeness_estimate",
-    "hln_compose_cc_topk_workspace_size", "hln_compose_cc_topk",
+    "hln_compose_cc_topk_workspace_size", "hln_compose_cc_topk", "hln_compose_cc1_workspace_size", "hln_compose_cc1",
     "hln_plan_create", "hln_plan_destroy", "hln_plan_width", "hln_closeness_batch_workspace_size",
     "hln_closeness_batch", "hln_plan_tune", "hln_plan_capture", "hln_plan_replay", "hln_plan_reserve",
     "hln_mlp_param_count", "hln_proposer_features", "hln_mlp_init", "hln_mlp_forward",
@@ -82,6 +82,8 @@ def lib():
         "hln_closeness_estimate": ([i32, i32, P, i32, P, P, P, P], st),
         "hln_compose_cc_topk_workspace_size": ([i32], sz),
         "hln_compose_cc_topk": ([i32, i32, i32, P, P, i32, P, P, P, P, sz, P], st),
+        "hln_compose_cc1_workspace_size": ([i32, i32], sz),
+        "hln_compose_cc1": ([P, i32, P, P, i32, i32, P, P, P, P, sz, P], st),
         "hln_plan_create": ([ctypes.POINTER(ctypes.c_void_p)], st),
         "hln_plan_destroy": ([P], None),
         "hln_plan_width": ([P, i32], i32),
@@ -311,6 +313,30 @@ def hln_compose_cc_topk(mode: int, n: int, S_list, R_list, k: int, ws=None, out=
     check(lib().hln_compose_cc_topk(mode, n, r, ctypes.cast(Sp, ctypes.c_void_p), ctypes.cast(Rp, ctypes.c_void_p),
                                     k, _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _ptr(ws), ws.numel(),
                                     _stream(stream)))
+    return out
+
+
+def hln_compose_cc1(layers, S_list, R_list, tau=(1, 2), ws=None, out=None, stream=None):
+    """CC1 nodes of the layers' AND aggregate (Sec. 5.1, readings in
+    include/hln.h).  Returns (ids, count, avg) device tensors: ids ascending
+    (the first count entries), count a 1-element int32, avg Eq. 3's value."""
+    r = len(layers)
+    n = layers[0].n
+    dev = layers[0].row_ptr.device
+    arr = (hln_csr * r)(*[g.c() for g in layers])
+    Sp = (ctypes.c_void_p * r)(*[t.data_ptr() for t in S_list])
+    Rp = (ctypes.c_void_p * r)(*[t.data_ptr() for t in R_list])
+    need = int(lib().hln_compose_cc1_workspace_size(n, r))
+    if need == 0:
+        raise HlnError(1, "hln_compose_cc1_workspace_size: bad arguments (n=%d, r=%d)" % (n, r))
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, dev)
+    if out is None:
+        out = (torch.empty(max(n, 1), dtype=torch.int32, device=dev), torch.empty(1, dtype=torch.int32, device=dev),
+               torch.empty(1, dtype=torch.float64, device=dev))
+    check(lib().hln_compose_cc1(ctypes.cast(arr, ctypes.c_void_p), r, ctypes.cast(Sp, ctypes.c_void_p),
+                                ctypes.cast(Rp, ctypes.c_void_p), int(tau[0]), int(tau[1]), _ptr(out[0]), _ptr(out[1]),
+                                _ptr(out[2]), _ptr(ws), ws.numel(), _stream(stream)))
     return out
 
 

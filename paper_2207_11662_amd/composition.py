@@ -6,9 +6,10 @@ aggregate from those per-layer results alone (Theta).  This module measures
 how well it does:
 
 * `study_subset`: for one layer subset, the ground truth (AND aggregate,
-  exact closeness, Sec. 4) against CC2 (Sec. 5.2, Algorithm 1) and the naive
-  composition (intersection of the layers' CC-node sets, Sec. 4), for the
-  above-average CC-node sets and for the top-k sets.  Scores: Jaccard
+  exact closeness, Sec. 4) against CC2 (Sec. 5.2, Algorithm 1), CC1 (Sec.
+  5.1, Eq. 2-3; a CC-node set, no ranking) and the naive composition
+  (intersection of the layers' CC-node sets, Sec. 4), for the above-average
+  CC-node sets and, for CC2 and naive, the top-k sets.  Scores: Jaccard
   coefficient (the paper's "accuracy"), precision, recall and F1 (Sec. 5,
   Sec. 6.1).
 * `subsets_sweep`: Psi once, then every subset of two or more layers; the
@@ -64,8 +65,8 @@ def cc_sets(mode: int, n: int, S_list, R_list, k: int, ws=None):
     return _ids(above), _ids(top)
 
 
-def study_subset(n: int, layer_graphs, layer_outs, subset, k: int, plan: L.Plan, ws=None) -> dict:
-    """Ground truth, CC2 and naive CC-node sets of one layer subset."""
+def study_subset(n: int, layer_graphs, layer_outs, subset, k: int, plan: L.Plan, ws=None, cc1_tau=(1, 2)) -> dict:
+    """Ground truth, CC2, CC1 and naive CC-node sets of one layer subset."""
     gs = [layer_graphs[i] for i in subset]
     Ss = [layer_outs[i]["S"] for i in subset]
     Rs = [layer_outs[i]["R"] for i in subset]
@@ -79,8 +80,11 @@ def study_subset(n: int, layer_graphs, layer_outs, subset, k: int, plan: L.Plan,
     # applied to top-k sets; it can hold fewer than k vertices)
     tops = [set(cc_sets(L.HLN_RANK_WF, n, [S], [R], k, ws)[1].tolist()) for S, R in zip(Ss, Rs)]
     naive_top = np.array(sorted(set.intersection(*tops)), dtype=np.int64)
+    ids1, cnt1, _ = L.hln_compose_cc1(gs, Ss, Rs, cc1_tau)
+    cc1_above = ids1[:int(cnt1.item())].cpu().numpy()
     return {"subset": list(subset), "and_arcs": int(g_and.nnz),
             "cc2_above": set_metrics(c_above, t_above), "cc2_topk": set_metrics(c_top, t_top),
+            "cc1_above": set_metrics(cc1_above, t_above),
             "naive_above": set_metrics(naive_above, t_above), "naive_topk": set_metrics(naive_top, t_top)}
 
 
@@ -100,7 +104,7 @@ def study_homln(h, k_frac: float = 0.1, pairs: bool = True, plan: L.Plan | None 
 def summarise(records) -> dict:
     """Mean of each score over a list of study_subset records."""
     out = {}
-    for key in ("cc2_above", "cc2_topk", "naive_above", "naive_topk"):
+    for key in ("cc2_above", "cc2_topk", "cc1_above", "naive_above", "naive_topk"):
         out[key] = {m: float(np.mean([r[key][m] for r in records])) for m in ("jaccard", "precision", "recall", "f1")}
     out["subsets"] = len(records)
     return out
@@ -120,6 +124,9 @@ def subsets_sweep(h, k_frac: float = 0.01, width_bits: int = 4096, with_or: bool
     nl = len(layers)
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     ws_sel = L.workspace(int(L.lib().hln_compose_cc_topk_workspace_size(n)), dev)
+    ws_cc1 = L.workspace(int(L.lib().hln_compose_cc1_workspace_size(n, nl)), dev)
+    cc1_out = (torch.empty(n, dtype=torch.int32, device=dev), torch.empty(1, dtype=torch.int32, device=dev),
+               torch.empty(1, dtype=torch.float64, device=dev))
     nnz_max = sum(g.nnz for g in layers)
     ws_cl = L.workspace(L.closeness_workspace_size(n, nnz_max, n, width_bits), dev)
     outs = [{"S": torch.empty(n, dtype=torch.int64, device=dev), "R": torch.empty(n, dtype=torch.int32, device=dev),
@@ -142,7 +149,7 @@ def subsets_sweep(h, k_frac: float = 0.01, width_bits: int = 4096, with_or: bool
             cap_and = min(g.nnz for g in gs)
             and_buf = (torch.empty(n + 1, dtype=torch.int32, device=dev), torch.empty(cap_and, dtype=torch.int32, device=dev))
             ws_cmp = L.workspace(L.compose_workspace_size(gs), dev)
-            e = [ev() for _ in range(5)]
+            e = [ev() for _ in range(6)]
             e[0].record()
             g_and = L.hln_compose_and(gs, ws=ws_cmp, out=and_buf)
             L.hln_closeness_layer(g_and, width_bits=width_bits, want_cc=False, out=gt_out, ws=ws_cl)
@@ -150,13 +157,17 @@ def subsets_sweep(h, k_frac: float = 0.01, width_bits: int = 4096, with_or: bool
             e[1].record()
             c_dev = cc_sets_dev(L.HLN_RANK_CC2, n, [outs[i]["S"] for i in sub], [outs[i]["R"] for i in sub], k, ws_sel)
             e[2].record()
+            L.hln_compose_cc1(gs, [outs[i]["S"] for i in sub], [outs[i]["R"] for i in sub], ws=ws_cc1, out=cc1_out)
+            e[5].record()
             torch.cuda.synchronize()
             L.device_status()
-            rec = {"subset": list(sub), "t_and_gt_ms": e[0].elapsed_time(e[1]), "t_theta_ms": e[1].elapsed_time(e[2])}
+            rec = {"subset": list(sub), "t_and_gt_ms": e[0].elapsed_time(e[1]), "t_theta_ms": e[1].elapsed_time(e[2]),
+                   "t_theta_cc1_ms": e[2].elapsed_time(e[5])}
             t_sets = (_ids(t_dev[0]), _ids(t_dev[1]))
             c_sets = (_ids(c_dev[0]), _ids(c_dev[1]))
             rec["cc2_above"] = set_metrics(c_sets[0], t_sets[0])
             rec["cc2_topk"] = set_metrics(c_sets[1], t_sets[1])
+            rec["cc1_above"] = set_metrics(cc1_out[0][:int(cc1_out[1].item())].cpu().numpy(), t_sets[0])
             del and_buf, ws_cmp
             if with_or:
                 cap_or = sum(g.nnz for g in gs)
@@ -177,6 +188,8 @@ def subsets_sweep(h, k_frac: float = 0.01, width_bits: int = 4096, with_or: bool
     t_theta = sum(x["t_theta_ms"] for x in recs)
     return {"layers": nl, "subsets": len(recs), "k": k, "t_psi_ms": t_psi, "t_and_gt_total_ms": t_gt,
             "t_theta_total_ms": t_theta, "speedup_decoupled": t_gt / (t_psi + t_theta),
+            "t_theta_cc1_total_ms": sum(x["t_theta_cc1_ms"] for x in recs),
+            "cc1_above_mean": {m: float(np.mean([x["cc1_above"][m] for x in recs])) for m in ("jaccard", "precision", "f1")},
             "t_or_gt_total_ms": sum(x.get("t_or_gt_ms", 0.0) for x in recs) if with_or else None,
             "cc2_topk_mean": {m: float(np.mean([x["cc2_topk"][m] for x in recs])) for m in ("jaccard", "precision", "f1")},
             "cc2_above_mean": {m: float(np.mean([x["cc2_above"][m] for x in recs])) for m in ("jaccard", "precision", "f1")},

@@ -27,7 +27,8 @@ def oracle_sets(n, layers_np, subset, k):
     sc = O.cc2_score(n, est)
     cc2 = (np.sort(O.above_mean(sc)), O.topk_desc(sc, k))
     naive = np.sort(O.naive(n, [x[2] for x in SR]))
-    return truth, cc2, naive
+    cc1 = O.cc1(n, Ls, [x[0] for x in SR], [x[1] for x in SR], (1, 2))
+    return truth, cc2, naive, cc1
 
 
 def test_study_sets_match_oracle_config1():
@@ -43,7 +44,7 @@ def test_study_sets_match_oracle_config1():
     recs = CM.study_homln(h, k_frac=0.1, pairs=True, plan=plan)
     assert [tuple(r["subset"]) for r in recs] == subsets
     for sub, rec in zip(subsets, recs):
-        truth, cc2, naive = oracle_sets(n, layers_np, sub, k)
+        truth, cc2, naive, cc1 = oracle_sets(n, layers_np, sub, k)
         g_and = P.hln_compose_and([layers[i] for i in sub]).trimmed()
         gt = P.Plan.outputs([g_and])
         plan.run([g_and], gt)
@@ -54,6 +55,7 @@ def test_study_sets_match_oracle_config1():
         assert rec["cc2_above"] == CM.set_metrics(cc2[0], truth[0])
         assert rec["cc2_topk"] == CM.set_metrics(cc2[1], truth[1])
         assert rec["naive_above"] == CM.set_metrics(naive, truth[0])
+        assert rec["cc1_above"] == CM.set_metrics(cc1, truth[0])
         say("subset", sub, "cc2 top-k jaccard %.3f, naive above jaccard %.3f"
             % (rec["cc2_topk"]["jaccard"], rec["naive_above"]["jaccard"]))
 
@@ -68,7 +70,8 @@ def test_subsets_sweep_small():
     layers_np = [csr_np(n, *e) for e in h.layers]
     k = res["k"]
     sub = (0, 2, 3)
-    truth, cc2, _ = oracle_sets(n, layers_np, sub, k)
+    truth, cc2, _, cc1 = oracle_sets(n, layers_np, sub, k)
     rec = [r for r in res["records"] if tuple(r["subset"]) == sub][0]
     assert rec["cc2_topk"] == CM.set_metrics(cc2[1], truth[1])
+    assert rec["cc1_above"] == CM.set_metrics(cc1, truth[0])
     say("speedup of the decoupled method", res["speedup_decoupled"])
