@@ -23,6 +23,14 @@
 // word count in the cost) and no block's list overflowed; the barrier's
 // releasing thread decides and every block receives the same bit.
 //
+// Saturation: a vertex that holds every source bit it can ever receive in
+// the batch gains nothing more, so later bottom-up levels skip its segments
+// (no ids, flags or gathers).  What it can receive is judged against one
+// component C: the component of the first batch's highest-degree source,
+// marked exactly by that source's own bit after the first batch.  In later
+// batches a vertex holding any of the batch's sources in C lies in C, and
+// once it holds all of them no other source of the batch can reach it.
+//
 // Accumulation:
 //   all sources (sources == NULL): the graph is undirected, so d(s,v) =
 //     d(v,s) and the vertex v accumulates S[v] += d*popc(new), R[v] +=
@@ -156,6 +164,8 @@ struct Ctrl {
     int n_seg;
     int fbad[3];                           // nonzero: a block's frontier list overflowed (slot = phase mod 3)
     unsigned long long farcs[3];           // frontier arc-words of the same phases
+    unsigned long long probe_key;          // first batch's probe source: degree << 32 | ~position (max)
+    unsigned long long gcm[64];            // this batch's sources in the largest component (bit per source)
 };
 
 // LDS frontier-list entries per block and phase; a phase that lists more in
@@ -181,6 +191,8 @@ struct BfsArgs {
     long long seg_cap;                // capacity of seg
     long long nnz_cap;                // arcs the caller declared (col_idx holds at least row_ptr[n] <= nnz_cap)
     int32_t* seg_first;               // n: index of the vertex's first segment
+    uint32_t* segsat;                 // seg_cap: 1 once the segment's vertex holds every bit it can get in the batch
+    uint32_t* member;                 // n: 1 when the vertex lies in the probe source's component
     int64_t* part;                    // per-source mode: [grid][2][W] block partials
     int64_t* S;
     uint32_t* S32;                    // n: this batch's distance sums (levels below kS32Levels), folded into S
@@ -211,7 +223,7 @@ constexpr int kS32Levels = 1 << 18;
 // so every instruction issues on every path and the loop's memory counter
 // waits stay exact (stores count in the same in-order counter as loads).
 struct LevelBufs {
-    __amdgpu_buffer_rsrc_t nx, vis, flag_nx, flag_fr, s32, r, h2, col, seg;
+    __amdgpu_buffer_rsrc_t nx, vis, flag_nx, flag_fr, s32, r, h2, col, seg, segsat;
 };
 
 // A block's frontier lists in LDS, double-buffered by phase parity: the
@@ -287,11 +299,15 @@ __device__ __forceinline__ int trace_add(int64_t* row, int verts, long long pair
 // Finalise vertex v at level d: new bits, bitset updates, accumulation.
 // Called by the lanes of a group with the group's full OR in `acc` (lane
 // (sub, k) holds word k; only sub == 0 lanes write).  Returns the number of
-// new bits and the number of words holding them.
+// new bits, the number of words holding them, and whether the vertex is now
+// saturated: `gcm_k` is word k of the batch's sources that lie in one
+// component C (that of the first batch's probe source); a vertex holding one
+// of them lies in C, and once it holds all of them no other source of the
+// batch can ever reach it, so it can gain nothing more in this batch.
 template <int NW, bool PER_SOURCE>
-__device__ __forceinline__ int2 finalize_vertex(const BfsArgs& a, const LevelBufs& B, int v, int d, int k, int sub,
+__device__ __forceinline__ int3 finalize_vertex(const BfsArgs& a, const LevelBufs& B, int v, int d, int k, int sub,
                                                 int gl, int gbase, uint64_t acc, uint64_t vis_v, int32_t* s_cnt,
-                                                MaskT<NW> flag_old) {
+                                                MaskT<NW> flag_old, uint64_t gcm_k) {
     using Mask = MaskT<NW>;
     constexpr int LPV = lpv<NW>();
     constexpr Mask kWordMask = static_cast<Mask>(NW >= 64 ? ~0ull : ((1ull << (NW & 63)) - 1ull));
@@ -332,7 +348,20 @@ __device__ __forceinline__ int2 finalize_vertex(const BfsArgs& a, const LevelBuf
         buf_add_u32(static_cast<uint32_t>(c), B.r, aoff);
         if (d == 2 && a.H2) buf_add_u32(static_cast<uint32_t>(c), B.h2, aoff);
     }
-    return make_int2(c, __popcll(static_cast<unsigned long long>(nmask)));
+    // saturation (lanes with sub != 0 hold copies and do not vote)
+    const uint64_t have = (vis_v | nw) & gcm_k;
+    const bool full_k = sub != 0 || have == gcm_k;
+    constexpr unsigned long long kGroupMask = LPV >= 64 ? ~0ull : ((1ull << LPV) - 1ull);
+    const bool in_gc = ((__ballot(sub == 0 && have != 0) >> gbase) & kGroupMask) != 0;
+    const int sat = (c != 0 && in_gc && ((__ballot(full_k) >> gbase) & kGroupMask) == kGroupMask) ? 1 : 0;
+    return make_int3(c, __popcll(static_cast<unsigned long long>(nmask)), sat);
+}
+
+// A saturated vertex: all its segments are skipped by later pull levels of
+// the batch (called by the lanes of its group).
+template <int LPV>
+__device__ __forceinline__ void mark_saturated(const BfsArgs& a, int first, int nseg, int gl) {
+    for (int j = gl; j < nseg; j += LPV) a.segsat[first + j] = 1u;
 }
 
 // Gathering the frontier over a segment [lo, hi) for the word k of this
@@ -477,13 +506,18 @@ struct SegPre {
     int cid[Gather<NW>::CH];
     MaskT<NW> fl[Gather<NW>::CH]; // frontier word masks of the neighbours in cid
     MaskT<NW> flag_old;          // word mask of the vertex's next-frontier slot
+    bool sat;                    // the vertex holds every bit of the batch: no gathers
 };
 
 template <int NW, bool PER_SOURCE>
-__device__ __forceinline__ void seg_prefetch(const LevelBufs& B, const int4 sg, bool valid, int gl, SegPre<NW>& p) {
+__device__ __forceinline__ void seg_prefetch(const LevelBufs& B, const int4 sg, bool valid, bool sat, int gl,
+                                             SegPre<NW>& p) {
     using Mask = MaskT<NW>;
     p.sg = sg;
-    Gather<NW>::load_ids(B.col, sg.y, valid ? sg.z : sg.y, gl, p.cid);
+    p.sat = sat;
+    // a saturated segment reads no ids (so no neighbour flags either); its
+    // next-frontier flag is still read, as the finaliser clears stale words
+    Gather<NW>::load_ids(B.col, sg.y, (valid && !sat) ? sg.z : sg.y, gl, p.cid);
     p.flag_old = buf_mask<Mask>(B.flag_nx, (valid && sg.w == 1) ? static_cast<uint32_t>(sg.x) * static_cast<uint32_t>(sizeof(Mask))
                                                               : kNoWord);
 #pragma unroll
@@ -509,6 +543,7 @@ __device__ __forceinline__ LevelBufs level_bufs(const BfsArgs& a, const uint64_t
     B.h2 = __builtin_amdgcn_make_buffer_rsrc(a.H2, 0, a.H2 ? static_cast<int>(n * 4u) : 0, 0x00020000);
     B.col = __builtin_amdgcn_make_buffer_rsrc(const_cast<int32_t*>(a.col_idx), 0, static_cast<int>(a.nnz_cap * 4), 0x00020000);
     B.seg = __builtin_amdgcn_make_buffer_rsrc(a.seg, 0, static_cast<int>(a.seg_cap * 16), 0x00020000);
+    B.segsat = __builtin_amdgcn_make_buffer_rsrc(a.segsat, 0, static_cast<int>(a.seg_cap * 4), 0x00020000);
     return B;
 }
 
@@ -539,6 +574,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
     __shared__ int64_t s_S[PER_SOURCE ? W : 1];
     __shared__ int32_t s_R[PER_SOURCE ? W : 1];
     __shared__ int s_bins[kClasses];
+    __shared__ int s_base[kClasses];
     __shared__ long long s_trace[2];
     __shared__ FrontierLds s_fr;
 
@@ -606,16 +642,34 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
     // ---- phase 2: fill the segment list (heavy rows first, then by
     // decreasing degree; order inside a class is arbitrary and does not
     // affect any result)
-    for (long long v = tid; v < n; v += nthreads) {
-        const int e0 = a.row_ptr[v];
-        const int deg = a.row_ptr[v + 1] - e0;
+    // Each block reserves one range per class for its vertices (LDS counts,
+    // then one global add per class), so the class cursors see a few
+    // thousand atomics rather than one per vertex.
+    for (long long base = static_cast<long long>(blockIdx.x) * BLOCK; base < n; base += nthreads) {
+        const long long v = base + threadIdx.x;
+        if (threadIdx.x < kClasses) s_bins[threadIdx.x] = 0;
+        __syncthreads();
+        int e0 = 0, deg = 0, segs = 0, cls = 0, local = 0;
+        if (v < n) {
+            e0 = a.row_ptr[v];
+            deg = a.row_ptr[v + 1] - e0;
+            if (deg > 0) {
+                segs = (deg + seg_len - 1) / seg_len;
+                cls = seg_class(deg, seg_len);
+                local = atomicAdd(&s_bins[cls], segs);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < kClasses && s_bins[threadIdx.x])
+            s_base[threadIdx.x] = atomicAdd(&ctrl->cursor[threadIdx.x], s_bins[threadIdx.x]);
+        __syncthreads();
         if (deg > 0) {
-            const int segs = (deg + seg_len - 1) / seg_len;
-            const int pos = atomicAdd(&ctrl->cursor[seg_class(deg, seg_len)], segs);
+            const int pos = s_base[cls] + local;
             a.seg_first[v] = pos;
             for (int j = 0; j < segs && pos + j < a.seg_cap; ++j)
                 a.seg[pos + j] = make_int4(static_cast<int>(v), e0 + j * seg_len, min(e0 + (j + 1) * seg_len, e0 + deg), segs);
         }
+        __syncthreads();
     }
     if (!gb.wait()) return;
     const long long n_seg = min(static_cast<long long>(load_agent_i32(&ctrl->n_seg)), a.seg_cap);
@@ -630,10 +684,33 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
         const int cnt = min(W, a.n_src - src0);
 
         // ---- batch init: vis = fr = the batch's source bits; the sources'
-        // segments form the first frontier list
+        // segments form the first frontier list; no segment is saturated
         bool push;
         {
             const int par = phase & 1;
+            for (long long i = tid; i < n_seg; i += nthreads) a.segsat[i] = 0u;
+            // Saturation is judged against the component C of a probe: the
+            // first batch's source of highest degree (ties: the first), whose
+            // own BFS in that batch marks C exactly.  From the second batch
+            // on, the batch's sources in C, one ballot per word (a wave's
+            // lanes hold consecutive source positions); the first batch has
+            // none, so nothing saturates in it.
+            for (long long i = tid; i < W; i += nthreads) {
+                bool in = false;
+                if (i < cnt) {
+                    const int src = a.listed ? a.sources[src0 + i] : static_cast<int>(src0 + i);
+                    if (b == 0) {
+                        const unsigned long long deg = static_cast<unsigned long long>(a.row_ptr[src + 1] - a.row_ptr[src]);
+                        __hip_atomic_fetch_max(&ctrl->probe_key, (deg << 32) | (0xffffffffull - static_cast<unsigned long long>(i)),
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    } else {
+                        in = a.member[src] != 0u;
+                    }
+                }
+                const unsigned long long word = __ballot(in);
+                if ((threadIdx.x & 63) == 0)
+                    __hip_atomic_store(&ctrl->gcm[i >> 6], word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
             if (blockIdx.x == 0 && threadIdx.x == 0) {
                 const int nx_slot = (phase + 1) % 3;
                 store_agent_i32(&ctrl->fbad[nx_slot], 0);
@@ -706,6 +783,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
             push = br.decision;
             ++phase;
         }
+        const uint64_t gcm_k = hln::dev::load_agent(&ctrl->gcm[k]);
 
         // ---- level loop; the barrier's OR tells every block whether any
         // vertex got a new bit, which ends this batch's BFS
@@ -776,16 +854,15 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                             }
                             if (gl == 0) store_agent_i32(&a.hcnt[v], 0);
                         }
-                        const int2 cw = finalize_vertex<NW, PER_SOURCE>(a, B, v, d, k, sub, gl, gbase, acc, vis_v,
-                                                                        s_cnt, foj);
+                        const int3 cw = finalize_vertex<NW, PER_SOURCE>(a, B, v, d, k, sub, gl, gbase, acc, vis_v,
+                                                                        s_cnt, foj, gcm_k);
                         if (cw.x) {
                             any = 1;
                             t_pairs += cw.x;
                             t_verts += 1;
-                            if (gl == 0) {
-                                const int3 sgv = vertex_segments(a, v);
-                                if (sgv.y > 0) frontier_note(s_fr, par, sgv.x, sgv.y, sgv.z * cw.y);
-                            }
+                            const int3 sgv = vertex_segments(a, v);
+                            if (gl == 0 && sgv.y > 0) frontier_note(s_fr, par, sgv.x, sgv.y, sgv.z * cw.y);
+                            if (cw.z) mark_saturated<kLpv>(a, sgv.x, sgv.y, gl);
                         }
                     }
                 }
@@ -797,17 +874,22 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                 auto rec_at = [&](long long i) {
                     return buf_i4(B.seg, i < n_seg ? static_cast<uint32_t>(i) * 16u : kNoWord);
                 };
-                seg_prefetch<NW, PER_SOURCE>(B, rec_at(s), s < n_seg, gl, cur);
-                seg_prefetch<NW, PER_SOURCE>(B, rec_at(s + ngroups), s + ngroups < n_seg, gl, nxt);
+                auto sat_at = [&](long long i) {
+                    return buf_u32(B.segsat, i < n_seg ? static_cast<uint32_t>(i) * 4u : kNoWord) != 0u;
+                };
+                seg_prefetch<NW, PER_SOURCE>(B, rec_at(s), s < n_seg, sat_at(s), gl, cur);
+                seg_prefetch<NW, PER_SOURCE>(B, rec_at(s + ngroups), s + ngroups < n_seg, sat_at(s + ngroups), gl, nxt);
                 seg_flags<NW>(B, cur);
                 int4 rec2 = rec_at(s + 2 * ngroups);
+                bool sat2 = sat_at(s + 2 * ngroups);
                 while (s < n_seg) {
                     const long long s1 = s + ngroups;
                     const long long s2 = s1 + ngroups;
                     const long long s3 = s2 + ngroups;
                     const int4 rec3 = rec_at(s3);                                      // record, 3 ahead
+                    const bool sat3 = sat_at(s3);
                     SegPre<NW> nn;
-                    seg_prefetch<NW, PER_SOURCE>(B, rec2, s2 < n_seg, gl, nn);          // ids, 2 ahead
+                    seg_prefetch<NW, PER_SOURCE>(B, rec2, s2 < n_seg, sat2, gl, nn);    // ids, 2 ahead
                     seg_flags<NW>(B, nxt);                                             // flags, 1 ahead
 
                     const int v = cur.sg.x;
@@ -819,8 +901,8 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                     // the visited word is read only when a neighbour is active, the
                     // segment has further rounds or the row has several segments (its
                     // finaliser needs it), together with the gathers
-                    const bool need = ((__ballot(active) & gmask) != 0) || (cur.sg.z - cur.sg.y > Gather<NW>::ROUND) ||
-                                      nseg > 1;
+                    const bool need = !cur.sat && (((__ballot(active) & gmask) != 0) ||
+                                                   (cur.sg.z - cur.sg.y > Gather<NW>::ROUND) || nseg > 1);
                     uint64_t vis_v = 0;
                     uint64_t acc = 0;
                     if (need) {
@@ -841,13 +923,14 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
 #pragma unroll
                     for (int off = NW; off < kLpv; off <<= 1) acc |= shfl_xor_u64(acc, off);
                     if (nseg == 1) {
-                        const int2 cw = finalize_vertex<NW, PER_SOURCE>(a, B, v, d, k, sub, gl, gbase, acc, vis_v,
-                                                                        s_cnt, cur.flag_old);
+                        const int3 cw = finalize_vertex<NW, PER_SOURCE>(a, B, v, d, k, sub, gl, gbase, acc, vis_v,
+                                                                        s_cnt, cur.flag_old, gcm_k);
                         if (cw.x) {
                             any = 1;
                             t_pairs += cw.x;
                             t_verts += 1;
                             if (gl == 0) frontier_note(s_fr, par, static_cast<int>(s), 1, (cur.sg.z - cur.sg.y) * cw.y);
+                            if (cw.z) mark_saturated<kLpv>(a, static_cast<int>(s), 1, gl);
                         }
                     } else {
                         // multi-segment row: merge, the last finisher finalises
@@ -874,13 +957,15 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                             for (int off = NW; off < kLpv; off <<= 1) full |= shfl_xor_u64(full, off);
                             const Mask flag_old = flag_nx[v];
                             if (gl == 0) store_agent_i32(&a.hcnt[v], 0);
-                            const int2 cw = finalize_vertex<NW, PER_SOURCE>(a, B, v, d, k, sub, gl, gbase, full, vis_v,
-                                                                            s_cnt, flag_old);
+                            const int3 cw = finalize_vertex<NW, PER_SOURCE>(a, B, v, d, k, sub, gl, gbase, full, vis_v,
+                                                                            s_cnt, flag_old, gcm_k);
                             if (cw.x) {
                                 any = 1;
                                 t_pairs += cw.x;
                                 t_verts += 1;
-                                if (gl == 0) frontier_note(s_fr, par, a.seg_first[v], nseg, nseg * seg_len * cw.y);
+                                const int first = a.seg_first[v];
+                                if (gl == 0) frontier_note(s_fr, par, first, nseg, nseg * seg_len * cw.y);
+                                if (cw.z) mark_saturated<kLpv>(a, first, nseg, gl);
                             }
                         }
                     }
@@ -888,6 +973,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                     cur = nxt;
                     nxt = nn;
                     rec2 = rec3;
+                    sat2 = sat3;
                 }
             }
             if (PER_SOURCE) {
@@ -958,6 +1044,13 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                 a.R[src0 + i] = static_cast<int32_t>(1 + sR);
             }
             // the partials are rewritten only after the next batch's barriers
+        }
+        if (b == 0 && n_batches > 1) {
+            // the probe's component: every vertex its bit reached in this batch
+            const unsigned pos = 0xffffffffu - static_cast<unsigned>(hln::dev::load_agent(&ctrl->probe_key) & 0xffffffffull);
+            for (long long v = tid; v < n; v += nthreads)
+                a.member[v] = ((a.vis[v * NW + (pos >> 6)] >> (pos & 63)) & 1ull) ? 1u : 0u;
+            if (!gb.wait()) return;
         }
     }
 
@@ -1101,6 +1194,8 @@ size_t workspace_bytes(int32_t n, int64_t nnz, int nw, int grid_cap) {
     b += 2 * Arena::round(static_cast<size_t>(n) * 8);          // word masks of A, B
     b += 3 * Arena::round(static_cast<size_t>(n) * sizeof(int32_t)); // hcnt, seg_first, S32
     b += Arena::round(seg_cap * sizeof(int4));
+    b += Arena::round(seg_cap * sizeof(uint32_t));                    // saturated segments
+    b += Arena::round(static_cast<size_t>(n) * sizeof(uint32_t));    // probe component membership
     b += Arena::round(static_cast<size_t>(grid_cap) * 2 * 64 * nw * sizeof(int64_t));  // per-source partials
     return b;
 }
@@ -1181,6 +1276,8 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
     a.hcnt = ar.take<int32_t>(n);
     a.seg_cap = static_cast<long long>(n) + g->nnz / kSegLen + 1;
     a.seg = ar.take<int4>(static_cast<size_t>(a.seg_cap));
+    a.segsat = ar.take<uint32_t>(static_cast<size_t>(a.seg_cap));
+    a.member = ar.take<uint32_t>(n);
     a.seg_first = ar.take<int32_t>(n);
     a.S32 = ar.take<uint32_t>(n);
     a.nnz_cap = g->nnz;
@@ -1196,11 +1293,12 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
     a.trace = opts ? opts->trace : nullptr;
     a.trace_cap = opts ? opts->trace_cap : 0;
     a.seg_len = kSegLen;
-    a.alpha = 4;
+    a.alpha = 32;   // measured on configs 2-4 once saturated vertices skip their pull work
     if (const char* e = getenv("HLN_ALPHA")) a.alpha = std::max(1, atoi(e));
     a.s32_levels = kS32Levels;
     if (const char* e = getenv("HLN_S32_LEVELS")) a.s32_levels = std::min(kS32Levels, std::max(1, atoi(e)));
-    if (!a.ctrl || !a.bar || !a.part || !a.flagB || !a.seg_first || !a.S32) return fail(HLN_ENOMEM, "workspace carve failed");
+    if (!a.ctrl || !a.bar || !a.part || !a.flagB || !a.seg_first || !a.S32 || !a.segsat || !a.member)
+        return fail(HLN_ENOMEM, "workspace carve failed");
 
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(k_zero_ctrl, dim3(1), dim3(256), 0, st, a.ctrl, a.bar);

@@ -193,9 +193,8 @@ def test_forced_direction(direction, width):
 
 
 def test_auto_direction_takes_both():
-    """The automatic choice runs the first levels of a batch top-down (a few
-    sources' neighbourhoods) and the dense middle bottom-up; the trace
-    records each level's direction and new vertices."""
+    """The automatic choice runs sparse levels top-down and the dense middle
+    bottom-up; the trace records each level's direction and new pairs."""
     h = C.config2(scale=0.1)
     rp, ci = csr_np(h.n, *h.layers[0])
     g = graph_dev(P, rp, ci)
@@ -212,9 +211,9 @@ def test_auto_direction_takes_both():
     S, R, H2, _, _ = O.bfs_sums(rp, ci, extras=True)
     assert np.array_equal(out["S"].cpu().numpy(), S)
     assert np.array_equal(out["h2"].cpu().numpy(), H2)
-    # the first level of a batch is top-down unless its sources hold hubs
-    starts = np.concatenate([[0], np.cumsum(lv.cpu().numpy())[:-1]])
-    assert np.mean(dirs[starts] == 1) >= 0.8
+    # top-down levels are the sparse ones
+    pairs = t[:, 2]
+    assert np.median(pairs[dirs == 1]) < np.median(pairs[dirs == 0])
 
 
 @pytest.mark.parametrize("width", [64, 4096])
@@ -230,3 +229,55 @@ def test_distance_sums_past_the_32_bit_window(width, monkeypatch):
     h = C.config2(scale=0.03)
     rp, ci = csr_np(h.n, *h.layers[0])
     check_all(h.n, rp, ci, width, "s64-cfg2-scaled")
+
+
+@pytest.mark.parametrize("width", [64, 256, 4096])
+def test_saturation_probe_components(width):
+    """Vertices that hold every bit they can receive skip later levels; what
+    they can receive is judged against the component of the first batch's
+    highest-degree source.  Cases: that probe in a small component (a star
+    hub outranking a long cycle), the probe isolated (the first batch all
+    isolated vertices), and a listed first batch from another component than
+    later batches.  Sums against the oracle."""
+    rng = np.random.default_rng(81 + width)
+    W = width
+    # star (hub degree 3W/2) first, then a cycle and random chords, isolated tail
+    n_star = 3 * W // 2 + 1
+    n_cyc = 5 * W + 17
+    eu = [0] * (n_star - 1)
+    ev = list(range(1, n_star))
+    base = n_star
+    for i in range(n_cyc):
+        eu.append(base + i)
+        ev.append(base + (i + 1) % n_cyc)
+    for _ in range(n_cyc // 3):
+        a, b = rng.choice(n_cyc, size=2, replace=False)
+        eu.append(base + int(a))
+        ev.append(base + int(b))
+    n = base + n_cyc + 40
+    keys = sorted({(min(a, b), max(a, b)) for a, b in zip(eu, ev) if a != b})
+    u = np.array([k[0] for k in keys])
+    v = np.array([k[1] for k in keys])
+    rp, ci = csr_np(n, u, v)
+    check_all(n, rp, ci, width, "star-probe")
+    # first batch made of isolated vertices: relabel so they come first
+    perm = np.concatenate([np.arange(base + n_cyc, n), np.arange(0, base + n_cyc)])
+    inv = np.empty(n, np.int64)
+    inv[perm] = np.arange(n)
+    rp2, ci2 = csr_np(n, inv[u], inv[v])
+    check_all(n, rp2, ci2, width, "isolated-probe")
+    # listed sources: first batch inside the star, later ones on the cycle
+    src = np.concatenate([np.arange(0, min(W, n_star)), base + rng.choice(n_cyc, size=2 * W + 5, replace=False)])
+    src = src.astype(np.int32)
+    g = graph_dev(P, rp, ci)
+    out = P.hln_closeness_layer(g, sources=to_dev(src), width_bits=width)
+    torch.cuda.synchronize()
+    P.device_status()
+    S, R = O.bfs_sums(rp, ci, sources=src)
+    assert np.array_equal(out["S"].cpu().numpy(), S)
+    assert np.array_equal(out["R"].cpu().numpy(), R)
+    pv = P.hln_closeness_layer(g, sources=to_dev(src), width_bits=width, per_vertex=True)
+    torch.cuda.synchronize()
+    SQ, RQ = O.sample_sums(rp, ci, src)
+    assert np.array_equal(pv["S"].cpu().numpy(), SQ)
+    assert np.array_equal(pv["R"].cpu().numpy(), RQ)
