@@ -12,7 +12,9 @@
 // One level, top-down (push): every segment of a frontier vertex u ORs
 //   fr[u] into its neighbours' accumulators (agent-scope atomics) and marks
 //   them touched; after a grid barrier the touched vertices are finalised
-//   as in the pull case and stale words of the older frontier are cleared.
+//   as in the pull case and the word masks of the older frontier cleared.
+// A frontier word is read only where its vertex's word mask has the bit, so
+// words outside the masks are never cleared.
 // A level's new bits at v are the sources at distance d from v.
 // Direction: every finalised vertex with new bits appends its segments to
 // its block's frontier list in LDS and adds its arc-words (arcs times the
@@ -182,7 +184,7 @@ struct BfsArgs {
     int listed;                       // sources come from the list (it may be empty)
     uint64_t* bufA;                   // n*NW
     uint64_t* bufB;                   // n*NW
-    void* flagA;                      // n word masks (MaskT<NW>): bit k clear implies bufA word k of v is zero
+    void* flagA;                      // n word masks (MaskT<NW>): bufA word k of v is read only when bit k is set
     void* flagB;                      // n: the same for bufB
     uint64_t* vis;                    // n*NW
     uint64_t* hacc;                   // n*NW partial ORs of multi-segment rows (kept zero)
@@ -318,10 +320,10 @@ __device__ __forceinline__ int3 finalize_vertex(const BfsArgs& a, const LevelBuf
     int c = sub == 0 ? __popcll(nw) : 0;
 #pragma unroll
     for (int off = 1; off < LPV; off <<= 1) c += shfl_xor_i32(c, off);
-    // new bits go to the next frontier; a word that held an older frontier
-    // and has nothing new is cleared; other words stay zero
-    const bool st_nx = sub == 0 && (nw != 0 || ((flag_old >> k) & 1u));
-    buf_store_u64(nw, B.nx, st_nx ? woff : kNoWord);
+    // new bits go to the next frontier; words without new bits keep whatever
+    // they held, as the word mask (exact, stored below when it changes) keeps
+    // every reader off them
+    buf_store_u64(nw, B.nx, (sub == 0 && nw != 0) ? woff : kNoWord);
     buf_store_u64(vis_v | nw, B.vis, (sub == 0 && nw != 0) ? woff : kNoWord);
     if (PER_SOURCE && sub == 0 && nw) {
         uint64_t b = nw;
@@ -516,7 +518,7 @@ __device__ __forceinline__ void seg_prefetch(const LevelBufs& B, const int4 sg, 
     p.sg = sg;
     p.sat = sat;
     // a saturated segment reads no ids (so no neighbour flags either); its
-    // next-frontier flag is still read, as the finaliser clears stale words
+    // next-frontier word mask is still read, as the finaliser clears a stale one
     Gather<NW>::load_ids(B.col, sg.y, (valid && !sat) ? sg.z : sg.y, gl, p.cid);
     p.flag_old = buf_mask<Mask>(B.flag_nx, (valid && sg.w == 1) ? static_cast<uint32_t>(sg.x) * static_cast<uint32_t>(sizeof(Mask))
                                                               : kNoWord);
@@ -724,8 +726,11 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                     uint64_t w0 = 0;
                     if (bit >= 0 && bit < cnt && (bit >> 6) == kk) w0 = 1ull << (bit & 63);
                     a.vis[i] = w0;
-                    a.bufA[i] = w0;
                 }
+                // frontier words are read only where the word mask has the bit,
+                // so only the sources' own words are written
+                for (long long i = tid; i < cnt; i += nthreads)
+                    a.bufA[static_cast<size_t>(src0 + i) * NW + (i >> 6)] = 1ull << (i & 63);
                 for (long long v = tid; v < n; v += nthreads) {
                     static_cast<Mask*>(a.flagA)[v] =
                         (v >= src0 && v < src0 + cnt) ? static_cast<Mask>(static_cast<Mask>(1) << ((v - src0) >> 6)) : Mask(0);
@@ -741,10 +746,10 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                     if (sg.y > 0) frontier_note(s_fr, par, sg.x, sg.y, sg.z);
                 }
             } else {
-                for (long long i = tid; i < static_cast<long long>(n) * NW; i += nthreads) {
-                    a.vis[i] = 0;
-                    a.bufA[i] = 0;
-                }
+                for (long long i = tid; i < static_cast<long long>(n) * NW; i += nthreads) a.vis[i] = 0;
+                // only the words the sources' bits go to are cleared
+                for (long long i = tid; i < cnt; i += nthreads)
+                    a.bufA[static_cast<size_t>(a.sources[src0 + i]) * NW + (i >> 6)] = 0;
                 for (long long v = tid; v < n; v += nthreads) {
                     static_cast<Mask*>(a.flagA)[v] = 0;
                     if (!PER_SOURCE) {
@@ -827,8 +832,8 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                     }
                 }
                 if (!gb.wait()) return;
-                // ---- part 2: finalise touched vertices; vertices that hold
-                // words of the older frontier in nx get them cleared
+                // ---- part 2: finalise touched vertices; vertices whose nx
+                // word mask still holds the older frontier get it cleared
                 for (long long v0 = gid_x * kLpv; v0 < n; v0 += ngroups * kLpv) {
                     const long long vl = v0 + gl;
                     int touched = 0;
