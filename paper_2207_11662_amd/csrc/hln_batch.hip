@@ -273,8 +273,11 @@ struct Layout {
     int n_tiles[4] = {0, 0, 0, 0};   // per width class: 64, 32, 16, 8
     int max_n_class[4] = {0, 0, 0, 0};
     int grid = 0;
-    size_t coop_bytes = 0;             // workspace of the largest graph on the cooperative kernel
-    size_t desc_bytes = 0, tiles_bytes = 0, counters_bytes = 0, heavy_bytes = 0;
+    size_t coop_bytes = 0;             // cooperative graphs: coop_slices slices of coop_slice_bytes
+    size_t coop_slice_bytes = 0;       // workspace of the largest graph on the cooperative kernel
+    int coop_slices = 1;               // partitions of a multi-graph cooperative launch at most
+    size_t desc_bytes = 0, tiles_bytes = 0, margs_bytes = 0, mlist_bytes = 0, counters_bytes = 0, heavy_bytes = 0;
+    size_t stage_bytes = 0;            // host-staged tables: descriptors, tiles, launch arguments, lists
     size_t vis_bytes = 0, part_bytes = 0, total = 0;
 };
 
@@ -293,6 +296,9 @@ int chosen_width(const hln_plan* plan, int n, size_t budget) {
 
 bool is_coop(int w) { return w >= 512; }
 
+constexpr int kMaxParts = 8;                 // partitions of a multi-graph cooperative launch
+constexpr int kCoopWidths = 3;               // widths it runs: 1024, 2048, 4096
+
 // Workspace layout.  Sizes are worst cases over every width a graph could be
 // tuned to (tiles of 8 sources, the cooperative kernel at 4096), so the
 // workspace size does not change when the plan is tuned.
@@ -304,12 +310,15 @@ hln_status plan_layout(const hln_plan* plan, const hln_csr* graphs, int32_t n_gr
     const size_t budget = lds_budget();
     L.n_graphs = n_graphs;
     long long max_tiles = 0;
+    double total_work = 0.0, max_work = 0.0;
     for (int g = 0; g < n_graphs; ++g) {
         const hln_csr& c = graphs[g];
         if (c.n < 1 || c.nnz < 0 || !c.row_ptr || (c.nnz > 0 && !c.col_idx))
             return fail(HLN_EINVAL, "graph %d: bad descriptor", g);
-        hln_opts o{4096, 0, 0, nullptr, nullptr, 0};
-        L.coop_bytes = std::max(L.coop_bytes, hln_closeness_workspace_size(c.n, c.nnz, c.n, &o));
+        L.coop_slice_bytes = std::max(L.coop_slice_bytes, hln::multi_slice_bytes(c.n, c.nnz, 4096));
+        const double work = static_cast<double>(c.n) * static_cast<double>(c.nnz + c.n);
+        total_work += work;
+        max_work = std::max(max_work, work);
         if (widest_fit(c.n, budget)) {
             max_tiles += (c.n + 7) / 8;
             L.max_n = std::max(L.max_n, c.n);
@@ -330,9 +339,15 @@ hln_status plan_layout(const hln_plan* plan, const hln_csr* graphs, int32_t n_gr
     L.heavy_bytes = Arena::round(sizeof(uint32_t) * static_cast<size_t>(L.total_nnz + 1));
     L.vis_bytes = Arena::round(static_cast<size_t>(L.grid) * std::max(L.max_n, 1) * 8);
     L.part_bytes = Arena::round(static_cast<size_t>(L.grid) * std::max(L.max_n, 1) * 4);
-    L.coop_bytes = Arena::round(L.coop_bytes);
-    L.total = L.desc_bytes + L.tiles_bytes + L.counters_bytes + L.heavy_bytes + L.vis_bytes + 2 * L.part_bytes +
-              L.coop_bytes;
+    // as many workspace slices as partitions a multi-graph launch can use:
+    // up to 8, no more than the graphs, and one when a single graph holds
+    // most of the work
+    L.coop_slices = std::max(1, std::min({kMaxParts, n_graphs, static_cast<int>(total_work / std::max(max_work, 1.0))}));
+    L.coop_bytes = static_cast<size_t>(L.coop_slices) * L.coop_slice_bytes;
+    L.margs_bytes = Arena::round(hln::multi_args_bytes(n_graphs));
+    L.mlist_bytes = Arena::round(sizeof(int) * (static_cast<size_t>(n_graphs) + kCoopWidths * (kMaxParts + 1)));
+    L.stage_bytes = L.desc_bytes + L.tiles_bytes + L.margs_bytes + L.mlist_bytes;
+    L.total = L.stage_bytes + L.counters_bytes + L.heavy_bytes + L.vis_bytes + 2 * L.part_bytes + L.coop_bytes;
     return HLN_OK;
 }
 
@@ -342,7 +357,7 @@ void build_tables(const hln_plan* plan, const hln_csr* graphs, int32_t n_graphs,
                   int32_t* const* R, double* const* cc, int32_t* const* h2, const Layout& L, char* dev_base,
                   TileGraph* desc, int2* tiles, int* first_tile) {
     const size_t budget = lds_budget();
-    uint32_t* arcs = reinterpret_cast<uint32_t*>(dev_base + L.desc_bytes + L.tiles_bytes + L.counters_bytes);
+    uint32_t* arcs = reinterpret_cast<uint32_t*>(dev_base + L.stage_bytes + L.counters_bytes);
     long long off = 0;
     std::vector<int> order(n_graphs);
     for (int g = 0; g < n_graphs; ++g) {
@@ -400,7 +415,7 @@ hln_status enqueue_batch(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs
     if (!workspace || reinterpret_cast<uintptr_t>(workspace) % hln::Arena::kAlign)
         return fail(HLN_EINVAL, "workspace NULL or not 256-byte aligned");
     if (workspace_bytes < L.total) return fail(HLN_ENOMEM, "workspace too small: %zu < %zu", workspace_bytes, L.total);
-    const size_t stage = L.desc_bytes + L.tiles_bytes;
+    const size_t stage = L.stage_bytes;
     // inside a stream capture (ours or the caller's) the staging is the
     // frozen buffer reserved beforehand: no allocation, no host wait
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
@@ -428,6 +443,68 @@ hln_status enqueue_batch(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs
     int2* tiles_h = reinterpret_cast<int2*>(static_cast<char*>(*pin) + L.desc_bytes);
     int first[5];
     build_tables(plan, graphs, n_graphs, S, R, cc, h2, L, dev, desc_h, tiles_h, first);
+
+    // Graphs on the cooperative kernel, grouped by width: each group is one
+    // multi-graph launch whose partitions take its graphs longest work first
+    // (each to the least loaded partition).  Launch arguments and lists go
+    // into the staging with the tables.
+    char* const coop_ws = dev + L.stage_bytes + L.counters_bytes + L.heavy_bytes + L.vis_bytes + 2 * L.part_bytes;
+    void* const args_h = static_cast<char*>(*pin) + L.desc_bytes + L.tiles_bytes;
+    int* const lists_h = reinterpret_cast<int*>(static_cast<char*>(*pin) + L.desc_bytes + L.tiles_bytes + L.margs_bytes);
+    struct CoopGroup {
+        int width, parts, pfirst_off;
+    };
+    std::vector<CoopGroup> groups;
+    std::vector<int> single;                 // cooperative graphs at another width: one launch each
+    {
+        static const int kWidths[kCoopWidths] = {1024, 2048, 4096};
+        auto work = [&](int g) {
+            return static_cast<double>(graphs[g].n) * static_cast<double>(graphs[g].nnz + graphs[g].n);
+        };
+        int plist_n = 0, pfirst_n = n_graphs;
+        for (int g = 0; g < n_graphs; ++g) {
+            const int w = desc_h[g].width;
+            if (is_coop(w) && w != 1024 && w != 2048 && w != 4096) single.push_back(g);
+        }
+        for (int wi = 0; wi < kCoopWidths; ++wi) {
+            std::vector<int> members;
+            double total = 0.0, mx = 0.0;
+            for (int g = 0; g < n_graphs; ++g)
+                if (desc_h[g].width == kWidths[wi]) {
+                    members.push_back(g);
+                    total += work(g);
+                    mx = std::max(mx, work(g));
+                }
+            if (members.empty()) continue;
+            const int parts = std::max(1, std::min({L.coop_slices, static_cast<int>(members.size()),
+                                                    static_cast<int>(total / std::max(mx, 1.0))}));
+            std::sort(members.begin(), members.end(), [&](int x, int y) {
+                return work(x) > work(y) || (work(x) == work(y) && x < y);
+            });
+            std::vector<std::vector<int>> bins(parts);
+            std::vector<double> load(parts, 0.0);
+            for (int g : members) {
+                const int q = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+                bins[q].push_back(g);
+                load[q] += work(g);
+            }
+            int* pf = lists_h + pfirst_n;
+            for (int q = 0; q < parts; ++q) {
+                pf[q] = plist_n;
+                for (int g : bins[q]) {
+                    lists_h[plist_n++] = g;
+                    const hln_status r = hln::multi_fill(graphs[g], S[g], R[g], cc ? cc[g] : nullptr,
+                                                         h2 ? h2[g] : nullptr, kWidths[wi],
+                                                         coop_ws + static_cast<size_t>(q) * L.coop_slice_bytes,
+                                                         L.coop_slice_bytes, args_h, g);
+                    if (r != HLN_OK) return r;
+                }
+            }
+            pf[parts] = plist_n;
+            groups.push_back(CoopGroup{kWidths[wi], parts, pfirst_n});
+            pfirst_n += parts + 1;
+        }
+    }
     HLN_TRY_HIP(hipMemcpyAsync(dev, *pin, stage, hipMemcpyHostToDevice, st));
     if (!capture_staging) {
         if (!plan->staged) HLN_TRY_HIP(hipEventCreateWithFlags(&plan->staged, hipEventDisableTiming));
@@ -436,8 +513,8 @@ hln_status enqueue_batch(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs
     }
     const TileGraph* desc_d = reinterpret_cast<const TileGraph*>(dev);
     const int2* tiles_d = reinterpret_cast<const int2*>(dev + L.desc_bytes);
-    int* counters = reinterpret_cast<int*>(dev + L.desc_bytes + L.tiles_bytes);
-    char* p = dev + L.desc_bytes + L.tiles_bytes + L.counters_bytes + L.heavy_bytes;
+    int* counters = reinterpret_cast<int*>(dev + L.stage_bytes);
+    char* p = dev + L.stage_bytes + L.counters_bytes + L.heavy_bytes;
     void* vis = p;
     int32_t* s_part = reinterpret_cast<int32_t*>(p + L.vis_bytes);
     int32_t* h_part = reinterpret_cast<int32_t*>(p + L.vis_bytes + L.part_bytes);
@@ -476,14 +553,19 @@ hln_status enqueue_batch(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs
     }
     hipLaunchKernelGGL(k_batch_cc, dim3(gx, gy), dim3(256), 0, st, desc_d, n_graphs);
     HLN_TRY_HIP(hipGetLastError());
-    // graphs tuned (or too large) for the persistent cooperative kernel,
-    // one launch each, sharing one workspace region in stream order
-    void* coop_ws = p + L.vis_bytes + 2 * L.part_bytes;
-    for (int g = 0; g < n_graphs; ++g) {
-        if (!is_coop(desc_h[g].width)) continue;
+    // graphs tuned (or too large) for the persistent cooperative kernel: one
+    // multi-graph launch per width; any other width one launch per graph in
+    // the first slice
+    const void* args_d = dev + L.desc_bytes + L.tiles_bytes;
+    const int* lists_d = reinterpret_cast<const int*>(dev + L.desc_bytes + L.tiles_bytes + L.margs_bytes);
+    for (const CoopGroup& cg : groups) {
+        const hln_status r = hln::multi_launch(cg.width, args_d, lists_d, lists_d + cg.pfirst_off, cg.parts, st);
+        if (r != HLN_OK) return r;
+    }
+    for (int g : single) {
         hln_opts o{desc_h[g].width, 0, 0, nullptr, nullptr, 0};
         hln_status r = hln_closeness_layer(&graphs[g], nullptr, graphs[g].n, &o, S[g], R[g], cc ? cc[g] : nullptr,
-                                           h2 ? h2[g] : nullptr, coop_ws, L.coop_bytes, st);
+                                           h2 ? h2[g] : nullptr, coop_ws, L.coop_slice_bytes, st);
         if (r != HLN_OK) return r;
     }
     return HLN_OK;
@@ -564,8 +646,8 @@ hln_status hln_plan_capture(hln_plan* plan, const hln_csr* graphs, int32_t n_gra
         Layout L;
         hln_status s = plan_layout(plan, graphs, n_graphs, L);
         if (s != HLN_OK) return s;
-        HLN_TRY_HIP(hipHostMalloc(&plan->cap_pinned, L.desc_bytes + L.tiles_bytes, hipHostMallocDefault));
-        plan->cap_pinned_bytes = L.desc_bytes + L.tiles_bytes;
+        HLN_TRY_HIP(hipHostMalloc(&plan->cap_pinned, L.stage_bytes, hipHostMallocDefault));
+        plan->cap_pinned_bytes = L.stage_bytes;
     }
     HLN_TRY_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     hln_status s = enqueue_batch(plan, graphs, n_graphs, S, R, cc, h2, workspace, workspace_bytes, st, true);
@@ -587,7 +669,7 @@ hln_status hln_plan_reserve(hln_plan* plan, const hln_csr* graphs, int32_t n_gra
     Layout L;
     hln_status s = plan_layout(plan, graphs, n_graphs, L);
     if (s != HLN_OK) return s;
-    const size_t stage = L.desc_bytes + L.tiles_bytes;
+    const size_t stage = L.stage_bytes;
     if (plan->cap_pinned_bytes >= stage) return HLN_OK;
     if (plan->cap_pinned) HLN_TRY_HIP(hipHostFree(plan->cap_pinned));
     plan->cap_pinned = nullptr;

@@ -29,6 +29,21 @@ const DeviceInfo* device_info();
 // out of range.  nullptr (with the error set) on failure.
 int* fault_word();
 
+// Several graphs' all-source closeness in one cooperative launch, for the
+// batched path (hln_msbfs.hip).  The caller stages an array of launch
+// arguments (multi_args_bytes(n) bytes, filled on the host by multi_fill for
+// each graph: its working set is carved from the workspace slice of the
+// partition that runs it, each slice multi_slice_bytes() for the largest
+// graph it serves) and, in device memory, the partitions' graph lists:
+// plist (argument indices) and pfirst (parts + 1 offsets into plist).  Only
+// widths 1024, 2048 and 4096 are supported.
+size_t multi_args_bytes(int n_graphs);
+size_t multi_slice_bytes(int32_t n, int64_t nnz, int width_bits);
+hln_status multi_fill(const hln_csr& g, int64_t* S, int32_t* R, double* cc, int32_t* h2, int width_bits, void* slice,
+                      size_t slice_bytes, void* args_host, int index);
+hln_status multi_launch(int width_bits, const void* args_dev, const int* plist_dev, const int* pfirst_dev, int parts,
+                        hipStream_t st);
+
 // Bump allocator over a caller workspace (256-byte alignment).
 struct Arena {
     char* base;
@@ -122,11 +137,17 @@ struct NoDecision {
     __device__ bool operator()() const { return false; }
 };
 
-struct GridBarrier {
+// kWholeGrid: every block of the grid takes part (their number and this
+// block's index come from the dispatch); otherwise `nb` blocks of one
+// partition of the grid, this one being `bid` among them.
+template <bool kWholeGrid>
+struct GridBarrierT {
     unsigned long long* bar;
     int* fault;
     uint64_t limit;
     unsigned passed;                            // barriers this block has passed (thread 0's copy is used)
+    unsigned nb_part;                           // partition only: blocks taking part
+    unsigned bid_part;                          // partition only: this block's index among them
 
     template <class Pre = NoHook, class Decide = NoDecision>
     __device__ __forceinline__ BarrierResult sync(int flag, Pre pre = Pre(), Decide decide = Decide()) {
@@ -141,9 +162,10 @@ struct GridBarrier {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const unsigned e = passed;
             const unsigned par = e & 1u;
-            const unsigned nb = gridDim.x;
+            const unsigned nb = kWholeGrid ? gridDim.x : nb_part;
+            const unsigned bid = kWholeGrid ? blockIdx.x : bid_part;
             const unsigned groups = nb < kSubs ? nb : kSubs;
-            const unsigned g = blockIdx.x % groups;
+            const unsigned g = bid % groups;
             const unsigned members = nb / groups + (g < nb % groups ? 1u : 0u);
             unsigned long long* sub = bar + kSub * (g + kSubs * par);
             unsigned long long* root = bar + kSub * (2 * kSubs + par);
@@ -196,6 +218,8 @@ struct GridBarrier {
 
     __device__ __forceinline__ bool wait() { return sync(0).ok; }
 };
+using GridBarrier = GridBarrierT<true>;
+using PartBarrier = GridBarrierT<false>;
 
 }  // namespace dev
 }  // namespace hln

@@ -549,8 +549,12 @@ __device__ __forceinline__ LevelBufs level_bufs(const BfsArgs& a, const uint64_t
     return B;
 }
 
-template <int NW, int BLOCK, bool PER_SOURCE>
-__global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
+// The whole computation for one graph, run by `nblk` blocks (this one is
+// `blk`) that synchronise through `gb`: the grid of k_closeness, or one
+// partition of the grid of k_closeness_multi.  Returns false when a barrier
+// wait failed (every block then leaves).
+template <int NW, int BLOCK, bool PER_SOURCE, class Barrier>
+__device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, const unsigned blk, const unsigned nblk) {
     constexpr int kLpv = lpv<NW>();
     constexpr int W = 64 * NW;
     using Mask = MaskT<NW>;
@@ -560,17 +564,16 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
     const int gbase = lane - gl;
     const int k = gl & (NW - 1);
     const int sub = gl / NW;
-    const long long tid = static_cast<long long>(blockIdx.x) * BLOCK + threadIdx.x;
-    const long long nthreads = static_cast<long long>(gridDim.x) * BLOCK;
+    const long long tid = static_cast<long long>(blk) * BLOCK + threadIdx.x;
+    const long long nthreads = static_cast<long long>(nblk) * BLOCK;
     const long long gid = tid / kLpv;
     const long long ngroups = nthreads / kLpv;
     // block-interleaved thread and group numbers: consecutive indices fall in
     // different blocks, which spreads the block-local frontier lists
-    const long long tid_x = static_cast<long long>(threadIdx.x) * gridDim.x + blockIdx.x;
-    const long long gid_x = static_cast<long long>(threadIdx.x / kLpv) * gridDim.x + blockIdx.x;
+    const long long tid_x = static_cast<long long>(threadIdx.x) * nblk + blk;
+    const long long gid_x = static_cast<long long>(threadIdx.x / kLpv) * nblk + blk;
     Ctrl* ctrl = a.ctrl;
     const int seg_len = a.seg_len;
-    hln::dev::GridBarrier gb{a.bar, a.fault, a.wait_ticks, 0u};
 
     __shared__ int32_t s_cnt[PER_SOURCE ? W : 1];
     __shared__ int64_t s_S[PER_SOURCE ? W : 1];
@@ -626,11 +629,11 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
     }
     __syncthreads();
     if (threadIdx.x < kClasses && s_bins[threadIdx.x]) atomicAdd(&ctrl->bins[threadIdx.x], s_bins[threadIdx.x]);
-    if (!gb.wait()) return;
-    if (load_agent_i32(a.fault) != 0) return;              // uniform: read after the barrier
+    if (!gb.wait()) return false;
+    if (load_agent_i32(a.fault) != 0) return false;              // uniform: read after the barrier
 
     // ---- phase 1: class offsets
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blk == 0 && threadIdx.x == 0) {
         int acc = 0;
         for (int c = 0; c < kClasses; ++c) {
             int b = load_agent_i32(&ctrl->bins[c]);
@@ -639,7 +642,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
         }
         store_agent_i32(&ctrl->n_seg, acc);
     }
-    if (!gb.wait()) return;
+    if (!gb.wait()) return false;
 
     // ---- phase 2: fill the segment list (heavy rows first, then by
     // decreasing degree; order inside a class is arbitrary and does not
@@ -647,7 +650,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
     // Each block reserves one range per class for its vertices (LDS counts,
     // then one global add per class), so the class cursors see a few
     // thousand atomics rather than one per vertex.
-    for (long long base = static_cast<long long>(blockIdx.x) * BLOCK; base < n; base += nthreads) {
+    for (long long base = static_cast<long long>(blk) * BLOCK; base < n; base += nthreads) {
         const long long v = base + threadIdx.x;
         if (threadIdx.x < kClasses) s_bins[threadIdx.x] = 0;
         __syncthreads();
@@ -673,7 +676,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
         }
         __syncthreads();
     }
-    if (!gb.wait()) return;
+    if (!gb.wait()) return false;
     const long long n_seg = min(static_cast<long long>(load_agent_i32(&ctrl->n_seg)), a.seg_cap);
 
     const int n_batches = (a.n_src + W - 1) / W;
@@ -713,7 +716,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                 if ((threadIdx.x & 63) == 0)
                     __hip_atomic_store(&ctrl->gcm[i >> 6], word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (blk == 0 && threadIdx.x == 0) {
                 const int nx_slot = (phase + 1) % 3;
                 store_agent_i32(&ctrl->fbad[nx_slot], 0);
                 __hip_atomic_store(&ctrl->farcs[nx_slot], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -767,7 +770,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                         s_S[i] = 0;
                         s_R[i] = 0;
                     }
-                if (!gb.wait()) return;
+                if (!gb.wait()) return false;
                 for (long long i = tid_x; i < cnt; i += nthreads) {
                     const int s = a.sources[src0 + i];
                     const size_t w = static_cast<size_t>(s) * NW + (i >> 6);
@@ -784,7 +787,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
             }
             const hln::dev::BarrierResult br =
                 gb.sync(0, PhaseEnd{&s_fr, ctrl, phase}, Decide{ctrl, m_arcs, a.direction, a.alpha, phase});
-            if (!br.ok) return;
+            if (!br.ok) return false;
             push = br.decision;
             ++phase;
         }
@@ -798,7 +801,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
         Mask* flag_nx = static_cast<Mask*>(a.flagB);
         for (int d = 1;; ++d) {
             const int par = phase & 1;                   // this phase's list; the previous one is par ^ 1
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (blk == 0 && threadIdx.x == 0) {
                 const int nx_slot = (phase + 1) % 3;
                 store_agent_i32(&ctrl->fbad[nx_slot], 0);
                 __hip_atomic_store(&ctrl->farcs[nx_slot], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -831,7 +834,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
                         if (wl >= 0) store_agent_i32(&a.hcnt[wl], 1);
                     }
                 }
-                if (!gb.wait()) return;
+                if (!gb.wait()) return false;
                 // ---- part 2: finalise touched vertices; vertices whose nx
                 // word mask still holds the older frontier get it cleared
                 for (long long v0 = gid_x * kLpv; v0 < n; v0 += ngroups * kLpv) {
@@ -1009,8 +1012,8 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
             }
             const hln::dev::BarrierResult br =
                 gb.sync(any, PhaseEnd{&s_fr, ctrl, phase}, Decide{ctrl, m_arcs, a.direction, a.alpha, phase});
-            if (!br.ok) return;
-            if (a.trace && trace_row < a.trace_cap && blockIdx.x == 0 && threadIdx.x == 0) {
+            if (!br.ok) return false;
+            if (a.trace && trace_row < a.trace_cap && blk == 0 && threadIdx.x == 0) {
                 a.trace[4 * trace_row] = static_cast<int64_t>(__builtin_amdgcn_s_memrealtime());
                 a.trace[4 * trace_row + 3] = push ? 1 : 0;
             }
@@ -1019,7 +1022,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
             ++trace_row;
             if (!br.any) {
                 // level d found nothing new: the batch's largest eccentricity is d - 1
-                if (a.levels && blockIdx.x == 0 && threadIdx.x == 0) a.levels[b] = d;
+                if (a.levels && blk == 0 && threadIdx.x == 0) a.levels[b] = d;
                 break;
             }
             uint64_t* t = fr;
@@ -1031,17 +1034,17 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
         }
 
         if (PER_SOURCE) {
-            int64_t* pS = a.part + static_cast<size_t>(blockIdx.x) * 2 * W;
+            int64_t* pS = a.part + static_cast<size_t>(blk) * 2 * W;
             int64_t* pR = pS + W;
             for (int i = threadIdx.x; i < W; i += BLOCK) {
                 pS[i] = s_S[i];
                 pR[i] = s_R[i];
             }
-            if (!gb.wait()) return;
+            if (!gb.wait()) return false;
             for (long long i = tid; i < cnt; i += nthreads) {
                 int64_t sS = 0, sR = 0;
-                for (unsigned blk = 0; blk < gridDim.x; ++blk) {
-                    const int64_t* q = a.part + static_cast<size_t>(blk) * 2 * W;
+                for (unsigned bb = 0; bb < nblk; ++bb) {
+                    const int64_t* q = a.part + static_cast<size_t>(bb) * 2 * W;
                     sS += q[i];
                     sR += q[W + i];
                 }
@@ -1055,7 +1058,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
             const unsigned pos = 0xffffffffu - static_cast<unsigned>(hln::dev::load_agent(&ctrl->probe_key) & 0xffffffffull);
             for (long long v = tid; v < n; v += nthreads)
                 a.member[v] = ((a.vis[v * NW + (pos >> 6)] >> (pos & 63)) & 1ull) ? 1u : 0u;
-            if (!gb.wait()) return;
+            if (!gb.wait()) return false;
         }
     }
 
@@ -1065,7 +1068,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
     // the final level barrier)
     if (PER_SOURCE) {
         // listed sources: the last writes of S and R are the reduction above
-        if (a.cc && !gb.wait()) return;
+        if (a.cc && !gb.wait()) return false;
     }
     if (!PER_SOURCE || a.cc) {
         const long long n_out = PER_SOURCE ? a.n_src : n;
@@ -1089,12 +1092,66 @@ __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
             }
         }
     }
+    return true;
+}
+
+template <int NW, int BLOCK, bool PER_SOURCE>
+__global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
+    hln::dev::GridBarrier gb{a.bar, a.fault, a.wait_ticks, 0u, 0u, 0u};
+    (void)closeness_run<NW, BLOCK, PER_SOURCE>(a, gb, blockIdx.x, gridDim.x);
 }
 
 __global__ void k_zero_ctrl(Ctrl* c, unsigned long long* bar) {
     int* p = reinterpret_cast<int*>(c);
     for (int i = threadIdx.x; i < static_cast<int>(sizeof(Ctrl) / sizeof(int)); i += blockDim.x) p[i] = 0;
     for (int i = threadIdx.x; i < hln::dev::kBarrierWords; i += blockDim.x) bar[i] = 0;
+}
+
+// Several graphs (all sources, per-vertex sums) in one cooperative launch:
+// the grid is cut into `parts` partitions, partition p holding the blocks b
+// with b % parts == p (blocks are dealt to the XCDs in turn, so with 8
+// partitions each keeps to one XCD and its L2).  A partition runs its list
+// of graphs one after another with the single-graph algorithm and a barrier
+// of its own, clearing its control block between two graphs.  All graphs of
+// a partition share one workspace slice.
+template <int NW, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_closeness_multi(const BfsArgs* __restrict__ args,
+                                                           const int* __restrict__ plist,
+                                                           const int* __restrict__ pfirst, int parts) {
+    const unsigned np = static_cast<unsigned>(parts);
+    const unsigned p = blockIdx.x % np;
+    const unsigned nblk = gridDim.x / np;
+    const unsigned blk = blockIdx.x / np;
+    if (blk >= nblk) return;                              // blocks past the last full round take no part
+    const int i0 = pfirst[p];
+    const int i1 = pfirst[p + 1];
+    if (i0 >= i1) return;
+    const BfsArgs& first = args[plist[i0]];
+    hln::dev::PartBarrier gb{first.bar, first.fault, first.wait_ticks, 0u, nblk, blk};
+    for (int i = i0; i < i1; ++i) {
+        const BfsArgs a = args[plist[i]];
+        if (i > i0) {
+            if (!gb.wait()) return;
+            if (blk == 0) {
+                int* c = reinterpret_cast<int*>(a.ctrl);
+                for (int j = threadIdx.x; j < static_cast<int>(sizeof(Ctrl) / sizeof(int)); j += BLOCK) c[j] = 0;
+            }
+            if (!gb.wait()) return;
+        }
+        if (!closeness_run<NW, BLOCK, false>(a, gb, blk, nblk)) return;
+    }
+}
+
+// Control blocks and barrier words of the partitions' slices, before a
+// multi-graph launch (block p clears partition p's).
+__global__ void k_zero_parts(const BfsArgs* __restrict__ args, const int* __restrict__ plist,
+                             const int* __restrict__ pfirst) {
+    const int p = blockIdx.x;
+    if (pfirst[p] >= pfirst[p + 1]) return;
+    const BfsArgs& a = args[plist[pfirst[p]]];
+    int* c = reinterpret_cast<int*>(a.ctrl);
+    for (int i = threadIdx.x; i < static_cast<int>(sizeof(Ctrl) / sizeof(int)); i += blockDim.x) c[i] = 0;
+    for (int i = threadIdx.x; i < hln::dev::kBarrierWords; i += blockDim.x) a.bar[i] = 0;
 }
 
 struct Layout {
@@ -1207,6 +1264,60 @@ size_t workspace_bytes(int32_t n, int64_t nnz, int nw, int grid_cap) {
 
 int grid_cap_for(int cus) { return cus * 4; }
 
+// Carves one graph's working set out of `workspace` (laid out as
+// workspace_bytes() counts it) and fills its launch arguments.
+hln_status fill_args(BfsArgs& a, const hln_csr* g, const int32_t* sources, int32_t n_src, bool per_vertex, int nw,
+                     const hln_opts* opts, int64_t* S, int32_t* R, double* cc, int32_t* h2, void* workspace,
+                     size_t workspace_bytes_in, int grid_cap, int* fault) {
+    using hln::fail;
+    a = BfsArgs{};
+    const int n = g->n;
+    hln::Arena ar{static_cast<char*>(workspace), workspace_bytes_in};
+    const size_t words = static_cast<size_t>(n) * nw;
+    a.n = n;
+    a.n_src = n_src;
+    a.row_ptr = g->row_ptr;
+    a.col_idx = g->col_idx;
+    a.sources = sources;
+    a.listed = (sources != nullptr || per_vertex) ? 1 : 0;
+    a.ctrl = ar.take<Ctrl>(1);
+    a.bar = ar.take<unsigned long long>(hln::dev::kBarrierWords);
+    a.bufA = ar.take<uint64_t>(words);
+    a.bufB = ar.take<uint64_t>(words);
+    a.vis = ar.take<uint64_t>(words);
+    a.hacc = ar.take<uint64_t>(words);
+    a.flagA = ar.take<uint64_t>(n);
+    a.flagB = ar.take<uint64_t>(n);
+    a.hcnt = ar.take<int32_t>(n);
+    a.seg_cap = static_cast<long long>(n) + g->nnz / kSegLen + 1;
+    a.seg = ar.take<int4>(static_cast<size_t>(a.seg_cap));
+    a.segsat = ar.take<uint32_t>(static_cast<size_t>(a.seg_cap));
+    a.member = ar.take<uint32_t>(n);
+    a.seg_first = ar.take<int32_t>(n);
+    a.S32 = ar.take<uint32_t>(n);
+    a.nnz_cap = g->nnz;
+    a.part = ar.take<int64_t>(static_cast<size_t>(grid_cap) * 2 * 64 * nw);
+    a.S = S;
+    a.R = R;
+    a.H2 = h2;
+    a.cc = cc;
+    a.fault = fault;
+    a.wait_ticks = 1000000000ull;   // 10 s at 100 MHz
+    a.direction = opts ? opts->direction : 0;
+    a.levels = opts ? opts->levels : nullptr;
+    a.trace = opts ? opts->trace : nullptr;
+    a.trace_cap = opts ? opts->trace_cap : 0;
+    a.seg_len = kSegLen;
+    a.alpha = 32;   // measured on configs 2-4 once saturated vertices skip their pull work
+    if (const char* e = getenv("HLN_ALPHA")) a.alpha = std::max(1, atoi(e));
+    a.s32_levels = kS32Levels;
+    if (const char* e = getenv("HLN_S32_LEVELS")) a.s32_levels = std::min(kS32Levels, std::max(1, atoi(e)));
+    if (!a.ctrl || !a.bar || !a.part || !a.flagB || !a.seg_first || !a.S32 || !a.segsat || !a.member)
+        return fail(HLN_ENOMEM, "workspace carve failed");
+    return HLN_OK;
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -1260,50 +1371,13 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
     int* fault = hln::fault_word();
     if (!fault) return HLN_EDEVICE;
 
-    const int n = g->n;
-    hln::Arena ar{static_cast<char*>(workspace), workspace_bytes_in};
-    const size_t words = static_cast<size_t>(n) * nw;
     BfsArgs a{};
-    a.n = n;
-    a.n_src = n_src;
-    a.row_ptr = g->row_ptr;
-    a.col_idx = g->col_idx;
-    a.sources = sources;
-    a.listed = (sources != nullptr || per_vertex) ? 1 : 0;
-    a.ctrl = ar.take<Ctrl>(1);
-    a.bar = ar.take<unsigned long long>(hln::dev::kBarrierWords);
-    a.bufA = ar.take<uint64_t>(words);
-    a.bufB = ar.take<uint64_t>(words);
-    a.vis = ar.take<uint64_t>(words);
-    a.hacc = ar.take<uint64_t>(words);
-    a.flagA = ar.take<uint64_t>(n);
-    a.flagB = ar.take<uint64_t>(n);
-    a.hcnt = ar.take<int32_t>(n);
-    a.seg_cap = static_cast<long long>(n) + g->nnz / kSegLen + 1;
-    a.seg = ar.take<int4>(static_cast<size_t>(a.seg_cap));
-    a.segsat = ar.take<uint32_t>(static_cast<size_t>(a.seg_cap));
-    a.member = ar.take<uint32_t>(n);
-    a.seg_first = ar.take<int32_t>(n);
-    a.S32 = ar.take<uint32_t>(n);
-    a.nnz_cap = g->nnz;
-    a.part = ar.take<int64_t>(static_cast<size_t>(grid_cap) * 2 * 64 * nw);
-    a.S = S;
-    a.R = R;
-    a.H2 = h2;
-    a.cc = cc;
-    a.fault = fault;
-    a.wait_ticks = 1000000000ull;   // 10 s at 100 MHz
-    a.direction = opts ? opts->direction : 0;
-    a.levels = opts ? opts->levels : nullptr;
-    a.trace = opts ? opts->trace : nullptr;
-    a.trace_cap = opts ? opts->trace_cap : 0;
-    a.seg_len = kSegLen;
-    a.alpha = 32;   // measured on configs 2-4 once saturated vertices skip their pull work
-    if (const char* e = getenv("HLN_ALPHA")) a.alpha = std::max(1, atoi(e));
-    a.s32_levels = kS32Levels;
-    if (const char* e = getenv("HLN_S32_LEVELS")) a.s32_levels = std::min(kS32Levels, std::max(1, atoi(e)));
-    if (!a.ctrl || !a.bar || !a.part || !a.flagB || !a.seg_first || !a.S32 || !a.segsat || !a.member)
-        return fail(HLN_ENOMEM, "workspace carve failed");
+    {
+        const hln_status fs = fill_args(a, g, sources, n_src, per_vertex, nw, opts, S, R, cc, h2, workspace,
+                                        workspace_bytes_in, grid_cap, fault);
+        if (fs != HLN_OK) return fs;
+    }
+    const int n = g->n;
 
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(k_zero_ctrl, dim3(1), dim3(256), 0, st, a.ctrl, a.bar);
@@ -1325,3 +1399,85 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
 }
 
 }  // extern "C"
+
+namespace {
+
+template <int NW>
+hln_status launch_multi(const void* args_dev, const int* plist_dev, const int* pfirst_dev, int parts, int cus,
+                        hipStream_t st) {
+    constexpr int BLOCK = 1024;
+    const void* f = reinterpret_cast<const void*>(&k_closeness_multi<NW, BLOCK>);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, BLOCK, 0) != hipSuccess || per_cu < 1)
+        return hln::fail(HLN_EUNSUPPORTED, "multi-graph kernel does not fit a compute unit");
+    // one block per compute unit, as the single-graph launch; a whole number
+    // of rounds of partitions
+    const int grid = std::max(parts, (cus / parts) * parts);
+    if (getenv("HLN_VERBOSE"))
+        fprintf(stderr, "[hln] closeness multi NW=%d parts=%d grid=%d\n", NW, parts, grid);
+    const BfsArgs* args = static_cast<const BfsArgs*>(args_dev);
+    hipLaunchKernelGGL(k_zero_parts, dim3(parts), dim3(256), 0, st, args, plist_dev, pfirst_dev);
+    HLN_TRY_HIP(hipGetLastError());
+    void* kargs[] = {const_cast<BfsArgs**>(&args), const_cast<int**>(&plist_dev), const_cast<int**>(&pfirst_dev),
+                     &parts};
+    hipError_t e = hipLaunchCooperativeKernel(f, dim3(grid), dim3(BLOCK), kargs, 0, st);
+    if (e != hipSuccess) {
+        // refused inside a stream capture: the same grid as an ordinary
+        // kernel node (see launch())
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusActive) {
+            (void)hipGetLastError();
+            hipLaunchKernelGGL((k_closeness_multi<NW, BLOCK>), dim3(grid), dim3(BLOCK), 0, st, args, plist_dev,
+                               pfirst_dev, parts);
+            e = hipGetLastError();
+        }
+    }
+    if (e != hipSuccess) return hln::fail(HLN_EDEVICE, "multi-graph closeness launch failed: %s", hipGetErrorString(e));
+    return HLN_OK;
+}
+
+}  // namespace
+
+namespace hln {
+
+size_t multi_args_bytes(int n_graphs) { return sizeof(BfsArgs) * static_cast<size_t>(n_graphs > 0 ? n_graphs : 1); }
+
+size_t multi_slice_bytes(int32_t n, int64_t nnz, int width_bits) {
+    hln_opts o{width_bits, 0, 0, nullptr, nullptr, 0};
+    const int nw = width_words(&o);
+    if (nw == 0 || n < 1 || nnz < 0) return 0;
+    const DeviceInfo* di = device_info();
+    return Arena::round(workspace_bytes(n, nnz, nw, grid_cap_for(di ? di->cus : 256)));
+}
+
+hln_status multi_fill(const hln_csr& g, int64_t* S, int32_t* R, double* cc, int32_t* h2, int width_bits, void* slice,
+                      size_t slice_bytes, void* args_host, int index) {
+    hln_opts o{width_bits, 0, 0, nullptr, nullptr, 0};
+    const int nw = width_words(&o);
+    if (nw == 0) return fail(HLN_EINVAL, "unsupported width %d", width_bits);
+    if (g.nnz >= (1LL << 29) || static_cast<long long>(g.n) + g.nnz / kSegLen + 1 >= (1LL << 27) ||
+        static_cast<long long>(g.n) * nw * 8 >= (1LL << 31))
+        return fail(HLN_EUNSUPPORTED, "graph too large for 32-bit buffer offsets");
+    const DeviceInfo* di = device_info();
+    if (!di) return HLN_EDEVICE;
+    int* fault = fault_word();
+    if (!fault) return HLN_EDEVICE;
+    BfsArgs* a = static_cast<BfsArgs*>(args_host) + index;
+    return fill_args(*a, &g, nullptr, g.n, false, nw, &o, S, R, cc, h2, slice, slice_bytes, grid_cap_for(di->cus),
+                     fault);
+}
+
+hln_status multi_launch(int width_bits, const void* args_dev, const int* plist_dev, const int* pfirst_dev, int parts,
+                        hipStream_t st) {
+    const DeviceInfo* di = device_info();
+    if (!di) return HLN_EDEVICE;
+    if (parts < 1 || parts > di->cus) return fail(HLN_EINVAL, "bad partition count %d", parts);
+    switch (width_bits) {
+        case 1024: return launch_multi<16>(args_dev, plist_dev, pfirst_dev, parts, di->cus, st);
+        case 2048: return launch_multi<32>(args_dev, plist_dev, pfirst_dev, parts, di->cus, st);
+        case 4096: return launch_multi<64>(args_dev, plist_dev, pfirst_dev, parts, di->cus, st);
+        default: return fail(HLN_EUNSUPPORTED, "multi-graph launch at width %d", width_bits);
+    }
+}
+
+}  // namespace hln

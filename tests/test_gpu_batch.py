@@ -118,3 +118,38 @@ def test_batch_large_graphs_use_the_persistent_kernel():
     torch.cuda.synchronize()
     P.device_status()
     check(gnp, outs, "large")
+
+
+def test_batch_several_persistent_graphs_share_one_launch():
+    """Six graphs above the LDS-tile limit go through one multi-graph launch
+    whose partitions of the grid run them concurrently (longest work first),
+    eagerly and captured in a hipGraph; every output against the oracle."""
+    rng = np.random.default_rng(11)
+    sizes = [66000, 70500, 68000, 72000, 67000, 69000]
+    gnp = []
+    for n in sizes:
+        m = int(n * rng.choice([0.7, 1.0, 1.5]))
+        keys = G.take_distinct(G.er_draw(n), m, n, rng)
+        gnp.append(csr_np(n, *G.keys_to_edges(keys, n)))
+    gnp.append(mixed_graphs(12, [900])[0])
+    plan = P.Plan()
+    assert all(plan.width(n) >= 512 for n in sizes)
+    graphs = [graph_dev(P, rp, ci) for rp, ci in gnp]
+    outs = P.Plan.outputs(graphs, want_h2=True)
+    plan.run(graphs, outs)
+    torch.cuda.synchronize()
+    P.device_status()
+    check(gnp, outs, "multi")
+    ws = P.workspace(plan.workspace_size(graphs))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan.capture(graphs, outs, ws, stream)
+    for rep in range(2):
+        for o in outs:
+            o["S"].fill_(-1)
+            o["R"].fill_(-1)
+        torch.cuda.synchronize()
+        plan.replay(stream)
+        stream.synchronize()
+        P.device_status()
+        check(gnp, outs, "multi-replay%d" % rep)
