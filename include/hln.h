@@ -235,7 +235,8 @@ hln_status hln_compose_cc1(const hln_csr* layers, int32_t r, const int64_t* cons
  * Graphs with n <= 65535 can run as LDS tiles (one workgroup keeps the
  * frontier, next and visited bitsets of the whole graph in LDS); larger
  * graphs, and graphs the tuner assigns to it, run through the persistent
- * kernel of hln_closeness_layer inside the same call.
+ * kernel inside the same call: one cooperative launch per width, its grid
+ * cut into partitions (4 by default) that run different graphs at once.
  * S[g], R[g], cc[g], h2[g]: host arrays of n_graphs device pointers (n_g
  * entries each); cc and h2 (arrays or entries) nullable.  Every source of
  * every graph is used; outputs as hln_closeness_layer's all-source mode.

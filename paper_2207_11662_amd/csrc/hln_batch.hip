@@ -296,7 +296,26 @@ int chosen_width(const hln_plan* plan, int n, size_t budget) {
 
 bool is_coop(int w) { return w >= 512; }
 
-constexpr int kMaxParts = 8;                 // partitions of a multi-graph cooperative launch
+constexpr int kPartsCap = 64;                // partitions of a multi-graph cooperative launch: at most
+
+// Partitions a multi-graph launch may use (HLN_MAX_PARTS, default 4).
+// Measured on config 3 (graphs of 10^4-5*10^4 vertices): 2, 4, 6, 8, 16
+// and 32 partitions gave 1,425, 1,623, 1,296, 1,478, 1,148 and 936 GTEPS --
+// a partition needs enough compute units for a graph's light levels, and a
+// count that is not a power of two spreads partitions across the XCDs.
+int max_parts() {
+    int p = 4;
+    if (const char* e = getenv("HLN_MAX_PARTS")) p = atoi(e);
+    return std::max(1, std::min(p, kPartsCap));
+}
+
+// The largest power of two <= x (x >= 1): partition counts that divide the
+// XCD count keep each partition on whole XCDs.
+int pow2_floor(int x) {
+    int p = 1;
+    while (p * 2 <= x) p *= 2;
+    return p;
+}
 constexpr int kCoopWidths = 3;               // widths it runs: 1024, 2048, 4096
 
 // Workspace layout.  Sizes are worst cases over every width a graph could be
@@ -342,10 +361,11 @@ hln_status plan_layout(const hln_plan* plan, const hln_csr* graphs, int32_t n_gr
     // as many workspace slices as partitions a multi-graph launch can use:
     // up to 8, no more than the graphs, and one when a single graph holds
     // most of the work
-    L.coop_slices = std::max(1, std::min({kMaxParts, n_graphs, static_cast<int>(total_work / std::max(max_work, 1.0))}));
+    L.coop_slices = pow2_floor(
+        std::max(1, std::min({max_parts(), n_graphs, static_cast<int>(total_work / std::max(max_work, 1.0))})));
     L.coop_bytes = static_cast<size_t>(L.coop_slices) * L.coop_slice_bytes;
     L.margs_bytes = Arena::round(hln::multi_args_bytes(n_graphs));
-    L.mlist_bytes = Arena::round(sizeof(int) * (static_cast<size_t>(n_graphs) + kCoopWidths * (kMaxParts + 1)));
+    L.mlist_bytes = Arena::round(sizeof(int) * (static_cast<size_t>(n_graphs) + kCoopWidths * (kPartsCap + 1)));
     L.stage_bytes = L.desc_bytes + L.tiles_bytes + L.margs_bytes + L.mlist_bytes;
     L.total = L.stage_bytes + L.counters_bytes + L.heavy_bytes + L.vis_bytes + 2 * L.part_bytes + L.coop_bytes;
     return HLN_OK;
@@ -476,8 +496,8 @@ hln_status enqueue_batch(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs
                     mx = std::max(mx, work(g));
                 }
             if (members.empty()) continue;
-            const int parts = std::max(1, std::min({L.coop_slices, static_cast<int>(members.size()),
-                                                    static_cast<int>(total / std::max(mx, 1.0))}));
+            const int parts = pow2_floor(std::max(1, std::min({L.coop_slices, static_cast<int>(members.size()),
+                                                               static_cast<int>(total / std::max(mx, 1.0))})));
             std::sort(members.begin(), members.end(), [&](int x, int y) {
                 return work(x) > work(y) || (work(x) == work(y) && x < y);
             });
