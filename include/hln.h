@@ -104,6 +104,28 @@ hln_status hln_csr_from_edges(int32_t n, int64_t m, const int32_t* eu, const int
                               int32_t* row_ptr, int32_t* col_idx,
                               void* workspace, size_t workspace_bytes, void* stream);
 
+/* hln_csr_from_edges_batch: hln_csr_from_edges of `count` edge lists in one
+ * set of launches (many small layers, e.g. the layers of many HoMLNs, at
+ * the cost of one large one).  lists [host] array of count descriptors; each
+ * list's outputs are exactly those of hln_csr_from_edges on it, under the
+ * same rules (n >= 1, 0 <= m <= 2^30, row_ptr always, eu / ev / col_idx when
+ * m > 0; ids outside [0, n) a device-side fault).  The totals sum(2 m) and
+ * sum(n + 1) must stay below 2^31 - 1 (HLN_EUNSUPPORTED: split the batch).
+ * Nothing is staged on the host, so the call can be captured into a
+ * hipGraph; the lists' outputs must not overlap.  count = 0 does nothing.
+ * The workspace size reads only n and m (0 for invalid sizes). */
+typedef struct {
+    int32_t n;
+    int64_t m;
+    const int32_t* eu;     /* [dev] m */
+    const int32_t* ev;     /* [dev] m */
+    int32_t* row_ptr;      /* [dev] n + 1, output */
+    int32_t* col_idx;      /* [dev] room for 2 m, output */
+} hln_edge_list;
+size_t hln_csr_from_edges_batch_workspace_size(const hln_edge_list* lists, int32_t count);
+hln_status hln_csr_from_edges_batch(const hln_edge_list* lists, int32_t count, void* workspace,
+                                    size_t workspace_bytes, void* stream);
+
 /* hln_csr_validate: checks the CSR conventions on the device and writes a
  * bit mask to *result [dev] (0 = valid): 1 row_ptr not monotone or
  * row_ptr[0] != 0 or row_ptr[n] != nnz, 2 id out of range, 4 row not
@@ -245,7 +267,12 @@ hln_status hln_compose_cc1(const hln_csr* layers, int32_t r, const int64_t* cons
  * and with the persistent kernel at 1024, 2048 and 4096 sources, and keeps
  * the fastest; it synchronises `stream` and overwrites that graph's S and
  * R.  hln_plan_width reports the width a graph of n vertices gets (untuned:
- * the widest fitting tile, else 4096).
+ * the widest fitting tile, else 4096).  hln_plan_set_width sets the choice
+ * of n's log2 class by hand (a tuned plan saved and restored, or two plans
+ * made to agree): 8, 16, 32 or 64 for LDS tiles (narrowed to the widest
+ * that fits a graph, the persistent kernel at 4096 where none does), 512,
+ * 1024, 2048 or 4096 for the persistent kernel, 0 for the untuned default;
+ * any other width is HLN_EINVAL and changes nothing.
  * hln_plan_capture records the whole batch (staging copy, preparation,
  * tile launches, closeness pass) into a hipGraph owned by the plan, which
  * hln_plan_replay launches on `stream`; the captured buffers must stay
@@ -258,6 +285,7 @@ typedef struct hln_plan hln_plan;
 hln_status hln_plan_create(hln_plan** plan);
 void hln_plan_destroy(hln_plan* plan);
 int32_t hln_plan_width(const hln_plan* plan, int32_t n);
+hln_status hln_plan_set_width(hln_plan* plan, int32_t n, int32_t width);
 size_t hln_closeness_batch_workspace_size(const hln_plan* plan, const hln_csr* graphs, int32_t n_graphs);
 hln_status hln_closeness_batch(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs, int64_t* const* S,
                                int32_t* const* R, double* const* cc, int32_t* const* h2,

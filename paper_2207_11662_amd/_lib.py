@@ -21,11 +21,12 @@ _STATUS = {0: "HLN_OK", 1: "HLN_EINVAL", 2: "HLN_ENOMEM", 3: "HLN_EDEVICE", 4: "
 # every symbol include/hln.h declares (checked by the tests)
 EXPORTS = [
     "hln_last_error", "hln_version", "hln_device_cu_count", "hln_device_status",
-    "hln_csr_from_edges_workspace_size", "hln_csr_from_edges", "hln_csr_validate",
+    "hln_csr_from_edges_workspace_size", "hln_csr_from_edges", "hln_csr_from_edges_batch_workspace_size",
+    "hln_csr_from_edges_batch", "hln_csr_validate",
     "hln_compose_workspace_size", "hln_compose_and", "hln_compose_or",
     "hln_closeness_workspace_size", "hln_closeness_layer", "hln_closeness_estimate",
     "hln_compose_cc_topk_workspace_size", "hln_compose_cc_topk", "hln_compose_cc1_workspace_size", "hln_compose_cc1",
-    "hln_plan_create", "hln_plan_destroy", "hln_plan_width", "hln_closeness_batch_workspace_size",
+    "hln_plan_create", "hln_plan_destroy", "hln_plan_width", "hln_plan_set_width", "hln_closeness_batch_workspace_size",
     "hln_closeness_batch", "hln_plan_tune", "hln_plan_capture", "hln_plan_replay", "hln_plan_reserve",
     "hln_mlp_param_count", "hln_proposer_features", "hln_mlp_init", "hln_mlp_forward",
     "hln_mlp_train_workspace_size", "hln_mlp_train_step", "hln_topk_workspace_size", "hln_topk", "hln_rank_labels",
@@ -43,6 +44,11 @@ class HlnError(RuntimeError):
 
 class hln_csr(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p)]
+
+
+class hln_edge_list(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("eu", ctypes.c_void_p), ("ev", ctypes.c_void_p),
                 ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p)]
 
 
@@ -73,6 +79,8 @@ def lib():
         "hln_device_status": ([P], st),
         "hln_csr_from_edges_workspace_size": ([i32, i64], sz),
         "hln_csr_from_edges": ([i32, i64, P, P, P, P, P, sz, P], st),
+        "hln_csr_from_edges_batch_workspace_size": ([ctypes.POINTER(hln_edge_list), i32], sz),
+        "hln_csr_from_edges_batch": ([ctypes.POINTER(hln_edge_list), i32, P, sz, P], st),
         "hln_csr_validate": ([csr_p, P, P], st),
         "hln_compose_workspace_size": ([csr_p, i32], sz),
         "hln_compose_and": ([csr_p, i32, P, P, i64, P, sz, P], st),
@@ -87,6 +95,7 @@ def lib():
         "hln_plan_create": ([ctypes.POINTER(ctypes.c_void_p)], st),
         "hln_plan_destroy": ([P], None),
         "hln_plan_width": ([P, i32], i32),
+        "hln_plan_set_width": ([P, i32, i32], st),
         "hln_closeness_batch_workspace_size": ([P, csr_p, i32], sz),
         "hln_closeness_batch": ([P, csr_p, i32, P, P, P, P, P, sz, P], st),
         "hln_plan_tune": ([P, csr_p, i32, P, P, P, sz, P], st),
@@ -247,6 +256,47 @@ def hln_csr_from_edges(n: int, eu: torch.Tensor, ev: torch.Tensor, ws: torch.Ten
     return Graph(out[0], out[1][:max(2 * m, 0)] if m else out[1][:0], 2 * m)
 
 
+def _edge_lists(items, outs):
+    arr = (hln_edge_list * max(len(items), 1))()
+    for i, ((n, eu, ev), (rp, ci)) in enumerate(zip(items, outs)):
+        assert eu.dtype == torch.int32 and ev.dtype == torch.int32 and eu.numel() == ev.numel()
+        assert rp.numel() >= n + 1 and ci.numel() >= 2 * eu.numel()
+        arr[i] = hln_edge_list(n, int(eu.numel()), _ptr(eu), _ptr(ev), _ptr(rp), _ptr(ci))
+    return arr
+
+
+def csr_from_edges_batch_workspace_size(items) -> int:
+    """Workspace bytes of hln_csr_from_edges_batch for (n, eu, ev) lists."""
+    arr = (hln_edge_list * max(len(items), 1))()
+    for i, (n, eu, _) in enumerate(items):
+        arr[i] = hln_edge_list(n, int(eu.numel()), None, None, None, None)
+    return int(lib().hln_csr_from_edges_batch_workspace_size(arr, len(items)))
+
+
+def hln_csr_from_edges_batch(items, ws: torch.Tensor | None = None, outs=None, stream=None) -> list:
+    """hln_csr_from_edges of many edge lists in one set of launches.  items:
+    (n, eu, ev) per list (int32 device tensors); outs: optional (row_ptr,
+    col_idx) per list.  Returns one Graph per list (nnz = the 2*m bound)."""
+    if not items:
+        return []
+    dev = items[0][1].device
+    if outs is None:
+        outs = [(torch.empty(n + 1, dtype=torch.int32, device=dev), torch.empty(max(2 * eu.numel(), 1), dtype=torch.int32,
+                                                                               device=dev)) for n, eu, _ in items]
+    arr = _edge_lists(items, outs)
+    need = int(lib().hln_csr_from_edges_batch_workspace_size(arr, len(items)))
+    if need == 0:           # invalid sizes: the call itself reports them
+        check(lib().hln_csr_from_edges_batch(arr, len(items), None, 0, _stream(stream)))
+    if ws is None or ws.numel() < need:
+        ws = workspace(need, dev)
+    check(lib().hln_csr_from_edges_batch(arr, len(items), _ptr(ws), ws.numel(), _stream(stream)))
+    res = []
+    for (n, eu, _), (rp, ci) in zip(items, outs):
+        m = int(eu.numel())
+        res.append(Graph(rp, ci[:2 * m] if m else ci[:0], 2 * m))
+    return res
+
+
 def hln_csr_validate(g: Graph, stream=None) -> int:
     """Bit mask of CSR convention violations (0 = valid); synchronises."""
     res = torch.zeros(1, dtype=torch.int32, device=g.row_ptr.device)
@@ -373,6 +423,10 @@ class Plan:
 
     def width(self, n: int) -> int:
         return int(lib().hln_plan_width(self.h, n))
+
+    def set_width(self, n: int, width: int):
+        """Set the width of n's log2(n) class (0: the untuned default)."""
+        check(lib().hln_plan_set_width(self.h, n, width))
 
     def _args(self, graphs, outs):
         arr = _layers_c(graphs)

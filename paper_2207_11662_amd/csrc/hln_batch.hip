@@ -624,6 +624,19 @@ int32_t hln_plan_width(const hln_plan* plan, int32_t n) {
     return chosen_width(plan, n, lds_budget());
 }
 
+hln_status hln_plan_set_width(hln_plan* plan, int32_t n, int32_t width) {
+    hln::clear_error();
+    if (!plan) return hln::fail(HLN_EINVAL, "plan is NULL");
+    if (n < 1) return hln::fail(HLN_EINVAL, "n must be >= 1 (got %d)", n);
+    switch (width) {
+        case 0: case 8: case 16: case 32: case 64: case 512: case 1024: case 2048: case 4096: break;
+        default: return hln::fail(HLN_EINVAL, "width %d is not 0, a tile width (8/16/32/64) or a persistent one "
+                                              "(512/1024/2048/4096)", width);
+    }
+    plan->width_for_class[log2_class(n)] = width;
+    return HLN_OK;
+}
+
 size_t hln_closeness_batch_workspace_size(const hln_plan* plan, const hln_csr* graphs, int32_t n_graphs) {
     Layout L;
     if (plan_layout(plan, graphs, n_graphs, L) != HLN_OK) return 0;

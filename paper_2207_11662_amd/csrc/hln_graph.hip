@@ -104,6 +104,108 @@ __global__ void k_ingest_fill(int n, const unsigned long long* __restrict__ keys
     }
 }
 
+// ---------------------------------------------------------- batched ingest
+// Many edge lists in one set of launches: list s owns edges [k_off[s]/2,
+// k_off[s+1]/2) of the concatenation, keys [k_off[s], k_off[s+1]) and
+// degree counters [d_off[s], d_off[s+1]) (n + 1 of them).  Keys of every
+// list are sorted at once as segments; flags and degrees are scanned over
+// the concatenation and each list subtracts the value at its own start.
+
+struct IngestList {
+    const int32_t* eu;
+    const int32_t* ev;
+    int32_t* row_ptr;
+    int32_t* col_idx;
+    int n;
+};
+
+// The list table and its offset arrays are written from kernel arguments
+// (no host staging, so the call can be captured), kPutChunk lists a launch.
+constexpr int kPutChunk = 24;
+struct PutChunk {
+    IngestList l[kPutChunk];
+    long long k_off[kPutChunk + 1], d_off[kPutChunk + 1], t_off[kPutChunk + 1];
+    int first, count;
+};
+
+__global__ void k_put_lists(PutChunk c, IngestList* lists, long long* k_off, long long* d_off, long long* t_off) {
+    const int i = threadIdx.x;
+    if (i < c.count) lists[c.first + i] = c.l[i];
+    if (i <= c.count) {
+        k_off[c.first + i] = c.k_off[i];
+        d_off[c.first + i] = c.d_off[i];
+        t_off[c.first + i] = c.t_off[i];
+    }
+}
+
+// largest s in [0, nseg) with off[s] <= x
+__device__ __forceinline__ int list_of(const long long* __restrict__ off, int nseg, long long x) {
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void k_bi_keys(const IngestList* __restrict__ lists, const long long* __restrict__ k_off, int nl,
+                          long long edges, unsigned long long* keys, int* fault) {
+    for (long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; e < edges;
+         e += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const int s = list_of(k_off, nl, 2 * e);
+        const IngestList L = lists[s];
+        const long long i = e - k_off[s] / 2;
+        const unsigned long long N = static_cast<unsigned long long>(L.n);
+        const int u = L.eu[i], v = L.ev[i];
+        unsigned long long k0 = N * N, k1 = N * N;
+        if (static_cast<unsigned>(u) >= static_cast<unsigned>(L.n) || static_cast<unsigned>(v) >= static_cast<unsigned>(L.n)) {
+            hln::dev::store_agent_i32(fault, 2);
+        } else if (u != v) {
+            k0 = static_cast<unsigned long long>(u) * N + static_cast<unsigned long long>(v);
+            k1 = static_cast<unsigned long long>(v) * N + static_cast<unsigned long long>(u);
+        }
+        keys[2 * e] = k0;
+        keys[2 * e + 1] = k1;
+    }
+}
+
+__global__ void k_bi_mark(const IngestList* __restrict__ lists, const long long* __restrict__ k_off, int nl,
+                          const unsigned long long* __restrict__ keys, long long count, int32_t* flag) {
+    for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+         i += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const int s = list_of(k_off, nl, i);
+        const unsigned long long N = static_cast<unsigned long long>(lists[s].n);
+        const unsigned long long k = keys[i];
+        flag[i] = (k < N * N && (i == k_off[s] || keys[i - 1] != k)) ? 1 : 0;
+    }
+}
+
+__global__ void k_bi_fill(const IngestList* __restrict__ lists, const long long* __restrict__ k_off,
+                          const long long* __restrict__ d_off, int nl, const unsigned long long* __restrict__ keys,
+                          long long count, const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
+                          int32_t* deg) {
+    for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+         i += static_cast<long long>(gridDim.x) * blockDim.x) {
+        if (!flag[i]) continue;
+        const int s = list_of(k_off, nl, i);
+        const IngestList L = lists[s];
+        const unsigned long long N = static_cast<unsigned long long>(L.n);
+        const unsigned long long k = keys[i];
+        L.col_idx[pos[i] - pos[k_off[s]]] = static_cast<int32_t>(k % N);
+        atomicAdd(&deg[d_off[s] + static_cast<long long>(k / N)], 1);
+    }
+}
+
+__global__ void k_bi_rowptr(const IngestList* __restrict__ lists, const long long* __restrict__ d_off, int nl,
+                            long long count, const int32_t* __restrict__ dscan) {
+    for (long long j = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; j < count;
+         j += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const int s = list_of(d_off, nl, j);
+        lists[s].row_ptr[j - d_off[s]] = dscan[j] - dscan[d_off[s]];
+    }
+}
+
 // ---------------------------------------------------------------- validate
 
 __global__ void k_validate(int n, long long nnz, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
@@ -246,6 +348,43 @@ hln_status check_layers(const hln_csr* layers, int32_t r, LayerSet& L) {
     return HLN_OK;
 }
 
+// Sizes of a batched ingest; HLN_OK with the totals, else the argument error.
+struct BatchSizes {
+    long long edges = 0, keys = 0, degs = 0, tiles = 0;
+    int key_bits = 1;
+};
+
+hln_status batch_sizes(const hln_edge_list* lists, int32_t count, BatchSizes& B, bool check_ptrs) {
+    using hln::fail;
+    if (count < 0) return fail(HLN_EINVAL, "count must be >= 0");
+    if (count > 0 && !lists) return fail(HLN_EINVAL, "lists is NULL");
+    for (int s = 0; s < count; ++s) {
+        const hln_edge_list& l = lists[s];
+        if (l.n < 1) return fail(HLN_EINVAL, "list %d: n must be >= 1", s);
+        if (l.m < 0 || l.m > (1ll << 30)) return fail(HLN_EINVAL, "list %d: m out of range", s);
+        if (check_ptrs && (!l.row_ptr || (l.m > 0 && (!l.eu || !l.ev || !l.col_idx))))
+            return fail(HLN_EINVAL, "list %d: NULL array", s);
+        B.edges += l.m;
+        B.degs += static_cast<long long>(l.n) + 1;
+        B.tiles += hln::prim::seg_sort_tiles(2 * l.m);
+        if (l.m > 0) B.key_bits = std::max(B.key_bits, key_bits_for(l.n));
+    }
+    B.keys = 2 * B.edges;
+    if (B.keys >= (1ll << 31) - 1 || B.degs >= (1ll << 31) - 1)
+        return fail(HLN_EUNSUPPORTED, "batch too large (arcs %lld, vertices %lld): split it", B.keys, B.degs);
+    return HLN_OK;
+}
+
+size_t batch_workspace(int32_t count, const BatchSizes& B) {
+    using hln::Arena;
+    const long long a = std::max<long long>(B.keys, 1);
+    const size_t L1 = static_cast<size_t>(count) + 1;
+    return Arena::round(L1 * sizeof(IngestList)) + 3 * Arena::round(L1 * 8) + 2 * Arena::round(static_cast<size_t>(a) * 8) +
+           2 * Arena::round(static_cast<size_t>(a + 1) * 4) + 2 * Arena::round(static_cast<size_t>(B.degs + 1) * 4) +
+           std::max(hln::prim::seg_sort_workspace(B.tiles),
+                    hln::prim::scan_workspace(std::max(a, B.degs) + 1));
+}
+
 }  // namespace
 
 extern "C" {
@@ -298,6 +437,85 @@ hln_status hln_csr_from_edges(int32_t n, int64_t m, const int32_t* eu, const int
     }
     hln_status s = hln::prim::scan_exclusive<int32_t>(deg, row_ptr, n, sws, sws_bytes, st);
     if (s != HLN_OK) return s;
+    HLN_TRY_HIP(hipGetLastError());
+    return HLN_OK;
+}
+
+size_t hln_csr_from_edges_batch_workspace_size(const hln_edge_list* lists, int32_t count) {
+    BatchSizes B;
+    if (batch_sizes(lists, count, B, false) != HLN_OK) return 0;
+    return batch_workspace(count, B);
+}
+
+hln_status hln_csr_from_edges_batch(const hln_edge_list* lists, int32_t count, void* workspace,
+                                    size_t workspace_bytes, void* stream) {
+    using hln::fail;
+    hln::clear_error();
+    BatchSizes B;
+    hln_status s = batch_sizes(lists, count, B, true);
+    if (s != HLN_OK) return s;
+    if (count == 0) return HLN_OK;
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % hln::Arena::kAlign)
+        return fail(HLN_EINVAL, "workspace NULL or not 256-byte aligned");
+    const size_t need = batch_workspace(count, B);
+    if (workspace_bytes < need) return fail(HLN_ENOMEM, "workspace too small: %zu < %zu", workspace_bytes, need);
+    int* fault = hln::fault_word();
+    if (!fault) return HLN_EDEVICE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const long long a = std::max<long long>(B.keys, 1);
+    hln::Arena ar{static_cast<char*>(workspace), workspace_bytes};
+    IngestList* tab = ar.take<IngestList>(count + 1);
+    long long* k_off = ar.take<long long>(count + 1);
+    long long* d_off = ar.take<long long>(count + 1);
+    long long* t_off = ar.take<long long>(count + 1);
+    unsigned long long* keys = ar.take<unsigned long long>(a);
+    unsigned long long* alt = ar.take<unsigned long long>(a);
+    int32_t* flag = ar.take<int32_t>(a + 1);
+    int32_t* pos = ar.take<int32_t>(a + 1);
+    int32_t* deg = ar.take<int32_t>(B.degs + 1);
+    int32_t* dscan = ar.take<int32_t>(B.degs + 1);
+    void* sws = ar.base + ar.off;
+    const size_t sws_bytes = workspace_bytes - ar.off;
+
+    long long ko = 0, dof = 0, to = 0;
+    for (int first = 0; first < count; first += kPutChunk) {
+        PutChunk c{};
+        c.first = first;
+        c.count = std::min(kPutChunk, count - first);
+        for (int i = 0; i <= c.count; ++i) {
+            c.k_off[i] = ko;
+            c.d_off[i] = dof;
+            c.t_off[i] = to;
+            if (i == c.count) break;
+            const hln_edge_list& l = lists[first + i];
+            c.l[i] = IngestList{l.eu, l.ev, l.row_ptr, l.col_idx, l.n};
+            ko += 2 * l.m;
+            dof += static_cast<long long>(l.n) + 1;
+            to += hln::prim::seg_sort_tiles(2 * l.m);
+        }
+        hipLaunchKernelGGL(k_put_lists, dim3(1), dim3(64), 0, st, c, tab, k_off, d_off, t_off);
+    }
+    HLN_TRY_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_zero_i32, dim3(grid_for(B.degs)), dim3(256), 0, st, deg, B.degs);
+    const unsigned long long* sorted = keys;
+    if (B.edges > 0) {
+        hipLaunchKernelGGL(k_bi_keys, dim3(grid_for(B.edges)), dim3(256), 0, st, tab, k_off, count, B.edges, keys,
+                           fault);
+        unsigned long long* out = nullptr;
+        s = hln::prim::sort_keys_segmented(keys, alt, k_off, t_off, count, B.tiles, B.key_bits, sws, sws_bytes, st,
+                                           &out);
+        if (s != HLN_OK) return s;
+        sorted = out;
+        hipLaunchKernelGGL(k_bi_mark, dim3(grid_for(B.keys)), dim3(256), 0, st, tab, k_off, count, sorted, B.keys,
+                           flag);
+        s = hln::prim::scan_exclusive<int32_t>(flag, pos, B.keys, sws, sws_bytes, st);
+        if (s != HLN_OK) return s;
+        hipLaunchKernelGGL(k_bi_fill, dim3(grid_for(B.keys)), dim3(256), 0, st, tab, k_off, d_off, count, sorted,
+                           B.keys, flag, pos, deg);
+    }
+    s = hln::prim::scan_exclusive<int32_t>(deg, dscan, B.degs, sws, sws_bytes, st);
+    if (s != HLN_OK) return s;
+    hipLaunchKernelGGL(k_bi_rowptr, dim3(grid_for(B.degs)), dim3(256), 0, st, tab, d_off, count, B.degs, dscan);
     HLN_TRY_HIP(hipGetLastError());
     return HLN_OK;
 }

@@ -100,43 +100,40 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const T* in, T* out, 
     }
 }
 
-__global__ __launch_bounds__(kSortBlock) void k_sort_hist(const unsigned long long* __restrict__ keys, long long count,
-                                                          int shift, int nb, int32_t* hist) {
-    __shared__ int s_h[kRadix];
+// Histogram of one tile's digits, keys [begin, end).
+__device__ __forceinline__ void hist_tile(const unsigned long long* __restrict__ keys, long long begin, long long end,
+                                          int shift, int* s_h) {
     s_h[threadIdx.x] = 0;
     __syncthreads();
-    const long long base = static_cast<long long>(blockIdx.x) * kSortTile;
     for (int r = 0; r < kSortRounds; ++r) {
-        const long long i = base + r * kSortBlock + threadIdx.x;
-        if (i < count) atomicAdd(&s_h[(keys[i] >> shift) & (kRadix - 1)], 1);
+        const long long i = begin + r * kSortBlock + threadIdx.x;
+        if (i < end) atomicAdd(&s_h[(keys[i] >> shift) & (kRadix - 1)], 1);
     }
     __syncthreads();
-    hist[static_cast<long long>(threadIdx.x) * nb + blockIdx.x] = s_h[threadIdx.x];
 }
 
-// Stable scatter of one tile: the tile is taken in rounds of kSortBlock keys
-// in index order; inside a round, lanes holding the same digit are ranked by
-// lane index (ballots over the digit bits) and waves in wave order.
-__global__ __launch_bounds__(kSortBlock) void k_sort_scatter(const unsigned long long* __restrict__ kin,
-                                                             const int32_t* __restrict__ vin,
-                                                             unsigned long long* __restrict__ kout,
-                                                             int32_t* __restrict__ vout, long long count, int shift,
-                                                             int nb, const int32_t* __restrict__ offs) {
+// Stable scatter of one tile, keys [begin, end) (at most kSortTile), whose
+// digit d goes to s_base[d] onwards.  The tile is taken in rounds of
+// kSortBlock keys in index order; inside a round, lanes holding the same
+// digit are ranked by lane index (ballots over the digit bits) and waves in
+// wave order.  kVals: values move with their keys.
+template <bool kVals>
+__device__ __forceinline__ void scatter_tile(const unsigned long long* __restrict__ kin,
+                                             const int32_t* __restrict__ vin, unsigned long long* __restrict__ kout,
+                                             int32_t* __restrict__ vout, long long begin, long long end, int shift,
+                                             int* s_base, int (*s_wcnt)[kRadix]) {
     constexpr int kWaves = kSortBlock / 64;
-    __shared__ int s_base[kRadix];
-    __shared__ int s_wcnt[kWaves][kRadix];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    s_base[threadIdx.x] = offs[static_cast<long long>(threadIdx.x) * nb + blockIdx.x];
     const unsigned long long lt = (1ull << lane) - 1ull;
-    const long long base = static_cast<long long>(blockIdx.x) * kSortTile;
     for (int r = 0; r < kSortRounds; ++r) {
         for (int i = threadIdx.x; i < kWaves * kRadix; i += kSortBlock) (&s_wcnt[0][0])[i] = 0;
         __syncthreads();
-        const long long idx = base + r * kSortBlock + threadIdx.x;
-        const bool valid = idx < count;
+        const long long idx = begin + r * kSortBlock + threadIdx.x;
+        const bool valid = idx < end;
         const unsigned long long key = valid ? kin[idx] : 0ull;
-        const int32_t val = valid ? vin[idx] : 0;
+        int32_t val = 0;
+        if constexpr (kVals) val = valid ? vin[idx] : 0;
         const int d = static_cast<int>((key >> shift) & (kRadix - 1));
         const unsigned long long live = __ballot(valid);
         unsigned long long same = live;
@@ -154,7 +151,7 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(const unsigned long
             for (int w = 0; w < wave; ++w) pre += s_wcnt[w][d];
             const int pos = s_base[d] + pre + rank;
             kout[pos] = key;
-            vout[pos] = val;
+            if constexpr (kVals) vout[pos] = val;
         }
         __syncthreads();
         int add = 0;
@@ -162,6 +159,84 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(const unsigned long
         s_base[threadIdx.x] += add;
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_sort_hist(const unsigned long long* __restrict__ keys, long long count,
+                                                          int shift, int nb, int32_t* hist) {
+    __shared__ int s_h[kRadix];
+    const long long base = static_cast<long long>(blockIdx.x) * kSortTile;
+    hist_tile(keys, base, count, shift, s_h);
+    hist[static_cast<long long>(threadIdx.x) * nb + blockIdx.x] = s_h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_sort_scatter(const unsigned long long* __restrict__ kin,
+                                                             const int32_t* __restrict__ vin,
+                                                             unsigned long long* __restrict__ kout,
+                                                             int32_t* __restrict__ vout, long long count, int shift,
+                                                             int nb, const int32_t* __restrict__ offs) {
+    __shared__ int s_base[kRadix];
+    __shared__ int s_wcnt[kSortBlock / 64][kRadix];
+    s_base[threadIdx.x] = offs[static_cast<long long>(threadIdx.x) * nb + blockIdx.x];
+    const long long base = static_cast<long long>(blockIdx.x) * kSortTile;
+    scatter_tile<true>(kin, vin, kout, vout, base, count, shift, s_base, s_wcnt);
+}
+
+// Segmented sort: segment s holds keys [key_off[s], key_off[s+1]) and tiles
+// [tile_off[s], tile_off[s+1]), one tile per kSortTile keys.  Its histogram
+// block starts at kRadix * tile_off[s], digit-major (d * tiles + tile), so
+// one exclusive scan over all histograms places every segment's keys in its
+// own range.  Largest s in [0, nseg) with off[s] <= x (empty segments are
+// skipped: a later segment with the same offset wins).
+__device__ __forceinline__ int seg_of(const long long* __restrict__ off, int nseg, long long x) {
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+struct SegTile {
+    long long begin, end;      // keys of this tile: [begin, min(end, begin + kSortTile))
+    long long hist_base;       // kRadix * tile_off[s]
+    long long nb, t;           // tiles of the segment, this tile's index in it
+};
+
+__device__ __forceinline__ SegTile seg_tile(const long long* __restrict__ key_off,
+                                            const long long* __restrict__ tile_off, int nseg) {
+    const long long b = blockIdx.x;
+    const int s = seg_of(tile_off, nseg, b);
+    SegTile T;
+    const long long t0 = tile_off[s];
+    T.nb = tile_off[s + 1] - t0;
+    T.t = b - t0;
+    T.begin = key_off[s] + T.t * kSortTile;
+    T.end = key_off[s + 1];
+    T.hist_base = static_cast<long long>(kRadix) * t0;
+    return T;
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_seg_hist(const unsigned long long* __restrict__ keys,
+                                                         const long long* __restrict__ key_off,
+                                                         const long long* __restrict__ tile_off, int nseg, int shift,
+                                                         int32_t* hist) {
+    __shared__ int s_h[kRadix];
+    const SegTile T = seg_tile(key_off, tile_off, nseg);
+    hist_tile(keys, T.begin, T.end, shift, s_h);
+    hist[T.hist_base + static_cast<long long>(threadIdx.x) * T.nb + T.t] = s_h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kSortBlock) void k_seg_scatter(const unsigned long long* __restrict__ kin,
+                                                            unsigned long long* __restrict__ kout,
+                                                            const long long* __restrict__ key_off,
+                                                            const long long* __restrict__ tile_off, int nseg,
+                                                            int shift, const int32_t* __restrict__ offs) {
+    __shared__ int s_base[kRadix];
+    __shared__ int s_wcnt[kSortBlock / 64][kRadix];
+    const SegTile T = seg_tile(key_off, tile_off, nseg);
+    s_base[threadIdx.x] = offs[T.hist_base + static_cast<long long>(threadIdx.x) * T.nb + T.t];
+    scatter_tile<false>(kin, nullptr, kout, nullptr, T.begin, T.end, shift, s_base, s_wcnt);
 }
 
 __global__ void k_copy_pairs(const unsigned long long* kin, const int32_t* vin, unsigned long long* kout,
@@ -238,6 +313,42 @@ hln_status sort_pairs(unsigned long long* keys, int32_t* vals, long long count, 
         hipLaunchKernelGGL(k_copy_pairs, dim3(grid), dim3(256), 0, st, ka, va, keys, vals, count);
     }
     HLN_TRY_HIP(hipGetLastError());
+    return HLN_OK;
+}
+
+long long seg_sort_tiles(long long count) { return (count + kSortTile - 1) / kSortTile; }
+
+size_t seg_sort_workspace(long long tiles) {
+    const long long hist = tiles * kRadix;
+    return Arena::round(static_cast<size_t>(hist + 1) * 4) + scan_workspace(hist);
+}
+
+hln_status sort_keys_segmented(unsigned long long* keys, unsigned long long* alt, const long long* key_off,
+                               const long long* tile_off, int nseg, long long tiles, int key_bits, void* ws,
+                               size_t ws_bytes, hipStream_t st, unsigned long long** sorted) {
+    *sorted = keys;
+    if (tiles <= 0 || nseg <= 0) return HLN_OK;
+    if (ws_bytes < seg_sort_workspace(tiles)) return fail(HLN_ENOMEM, "sort workspace too small");
+    if (tiles * kRadix >= (1ll << 31) || tiles >= (1ll << 31)) return fail(HLN_EUNSUPPORTED, "sort too large");
+    Arena ar{static_cast<char*>(ws), ws_bytes};
+    int32_t* hist = ar.take<int32_t>(tiles * kRadix + 1);
+    void* sws = ar.base + ar.off;
+    const size_t sws_bytes = ws_bytes - ar.off;
+    unsigned long long* ka = keys;
+    unsigned long long* kb = alt;
+    const int passes = std::max(1, (key_bits + 7) / 8);
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(k_seg_hist, dim3(static_cast<unsigned>(tiles)), dim3(kSortBlock), 0, st, ka, key_off,
+                           tile_off, nseg, shift, hist);
+        hln_status s = scan_exclusive<int32_t>(hist, hist, tiles * kRadix, sws, sws_bytes, st);
+        if (s != HLN_OK) return s;
+        hipLaunchKernelGGL(k_seg_scatter, dim3(static_cast<unsigned>(tiles)), dim3(kSortBlock), 0, st, ka, kb,
+                           key_off, tile_off, nseg, shift, hist);
+        std::swap(ka, kb);
+    }
+    HLN_TRY_HIP(hipGetLastError());
+    *sorted = ka;
     return HLN_OK;
 }
 

@@ -24,13 +24,9 @@ from . import _lib as L
 
 def upload_homln(h, stream=None):
     """Device CSR layers of a HoMLN (edge lists through the ingest kernels)."""
-    graphs = []
-    for eu, ev in h.layers:
-        du = torch.from_numpy(np.ascontiguousarray(eu, dtype=np.int32)).cuda()
-        dv = torch.from_numpy(np.ascontiguousarray(ev, dtype=np.int32)).cuda()
-        g = L.hln_csr_from_edges(h.n, du, dv, stream=stream)
-        graphs.append(g.trimmed())
-    return graphs
+    items = [(h.n, torch.from_numpy(np.ascontiguousarray(eu, dtype=np.int32)).cuda(),
+              torch.from_numpy(np.ascontiguousarray(ev, dtype=np.int32)).cuda()) for eu, ev in h.layers]
+    return [g.trimmed() for g in L.hln_csr_from_edges_batch(items, stream=stream)]
 
 
 def psi(plan: L.Plan, graphs, stream=None):

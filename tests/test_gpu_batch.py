@@ -153,3 +153,33 @@ def test_batch_several_persistent_graphs_share_one_launch():
         stream.synchronize()
         P.device_status()
         check(gnp, outs, "multi-replay%d" % rep)
+
+
+def test_plan_set_width_pins_the_choice():
+    """Widths set by hand: every tile width and every persistent width
+    (512 runs one launch per graph, 1024-4096 the multi-graph launch) give
+    the oracle's outputs; a tile width wider than fits is narrowed; bad
+    widths are rejected and change nothing."""
+    sizes = [3000, 5000, 9000]             # classes 2^11, 2^12, 2^13
+    gnp = mixed_graphs(21, sizes)
+    graphs = [graph_dev(P, rp, ci) for rp, ci in gnp]
+    for ws in [(8, 16, 32), (64, 64, 64), (512, 1024, 4096), (2048, 2048, 16), (0, 0, 0)]:
+        plan = P.Plan()
+        for n, w in zip(sizes, ws):
+            plan.set_width(n, w)
+        got = [plan.width(n) for n in sizes]
+        say("set", ws, "->", got)
+        fit = [P.Plan().width(n) for n in sizes]
+        for w, g, f in zip(ws, got, fit):
+            assert g == (f if w == 0 else min(w, f) if w <= 64 else w)
+        outs = P.Plan.outputs(graphs, want_h2=True)
+        plan.run(graphs, outs)
+        torch.cuda.synchronize()
+        P.device_status()
+        check(gnp, outs, "set%s" % (ws,))
+    plan = P.Plan()
+    plan.set_width(3000, 1024)
+    for bad in [(3000, 128), (3000, 4), (3000, 8192), (0, 64), (-5, 64)]:
+        with pytest.raises(P.HlnError):
+            plan.set_width(*bad)
+    assert plan.width(3000) == 1024

@@ -68,6 +68,121 @@ def test_ingest_rejects_out_of_range_ids():
     P.device_status()                                  # the fault word was cleared
 
 
+def ingest_batch(items, capture=False):
+    """hln_csr_from_edges_batch over (n, eu, ev) numpy lists; eager, or
+    captured in a hipGraph and replayed twice (outputs poisoned before each
+    replay)."""
+    dev_items = [(n, to_dev(eu), to_dev(ev)) for n, eu, ev in items]
+    if not capture:
+        gs = P.hln_csr_from_edges_batch(dev_items)
+        torch.cuda.synchronize()
+        P.device_status()
+        return [(g.row_ptr.cpu().numpy(), g.trimmed().col_idx.cpu().numpy()) for g in gs]
+    outs = [(torch.empty(n + 1, dtype=torch.int32, device="cuda"),
+             torch.empty(max(2 * len(eu), 1), dtype=torch.int32, device="cuda")) for n, eu, _ in items]
+    ws = P.workspace(P.csr_from_edges_batch_workspace_size(dev_items))
+    P.hln_csr_from_edges_batch(dev_items, ws=ws, outs=outs)          # eager pass first
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        P.hln_csr_from_edges_batch(dev_items, ws=ws, outs=outs)
+    res = None
+    for rep in range(2):
+        for rp, ci in outs:
+            rp.fill_(-7)
+            ci.fill_(-7)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        P.device_status()
+        got = [(rp.cpu().numpy(), ci[:int(rp[-1].item())].cpu().numpy()) for rp, ci in outs]
+        if res is not None:
+            for (a, b), (c, d) in zip(res, got):
+                assert np.array_equal(a, c) and np.array_equal(b, d)
+        res = got
+    return res
+
+
+def messy_lists(seed, count, nmax):
+    rng = np.random.default_rng(seed)
+    items = []
+    for t in range(count):
+        n = int(rng.integers(1, nmax))
+        m = int(rng.integers(0, 4 * n + 1)) if t % 5 else 0
+        eu = rng.integers(0, n, size=m).astype(np.int32)
+        ev = rng.integers(0, n, size=m).astype(np.int32)
+        if m and t % 3 == 0:                           # repeated edges and both orientations
+            eu = np.concatenate([eu, ev[: m // 2]])
+            ev = np.concatenate([ev, eu[: m // 2]])
+        items.append((n, eu, ev))
+    return items
+
+
+def check_batch(items, got, tag):
+    for i, ((n, eu, ev), (rp, ci)) in enumerate(zip(items, got)):
+        rp_o, ci_o = O.csr_from_edges(n, eu, ev)
+        assert np.array_equal(rp, rp_o), (tag, i, n, len(eu))
+        assert np.array_equal(ci, ci_o), (tag, i, n, len(eu))
+
+
+def test_ingest_batch_messy_lists():
+    """Many lists of different sizes (empty lists, self-loops, duplicates,
+    both orientations, n = 1) in one call, against the oracle."""
+    items = messy_lists(5, 57, 3000) + [(1, np.zeros(0, np.int32), np.zeros(0, np.int32)),
+                                        (3, np.array([1, 1, 2], np.int32), np.array([1, 1, 2], np.int32))]
+    say("batch lists", len(items), "arcs", sum(2 * len(eu) for _, eu, _ in items))
+    check_batch(items, ingest_batch(items), "messy")
+
+
+def test_ingest_batch_mixed_key_widths_and_configs():
+    """Lists whose keys need 2 to 5 radix passes (n from 3 to 70,000) and
+    config 1's layers next to config 2's at 0.2 scale, several sort tiles
+    per list; equal to the single-list call bit for bit."""
+    rng = np.random.default_rng(9)
+    items = []
+    for n in [3, 250, 4000, 70000, 66000]:
+        m = int(n * rng.choice([1.0, 3.0]))
+        items.append((n, rng.integers(0, n, size=m).astype(np.int32), rng.integers(0, n, size=m).astype(np.int32)))
+    for cfg, scale in [(1, 1.0), (2, 0.2)]:
+        h = C.make_config(cfg, scale)
+        items += [(h.n, eu.astype(np.int32), ev.astype(np.int32)) for eu, ev in h.layers]
+    got = ingest_batch(items)
+    check_batch(items, got, "mixed")
+    for (n, eu, ev), (rp, ci) in zip(items, got):
+        rp1, ci1, _ = ingest(n, eu, ev)
+        assert np.array_equal(rp, rp1) and np.array_equal(ci, ci1)
+
+
+def test_ingest_batch_captured():
+    items = messy_lists(13, 30, 5000)
+    check_batch(items, ingest_batch(items, capture=True), "captured")
+
+
+def test_ingest_batch_edge_cases_and_errors():
+    assert P.hln_csr_from_edges_batch([]) == []
+    L = P.lib()
+    assert L.hln_csr_from_edges_batch(None, 0, None, 0, None) == 0
+    # only empty lists
+    items = [(5, np.zeros(0, np.int32), np.zeros(0, np.int32)), (1, np.zeros(0, np.int32), np.zeros(0, np.int32))]
+    check_batch(items, ingest_batch(items), "empty")
+    eu = to_dev(np.array([0, 1], np.int32))
+    for bad in [(0, eu, eu)]:
+        with pytest.raises(P.HlnError):
+            P.hln_csr_from_edges_batch([(4, eu, eu), bad])
+    small = torch.zeros(256, dtype=torch.uint8, device="cuda")
+    outs = [(torch.empty(5, dtype=torch.int32, device="cuda"), torch.empty(4, dtype=torch.int32, device="cuda"))]
+    arr = P._lib._edge_lists([(4, eu, eu)], outs)
+    assert L.hln_csr_from_edges_batch(arr, 1, P._lib._ptr(small), 256, None) == 2      # workspace too small
+    assert L.hln_csr_from_edges_batch(None, 1, None, 0, None) == 1
+    assert L.hln_csr_from_edges_batch(None, -1, None, 0, None) == 1
+    # an id out of range in one list is a device fault; the others are not touched by it
+    ev = to_dev(np.array([1, 9], np.int32))
+    P.hln_csr_from_edges_batch([(4, eu, eu), (4, eu, ev)])
+    with pytest.raises(P.HlnError):
+        P.device_status()
+    P.device_status()
+
+
 def test_validate_flags():
     n, eu, ev = G.named_graph("cycle", 9)
     rp, ci = csr_np(n, *G.to_edges(n, eu, ev))
