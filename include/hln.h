@@ -220,6 +220,28 @@ hln_status hln_compose_cc_topk(int32_t mode, int32_t n, int32_t r, const int64_t
                                int32_t k, int32_t* ids, double* score, int32_t* count,
                                void* workspace, size_t workspace_bytes, void* stream);
 
+/* hln_compose_cc_topk_batch: the k >= 0 form of hln_compose_cc_topk for
+ * `count` problems in one set of launches (e.g. the CC2 top-k of many
+ * HoMLNs); each problem's ids, score and count are exactly those of the
+ * one-problem call.  mode HLN_RANK_WF (r = 1) or HLN_RANK_CC2, 1 <= r <= 64,
+ * 0 <= k <= n, S / R as there.  The keys of all problems go through one
+ * segmented radix sort; the problem table is written by kernels from their
+ * launch arguments, so nothing is staged on the host and the call can be
+ * captured.  sum(n) must stay below 2^31 - 1 (HLN_EUNSUPPORTED: split the
+ * batch).  count = 0 does nothing.  The workspace size reads only mode, n,
+ * r and k (0 for invalid problems). */
+typedef struct {
+    int32_t mode, n, r, k;
+    const int64_t* const* S;   /* [host] r device pointers (n entries each) */
+    const int32_t* const* R;   /* [host] r device pointers */
+    int32_t* ids;              /* [dev] k, output */
+    double* score;             /* [dev] k, output, nullable */
+    int32_t* count;            /* [dev] 1, output (= k) */
+} hln_topk_problem;
+size_t hln_compose_cc_topk_batch_workspace_size(const hln_topk_problem* problems, int32_t count);
+hln_status hln_compose_cc_topk_batch(const hln_topk_problem* problems, int32_t count, void* workspace,
+                                     size_t workspace_bytes, void* stream);
+
 /* ------------------------------------------------------------------------
  * Heuristic CC1 (Sec. 5.1, Eq. 2-3): CC nodes of the AND aggregate of r
  * layers from per-layer degrees, penalised distance sums and neighbour

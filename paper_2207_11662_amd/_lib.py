@@ -25,7 +25,8 @@ EXPORTS = [
     "hln_csr_from_edges_batch", "hln_csr_validate",
     "hln_compose_workspace_size", "hln_compose_and", "hln_compose_or",
     "hln_closeness_workspace_size", "hln_closeness_layer", "hln_closeness_estimate",
-    "hln_compose_cc_topk_workspace_size", "hln_compose_cc_topk", "hln_compose_cc1_workspace_size", "hln_compose_cc1",
+    "hln_compose_cc_topk_workspace_size", "hln_compose_cc_topk",
+    "hln_compose_cc_topk_batch_workspace_size", "hln_compose_cc_topk_batch", "hln_compose_cc1_workspace_size", "hln_compose_cc1",
     "hln_plan_create", "hln_plan_destroy", "hln_plan_width", "hln_plan_set_width", "hln_closeness_batch_workspace_size",
     "hln_closeness_batch", "hln_plan_tune", "hln_plan_capture", "hln_plan_replay", "hln_plan_reserve",
     "hln_mlp_param_count", "hln_proposer_features", "hln_mlp_init", "hln_mlp_forward",
@@ -50,6 +51,12 @@ class hln_csr(ctypes.Structure):
 class hln_edge_list(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64), ("eu", ctypes.c_void_p), ("ev", ctypes.c_void_p),
                 ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p)]
+
+
+class hln_topk_problem(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("n", ctypes.c_int32), ("r", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("S", ctypes.c_void_p), ("R", ctypes.c_void_p), ("ids", ctypes.c_void_p), ("score", ctypes.c_void_p),
+                ("count", ctypes.c_void_p)]
 
 
 class hln_opts(ctypes.Structure):
@@ -90,6 +97,8 @@ def lib():
         "hln_closeness_estimate": ([i32, i32, P, i32, P, P, P, P], st),
         "hln_compose_cc_topk_workspace_size": ([i32], sz),
         "hln_compose_cc_topk": ([i32, i32, i32, P, P, i32, P, P, P, P, sz, P], st),
+        "hln_compose_cc_topk_batch_workspace_size": ([ctypes.POINTER(hln_topk_problem), i32], sz),
+        "hln_compose_cc_topk_batch": ([ctypes.POINTER(hln_topk_problem), i32, P, sz, P], st),
         "hln_compose_cc1_workspace_size": ([i32, i32], sz),
         "hln_compose_cc1": ([P, i32, P, P, i32, i32, P, P, P, P, sz, P], st),
         "hln_plan_create": ([ctypes.POINTER(ctypes.c_void_p)], st),
@@ -364,6 +373,49 @@ def hln_compose_cc_topk(mode: int, n: int, S_list, R_list, k: int, ws=None, out=
                                     k, _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _ptr(ws), ws.numel(),
                                     _stream(stream)))
     return out
+
+
+class TopkBatch:
+    """The k >= 0 top-k of many problems in one call
+    (hln_compose_cc_topk_batch).  problems: (mode, n, S_list, R_list, k)
+    each; outs: optional (ids, score, count) per problem.  The host-side
+    problem table is built once and kept (so the call can be repeated or
+    captured); run() enqueues the batch and returns the outs."""
+
+    def __init__(self, problems, outs=None, ws=None):
+        self.problems = list(problems)
+        dev = self.problems[0][2][0].device if self.problems else torch.device("cuda")
+        if outs is None:
+            outs = [(torch.empty(max(k, 1), dtype=torch.int32, device=dev),
+                     torch.empty(max(k, 1), dtype=torch.float64, device=dev),
+                     torch.empty(1, dtype=torch.int32, device=dev)) for _, _, _, _, k in self.problems]
+        self.outs = outs
+        self._keep = []
+        self.arr = (hln_topk_problem * max(len(self.problems), 1))()
+        for i, ((mode, n, S_list, R_list, k), (ids, sc, cnt)) in enumerate(zip(self.problems, outs)):
+            Sp = (ctypes.c_void_p * len(S_list))(*[t.data_ptr() for t in S_list])
+            Rp = (ctypes.c_void_p * len(R_list))(*[t.data_ptr() for t in R_list])
+            self._keep += [Sp, Rp]
+            self.arr[i] = hln_topk_problem(mode, n, len(S_list), k, ctypes.cast(Sp, ctypes.c_void_p),
+                                           ctypes.cast(Rp, ctypes.c_void_p), _ptr(ids),
+                                           None if sc is None else _ptr(sc), _ptr(cnt))
+        self.need = int(lib().hln_compose_cc_topk_batch_workspace_size(self.arr, len(self.problems)))
+        if ws is None or ws.numel() < self.need:
+            ws = workspace(self.need, dev) if self.need else None
+        self.ws = ws
+
+    def run(self, stream=None):
+        wsp, wsn = (None, 0) if self.ws is None else (_ptr(self.ws), self.ws.numel())
+        check(lib().hln_compose_cc_topk_batch(self.arr, len(self.problems), wsp, wsn, _stream(stream)))
+        return self.outs
+
+
+def hln_compose_cc_topk_batch(problems, ws=None, outs=None, stream=None):
+    """Top-k of many problems, (mode, n, S_list, R_list, k) each; returns one
+    (ids, score, count) per problem."""
+    if not problems:
+        return []
+    return TopkBatch(problems, outs=outs, ws=ws).run(stream)
 
 
 def hln_compose_cc1(layers, S_list, R_list, tau=(1, 2), ws=None, out=None, stream=None):

@@ -501,11 +501,11 @@ hln_status hln_csr_from_edges_batch(const hln_edge_list* lists, int32_t count, v
     if (B.edges > 0) {
         hipLaunchKernelGGL(k_bi_keys, dim3(grid_for(B.edges)), dim3(256), 0, st, tab, k_off, count, B.edges, keys,
                            fault);
-        unsigned long long* out = nullptr;
-        s = hln::prim::sort_keys_segmented(keys, alt, k_off, t_off, count, B.tiles, B.key_bits, sws, sws_bytes, st,
-                                           &out);
+        bool in_alt = false;
+        s = hln::prim::sort_segmented(keys, alt, nullptr, nullptr, k_off, t_off, count, B.tiles, B.key_bits, sws,
+                                      sws_bytes, st, &in_alt);
         if (s != HLN_OK) return s;
-        sorted = out;
+        sorted = in_alt ? alt : keys;
         hipLaunchKernelGGL(k_bi_mark, dim3(grid_for(B.keys)), dim3(256), 0, st, tab, k_off, count, sorted, B.keys,
                            flag);
         s = hln::prim::scan_exclusive<int32_t>(flag, pos, B.keys, sws, sws_bytes, st);

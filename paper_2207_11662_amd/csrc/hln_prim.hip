@@ -227,8 +227,11 @@ __global__ __launch_bounds__(kSortBlock) void k_seg_hist(const unsigned long lon
     hist[T.hist_base + static_cast<long long>(threadIdx.x) * T.nb + T.t] = s_h[threadIdx.x];
 }
 
+template <bool kVals>
 __global__ __launch_bounds__(kSortBlock) void k_seg_scatter(const unsigned long long* __restrict__ kin,
+                                                            const int32_t* __restrict__ vin,
                                                             unsigned long long* __restrict__ kout,
+                                                            int32_t* __restrict__ vout,
                                                             const long long* __restrict__ key_off,
                                                             const long long* __restrict__ tile_off, int nseg,
                                                             int shift, const int32_t* __restrict__ offs) {
@@ -236,7 +239,7 @@ __global__ __launch_bounds__(kSortBlock) void k_seg_scatter(const unsigned long 
     __shared__ int s_wcnt[kSortBlock / 64][kRadix];
     const SegTile T = seg_tile(key_off, tile_off, nseg);
     s_base[threadIdx.x] = offs[T.hist_base + static_cast<long long>(threadIdx.x) * T.nb + T.t];
-    scatter_tile<false>(kin, nullptr, kout, nullptr, T.begin, T.end, shift, s_base, s_wcnt);
+    scatter_tile<kVals>(kin, vin, kout, vout, T.begin, T.end, shift, s_base, s_wcnt);
 }
 
 __global__ void k_copy_pairs(const unsigned long long* kin, const int32_t* vin, unsigned long long* kout,
@@ -323,10 +326,10 @@ size_t seg_sort_workspace(long long tiles) {
     return Arena::round(static_cast<size_t>(hist + 1) * 4) + scan_workspace(hist);
 }
 
-hln_status sort_keys_segmented(unsigned long long* keys, unsigned long long* alt, const long long* key_off,
-                               const long long* tile_off, int nseg, long long tiles, int key_bits, void* ws,
-                               size_t ws_bytes, hipStream_t st, unsigned long long** sorted) {
-    *sorted = keys;
+hln_status sort_segmented(unsigned long long* keys, unsigned long long* alt, int32_t* vals, int32_t* valt,
+                          const long long* key_off, const long long* tile_off, int nseg, long long tiles, int key_bits,
+                          void* ws, size_t ws_bytes, hipStream_t st, bool* in_alt) {
+    *in_alt = false;
     if (tiles <= 0 || nseg <= 0) return HLN_OK;
     if (ws_bytes < seg_sort_workspace(tiles)) return fail(HLN_ENOMEM, "sort workspace too small");
     if (tiles * kRadix >= (1ll << 31) || tiles >= (1ll << 31)) return fail(HLN_EUNSUPPORTED, "sort too large");
@@ -336,6 +339,8 @@ hln_status sort_keys_segmented(unsigned long long* keys, unsigned long long* alt
     const size_t sws_bytes = ws_bytes - ar.off;
     unsigned long long* ka = keys;
     unsigned long long* kb = alt;
+    int32_t* va = vals;
+    int32_t* vb = valt;
     const int passes = std::max(1, (key_bits + 7) / 8);
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
@@ -343,12 +348,17 @@ hln_status sort_keys_segmented(unsigned long long* keys, unsigned long long* alt
                            tile_off, nseg, shift, hist);
         hln_status s = scan_exclusive<int32_t>(hist, hist, tiles * kRadix, sws, sws_bytes, st);
         if (s != HLN_OK) return s;
-        hipLaunchKernelGGL(k_seg_scatter, dim3(static_cast<unsigned>(tiles)), dim3(kSortBlock), 0, st, ka, kb,
-                           key_off, tile_off, nseg, shift, hist);
+        if (vals)
+            hipLaunchKernelGGL(k_seg_scatter<true>, dim3(static_cast<unsigned>(tiles)), dim3(kSortBlock), 0, st, ka, va,
+                               kb, vb, key_off, tile_off, nseg, shift, hist);
+        else
+            hipLaunchKernelGGL(k_seg_scatter<false>, dim3(static_cast<unsigned>(tiles)), dim3(kSortBlock), 0, st, ka,
+                               nullptr, kb, nullptr, key_off, tile_off, nseg, shift, hist);
         std::swap(ka, kb);
+        std::swap(va, vb);
+        *in_alt = !*in_alt;
     }
     HLN_TRY_HIP(hipGetLastError());
-    *sorted = ka;
     return HLN_OK;
 }
 

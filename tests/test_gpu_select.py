@@ -97,3 +97,89 @@ def test_end_to_end_config1():
     torch.cuda.synchronize()
     est = O.cc2_est(n, [S for S, _ in refs[:3]], [R for _, R in refs[:3]])
     assert np.array_equal(ids[: int(count.item())].cpu().numpy(), O.topk_asc_i64(est, k))
+
+
+def batch_problems(seed, count, nmax):
+    """Mixed WF and CC2 problems (with and without ties, k from 0 to n)."""
+    rng = np.random.default_rng(seed)
+    probs = []
+    for p in range(count):
+        n = int(rng.integers(1, nmax))
+        ties = bool(p % 2)
+        if p % 3 == 0:
+            S, R = synthetic_sums(rng, n, ties)
+            cc = O.closeness_wf(n, S, R)
+            k = int(rng.choice([0, 1, max(n // 10, 0), n]))
+            probs.append((P.HLN_RANK_WF, n, [S], [R], k, O.topk_desc(cc, k), cc))
+        else:
+            r = int(rng.integers(1, 5))
+            sums = [synthetic_sums(rng, n, ties) for _ in range(r)]
+            est = O.cc2_est(n, [s for s, _ in sums], [x for _, x in sums])
+            k = int(rng.choice([0, 1, max(n // 10, 0), n]))
+            probs.append((P.HLN_RANK_CC2, n, [s for s, _ in sums], [x for _, x in sums], k, O.topk_asc_i64(est, k),
+                          O.cc2_score(n, est)))
+    return probs
+
+
+def check_topk_batch(probs, outs, tag):
+    for i, ((mode, n, S_list, R_list, k, ref, score), (ids, sc, cnt)) in enumerate(zip(probs, outs)):
+        c = int(cnt.item())
+        assert c == k, (tag, i)
+        assert np.array_equal(ids[:c].cpu().numpy(), ref), (tag, i, mode, n, k)
+        assert np.array_equal(sc[:c].cpu().numpy().view(np.int64), score[ref].view(np.int64)), (tag, i)
+
+
+def test_topk_batch_against_oracle_and_single_calls():
+    """Forty problems of mixed modes and sizes (n from 1 to 6,000, k from 0
+    to n, ties) in one call: every problem against the oracle, and against
+    the one-problem call bit for bit."""
+    probs = batch_problems(21, 40, 6000)
+    dev_probs = [(mode, n, [to_dev(s, torch.int64) for s in S], [to_dev(x, torch.int32) for x in R], k)
+                 for mode, n, S, R, k, _, _ in probs]
+    outs = P.hln_compose_cc_topk_batch(dev_probs)
+    torch.cuda.synchronize()
+    P.device_status()
+    check_topk_batch(probs, outs, "batch")
+    for (mode, n, S, R, k), (ids, sc, cnt) in zip(dev_probs, outs):
+        i1, s1, c1 = P.hln_compose_cc_topk(mode, n, S, R, k)
+        torch.cuda.synchronize()
+        assert int(c1.item()) == int(cnt.item())
+        assert torch.equal(i1[:k].cpu(), ids[:k].cpu()) and torch.equal(s1[:k].cpu(), sc[:k].cpu())
+
+
+def test_topk_batch_captured_and_repeated():
+    probs = batch_problems(23, 30, 3000)
+    dev_probs = [(mode, n, [to_dev(s, torch.int64) for s in S], [to_dev(x, torch.int32) for x in R], k)
+                 for mode, n, S, R, k, _, _ in probs]
+    tb = P.TopkBatch(dev_probs)
+    tb.run()
+    torch.cuda.synchronize()
+    check_topk_batch(probs, tb.outs, "eager")
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        tb.run()
+    for rep in range(2):
+        for ids, sc, cnt in tb.outs:
+            ids.fill_(-3)
+            sc.fill_(-3.0)
+            cnt.fill_(-3)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        P.device_status()
+        check_topk_batch(probs, tb.outs, "replay%d" % rep)
+
+
+def test_topk_batch_errors():
+    L = P.lib()
+    assert L.hln_compose_cc_topk_batch(None, 0, None, 0, None) == 0
+    assert L.hln_compose_cc_topk_batch(None, 1, None, 0, None) == 1
+    S = [torch.zeros(10, dtype=torch.int64, device="cuda")] * 2
+    R = [torch.ones(10, dtype=torch.int32, device="cuda")] * 2
+    for bad in [(P.HLN_RANK_NAIVE, 10, S, R, 2), (P.HLN_RANK_WF, 10, S, R, 2), (P.HLN_RANK_CC2, 10, S, R, 11),
+                (P.HLN_RANK_CC2, 10, S, R, -1), (P.HLN_RANK_CC2, 0, S, R, 0)]:
+        with pytest.raises(P.HlnError):
+            P.hln_compose_cc_topk_batch([(P.HLN_RANK_CC2, 10, S, R, 3), bad])
+    tb = P.TopkBatch([(P.HLN_RANK_CC2, 10, S, R, 3)])
+    small = torch.zeros(256, dtype=torch.uint8, device="cuda")
+    assert L.hln_compose_cc_topk_batch(tb.arr, 1, P._lib._ptr(small), 256, None) == 2
