@@ -889,14 +889,97 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
             } else {
                 // ---- bottom-up over all segments
                 const __amdgpu_buffer_rsrc_t fr_rsrc = words_rsrc(fr, static_cast<uint32_t>(n) * (NW * 8u));
-                long long s = gid;
-                SegPre<NW> cur, nxt;
                 auto rec_at = [&](long long i) {
                     return buf_i4(B.seg, i < n_seg ? static_cast<uint32_t>(i) * 16u : kNoWord);
                 };
                 auto sat_at = [&](long long i) {
                     return buf_u32(B.segsat, i < n_seg ? static_cast<uint32_t>(i) * 4u : kNoWord) != 0u;
                 };
+                // the end of a segment: merge a multi-segment row's partial OR
+                // (the last finisher finalises) or finalise a single-segment row
+                auto finish = [&](long long s, int4 sg, uint64_t acc, uint64_t vis_v, Mask flag_old) {
+                    const int v = sg.x;
+                    const int nseg = sg.w;
+                    const size_t base = static_cast<size_t>(v) * NW + k;
+#pragma unroll
+                    for (int off = NW; off < kLpv; off <<= 1) acc |= shfl_xor_u64(acc, off);
+                    if (nseg == 1) {
+                        const int3 cw = finalize_vertex<NW, PER_SOURCE>(a, B, v, d, k, sub, gl, gbase, acc, vis_v,
+                                                                        s_cnt, flag_old, gcm_k);
+                        if (cw.x) {
+                            any = 1;
+                            t_pairs += cw.x;
+                            t_verts += 1;
+                            if (gl == 0) frontier_note(s_fr, par, static_cast<int>(s), 1, (sg.z - sg.y) * cw.y);
+                            if (cw.z) mark_saturated<kLpv>(a, static_cast<int>(s), 1, gl);
+                        }
+                    } else {
+                        // multi-segment row: merge, the last finisher finalises
+                        if (sub == 0 && acc)
+                            __hip_atomic_fetch_or(reinterpret_cast<unsigned long long*>(&a.hacc[base]),
+                                                  static_cast<unsigned long long>(acc), __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+                        // the wave's OR atomics are performed before the count is
+                        // raised (agent-scope atomics complete at the coherence
+                        // point; vmcnt(0) waits for their acknowledgement)
+                        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                        __builtin_amdgcn_s_waitcnt(0);
+                        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                        int old = 0;
+                        if (gl == 0)
+                            old = __hip_atomic_fetch_add(&a.hcnt[v], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        old = __shfl(old, gbase, 64);
+                        if (old == nseg - 1) {
+                            uint64_t full = 0;
+                            if (sub == 0)
+                                full = __hip_atomic_exchange(reinterpret_cast<unsigned long long*>(&a.hacc[base]), 0ull,
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                            for (int off = NW; off < kLpv; off <<= 1) full |= shfl_xor_u64(full, off);
+                            const Mask flag_old = flag_nx[v];
+                            if (gl == 0) store_agent_i32(&a.hcnt[v], 0);
+                            const int3 cw = finalize_vertex<NW, PER_SOURCE>(a, B, v, d, k, sub, gl, gbase, full, vis_v,
+                                                                            s_cnt, flag_old, gcm_k);
+                            if (cw.x) {
+                                any = 1;
+                                t_pairs += cw.x;
+                                t_verts += 1;
+                                const int first = a.seg_first[v];
+                                if (gl == 0) frontier_note(s_fr, par, first, nseg, nseg * seg_len * cw.y);
+                                if (cw.z) mark_saturated<kLpv>(a, first, nseg, gl);
+                            }
+                        }
+                    }
+                };
+                // Level 1 of an all-source batch at W = 4096: the frontier is the
+                // batch's sources src0 .. src0 + cnt - 1 with one bit each, so a
+                // neighbour's frontier word follows from its id: the level reads
+                // column ids only (no neighbour masks, no frontier words).
+                bool level1_ids = false;
+                if constexpr (NW == 64) level1_ids = d == 1 && !a.listed;
+                if (level1_ids) {
+                    for (long long s1 = gid; s1 < n_seg; s1 += ngroups) {
+                        const int4 sg = rec_at(s1);
+                        const int len = sg.z - sg.y;
+                        const int cidl = gl < len ? static_cast<int>(buf_u32(B.col, static_cast<uint32_t>(sg.y + gl) * 4u)) : -1;
+                        const Mask flag_old = buf_mask<Mask>(B.flag_nx, sg.w == 1 ? static_cast<uint32_t>(sg.x) * static_cast<uint32_t>(sizeof(Mask))
+                                                                                  : kNoWord);
+                        const int rel_l = cidl - src0;
+                        unsigned long long hits = __ballot(cidl >= 0 && rel_l >= 0 && rel_l < cnt);
+                        uint64_t acc = 0;
+                        while (hits) {
+                            const int t = __ffsll(static_cast<long long>(hits)) - 1;
+                            hits &= hits - 1;
+                            const int rel = __builtin_amdgcn_readlane(rel_l, t);
+                            if ((rel >> 6) == k) acc |= 1ull << (rel & 63);
+                        }
+                        uint64_t vis_v = 0;
+                        if (__ballot(acc != 0) != 0 || sg.w > 1) vis_v = a.vis[static_cast<size_t>(sg.x) * NW + k];
+                        finish(s1, sg, acc, vis_v, flag_old);
+                    }
+                }
+                long long s = level1_ids ? n_seg : gid;
+                SegPre<NW> cur, nxt;
                 seg_prefetch<NW, PER_SOURCE>(B, rec_at(s), s < n_seg, sat_at(s), gl, cur);
                 seg_prefetch<NW, PER_SOURCE>(B, rec_at(s + ngroups), s + ngroups < n_seg, sat_at(s + ngroups), gl, nxt);
                 seg_flags<NW>(B, cur);
@@ -940,55 +1023,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                                                         cur.sg.z - c, vis_v | acc);
                         }
                     }
-#pragma unroll
-                    for (int off = NW; off < kLpv; off <<= 1) acc |= shfl_xor_u64(acc, off);
-                    if (nseg == 1) {
-                        const int3 cw = finalize_vertex<NW, PER_SOURCE>(a, B, v, d, k, sub, gl, gbase, acc, vis_v,
-                                                                        s_cnt, cur.flag_old, gcm_k);
-                        if (cw.x) {
-                            any = 1;
-                            t_pairs += cw.x;
-                            t_verts += 1;
-                            if (gl == 0) frontier_note(s_fr, par, static_cast<int>(s), 1, (cur.sg.z - cur.sg.y) * cw.y);
-                            if (cw.z) mark_saturated<kLpv>(a, static_cast<int>(s), 1, gl);
-                        }
-                    } else {
-                        // multi-segment row: merge, the last finisher finalises
-                        if (sub == 0 && acc)
-                            __hip_atomic_fetch_or(reinterpret_cast<unsigned long long*>(&a.hacc[base]),
-                                                  static_cast<unsigned long long>(acc), __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-                        // the wave's OR atomics are performed before the count is
-                        // raised (agent-scope atomics complete at the coherence
-                        // point; vmcnt(0) waits for their acknowledgement)
-                        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                        __builtin_amdgcn_s_waitcnt(0);
-                        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                        int old = 0;
-                        if (gl == 0)
-                            old = __hip_atomic_fetch_add(&a.hcnt[v], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        old = __shfl(old, gbase, 64);
-                        if (old == nseg - 1) {
-                            uint64_t full = 0;
-                            if (sub == 0)
-                                full = __hip_atomic_exchange(reinterpret_cast<unsigned long long*>(&a.hacc[base]), 0ull,
-                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-#pragma unroll
-                            for (int off = NW; off < kLpv; off <<= 1) full |= shfl_xor_u64(full, off);
-                            const Mask flag_old = flag_nx[v];
-                            if (gl == 0) store_agent_i32(&a.hcnt[v], 0);
-                            const int3 cw = finalize_vertex<NW, PER_SOURCE>(a, B, v, d, k, sub, gl, gbase, full, vis_v,
-                                                                            s_cnt, flag_old, gcm_k);
-                            if (cw.x) {
-                                any = 1;
-                                t_pairs += cw.x;
-                                t_verts += 1;
-                                const int first = a.seg_first[v];
-                                if (gl == 0) frontier_note(s_fr, par, first, nseg, nseg * seg_len * cw.y);
-                                if (cw.z) mark_saturated<kLpv>(a, first, nseg, gl);
-                            }
-                        }
-                    }
+                    finish(s, cur.sg, acc, vis_v, cur.flag_old);
                     s = s1;
                     cur = nxt;
                     nxt = nn;
