@@ -13,7 +13,7 @@ HBM, then
 Throughput is GTEPS: for every graph and every source s, the undirected
 edges of s's component (Graph500 convention), divided by the step time.
 
-Prints one JSON line.  --gpus > 1 is refused (this build runs on one GPU).
+Prints one JSON line.  --gpus > 1 is refused (the library runs on one GPU).
 """
 from __future__ import annotations
 
@@ -137,7 +137,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not supported (the multi-GPU "
+        print("bench.py: the library runs on one GPU; --gpus %d is not supported (the multi-GPU "
               "sharding is a design note, not a built path)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

@@ -3,7 +3,7 @@
 // already computed (the Psi step: degree, distance sums and reach, 2-hop
 // count).  Its
 // top candidates are then scored by exact BFS on the AND graph; the
-// exhaustive computation stays the fallback and the judge of precision.
+// exhaustive computation stays the fallback and the precision reference.
 // (Not in the paper: the features echo CC1's degree bound, Sec. 5.1, and
 // CC2's per-layer distance sums, Sec. 5.2.)
 //

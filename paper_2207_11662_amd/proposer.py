@@ -9,7 +9,7 @@ returns the best of them by exact closeness.  Every step is a kernel of
 ``libhln.so``; this module only sequences the calls.  The method itself is
 not in the paper: it is an accelerator whose answers are exact closeness
 values of real vertices, with the exhaustive computation as the fallback
-and the judge of its precision.
+and the reference its precision is measured against.
 
 Training data: for each HoMLN, features from its layers and labels from
 the exact closeness of its AND graph (log-rank, 1 = most central).
