@@ -1088,15 +1088,24 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                 pR[i] = s_R[i];
             }
             if (!gb.wait()) return false;
-            for (long long i = tid; i < cnt; i += nthreads) {
-                int64_t sS = 0, sR = 0;
-                for (unsigned bb = 0; bb < nblk; ++bb) {
+            // one wave per source: its lanes take every 64th block's partial
+            // (all in flight at once), then a wave sum (exact: integers)
+            for (long long i = tid >> 6; i < cnt; i += nthreads >> 6) {
+                uint64_t sS = 0, sR = 0;
+                for (unsigned bb = static_cast<unsigned>(lane); bb < nblk; bb += 64) {
                     const int64_t* q = a.part + static_cast<size_t>(bb) * 2 * W;
-                    sS += q[i];
-                    sR += q[W + i];
+                    sS += static_cast<uint64_t>(q[i]);
+                    sR += static_cast<uint64_t>(q[W + i]);
                 }
-                a.S[src0 + i] = sS;
-                a.R[src0 + i] = static_cast<int32_t>(1 + sR);
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    sS += shfl_xor_u64(sS, off);
+                    sR += shfl_xor_u64(sR, off);
+                }
+                if (lane == 0) {
+                    a.S[src0 + i] = static_cast<int64_t>(sS);
+                    a.R[src0 + i] = static_cast<int32_t>(1 + static_cast<int64_t>(sR));
+                }
             }
             // the partials are rewritten only after the next batch's barriers
         }
