@@ -789,12 +789,20 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                     atomicOr(reinterpret_cast<unsigned long long*>(&a.vis[w]), 1ull << (i & 63));
                     atomicOr(reinterpret_cast<unsigned long long*>(&a.bufA[w]), 1ull << (i & 63));
                     if (!PER_SOURCE) atomicAdd(&a.R[s], 1);      // per-vertex sums: the source reaches itself
-                    // the first source bit on a vertex lists it (once, even if
-                    // the vertex is listed as a source more than once)
-                    if (atomicOr(&static_cast<Mask*>(a.flagA)[s], static_cast<Mask>(static_cast<Mask>(1) << (i >> 6))) == 0) {
-                        const int3 sg = vertex_segments(a, s);
-                        if (sg.y > 0) frontier_note(s_fr, par, sg.x, sg.y, sg.z);
-                    }
+                    atomicOr(&static_cast<Mask*>(a.flagA)[s], static_cast<Mask>(static_cast<Mask>(1) << (i >> 6)));
+                }
+                // The sources' segments form the first frontier lists, spread
+                // over the blocks: segment j of a source goes to the list of
+                // block (first + j) mod nblk, so a hub among the sources is
+                // pushed by many blocks instead of by one.  A vertex listed
+                // twice is noted twice (its words are ORed in twice: no change).
+                for (int i = threadIdx.x; i < cnt; i += BLOCK) {
+                    const int3 sg = vertex_segments(a, a.sources[src0 + i]);
+                    long long j = (static_cast<long long>(blk) - sg.x) % static_cast<long long>(nblk);
+                    if (j < 0) j += nblk;
+                    for (; j < sg.y; j += nblk)
+                        frontier_note(s_fr, par, sg.x + static_cast<int>(j), 1,
+                                      min(seg_len, sg.z - static_cast<int>(j) * seg_len));
                 }
             }
             const hln::dev::BarrierResult br =
