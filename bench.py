@@ -203,6 +203,12 @@ def main():
     cws = P.workspace(P.compose_workspace_size(layer_graphs), dev)
     stream = torch.cuda.current_stream()
 
+    # the five graphs' top-10% and CC2's top-10% in one batched selection call
+    Sl = [outs[i]["S"] for i in range(L)]
+    Rl = [outs[i]["R"] for i in range(L)]
+    topk = P.TopkBatch([(P.HLN_RANK_WF, n, [outs[gi]["S"]], [outs[gi]["R"]], K) for gi in range(G)] +
+                       [(P.HLN_RANK_CC2, n, Sl, Rl, K)], outs=sel[:G + 1])
+
     def step(events=None):
         gs = P.hln_csr_from_edges_batch(ing_items, ws=iws, outs=csr_bufs)
         gA = P.hln_compose_and(gs, ws=cws, out=and_buf)
@@ -214,11 +220,7 @@ def main():
                                   direction=args.direction)
             if events is not None:
                 events[gi][1].record(stream)
-        for gi in range(G):
-            P.hln_compose_cc_topk(P.HLN_RANK_WF, n, [outs[gi]["S"]], [outs[gi]["R"]], K, ws=ws, out=sel[gi])
-        Sl = [outs[i]["S"] for i in range(L)]
-        Rl = [outs[i]["R"] for i in range(L)]
-        P.hln_compose_cc_topk(P.HLN_RANK_CC2, n, Sl, Rl, K, ws=ws, out=sel[G])
+        topk.run()
         P.hln_compose_cc_topk(P.HLN_RANK_NAIVE, n, Sl, Rl, -1, ws=ws, out=sel[G + 1])
 
     for _ in range(args.warmup):
