@@ -110,6 +110,44 @@ def summarise(records) -> dict:
     return out
 
 
+def batched_and_truth(layers, subsets, k: int, width_bits: int = 4096) -> dict:
+    """The AND ground truths of all subsets at once: every subset's AND
+    graph, then the closeness of all of them through one plan call (graphs
+    above the LDS-tile limit share one partitioned persistent launch) and
+    their top-k sets through one batched selection call; timed as a whole
+    with HIP events.  Returns the time and each subset's top-k ids."""
+    dev = layers[0].row_ptr.device
+    n = layers[0].n
+    bufs, wss = [], []
+    for sub in subsets:
+        gs = [layers[i] for i in sub]
+        bufs.append((torch.empty(n + 1, dtype=torch.int32, device=dev),
+                     torch.empty(min(g.nnz for g in gs), dtype=torch.int32, device=dev)))
+        wss.append(L.workspace(L.compose_workspace_size(gs), dev))
+    graphs = [L.Graph(rp, ci, ci.numel()) for rp, ci in bufs]
+    plan = L.Plan()
+    plan.set_width(n, width_bits)
+    outs = L.Plan.outputs(graphs)
+    bws = L.workspace(plan.workspace_size(graphs), dev)
+    sel = L.TopkBatch([(L.HLN_RANK_WF, n, [o["S"]], [o["R"]], k) for o in outs])
+
+    def run():
+        for sub, buf, w in zip(subsets, bufs, wss):
+            L.hln_compose_and([layers[i] for i in sub], ws=w, out=buf)
+        plan.run(graphs, outs, ws=bws)
+        sel.run()
+
+    run()                                   # warm-up
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    run()
+    b.record()
+    torch.cuda.synchronize()
+    L.device_status()
+    return {"t_ms": a.elapsed_time(b), "topk": [ids[:k].cpu().numpy() for ids, _, _ in sel.outs]}
+
+
 def subsets_sweep(h, k_frac: float = 0.01, width_bits: int = 4096, with_or: bool = True) -> dict:
     """f2: Psi once, then every subset of >= 2 layers.  Times (HIP events on
     the current stream): Psi (all-source closeness of every layer), per
@@ -183,11 +221,17 @@ def subsets_sweep(h, k_frac: float = 0.01, width_bits: int = 4096, with_or: bool
                 rec["t_or_gt_ms"] = e[3].elapsed_time(e[4])
                 rec["or_vs_and_topk"] = set_metrics(_ids(o_dev[1]), t_sets[1])
                 del or_buf, ws_cmp
+            rec["_gt_topk"] = t_sets[1]
             recs.append(rec)
+    batched = batched_and_truth(layers, [x["subset"] for x in recs], k, width_bits)
+    for x, ids in zip(recs, batched.pop("topk")):
+        assert np.array_equal(ids, x.pop("_gt_topk")), "batched AND ground truth differs"
     t_gt = sum(x["t_and_gt_ms"] for x in recs)
     t_theta = sum(x["t_theta_ms"] for x in recs)
     return {"layers": nl, "subsets": len(recs), "k": k, "t_psi_ms": t_psi, "t_and_gt_total_ms": t_gt,
             "t_theta_total_ms": t_theta, "speedup_decoupled": t_gt / (t_psi + t_theta),
+            "t_and_gt_batched_ms": batched["t_ms"],
+            "speedup_decoupled_vs_batched_gt": batched["t_ms"] / (t_psi + t_theta),
             "t_theta_cc1_total_ms": sum(x["t_theta_cc1_ms"] for x in recs),
             "cc1_above_mean": {m: float(np.mean([x["cc1_above"][m] for x in recs])) for m in ("jaccard", "precision", "f1")},
             "t_or_gt_total_ms": sum(x.get("t_or_gt_ms", 0.0) for x in recs) if with_or else None,

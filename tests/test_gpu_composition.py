@@ -60,11 +60,16 @@ def test_study_sets_match_oracle_config1():
             % (rec["cc2_topk"]["jaccard"], rec["naive_above"]["jaccard"]))
 
 
-def test_subsets_sweep_small():
+@pytest.mark.parametrize("width", [512, 4096])
+def test_subsets_sweep_small(width):
+    """Also checks, inside the sweep, that the batched AND ground truths (all
+    subsets through one plan call: one launch per graph at 512, the
+    partitioned multi-graph launch at 4096) give every subset's top-k set."""
     h = C.config2(scale=0.02)
-    res = CM.subsets_sweep(h, k_frac=0.05, width_bits=512)
+    res = CM.subsets_sweep(h, k_frac=0.05, width_bits=width)
     assert res["subsets"] == 2 ** 4 - 4 - 1
     assert all(r["t_and_gt_ms"] > 0 and r["t_theta_ms"] > 0 for r in res["records"])
+    assert res["t_and_gt_batched_ms"] > 0
     # the sweep's CC2 scores agree with the oracle on one subset
     n = h.n
     layers_np = [csr_np(n, *e) for e in h.layers]
