@@ -101,3 +101,64 @@ def test_select_argument_checks():
     assert args(0, 1, -2) == HLN_EINVAL
     assert args(2, 2, 5) == HLN_EINVAL                    # naive needs k = -1
     assert args(1, 2, 5, ws - 1) == HLN_ENOMEM
+
+
+def test_batched_ingest_argument_checks():
+    L = P.lib()
+    EL = P._lib.hln_edge_list
+    ok = EL(5, 3, FAKE, FAKE, FAKE, FAKE)
+    arr = (EL * 2)(ok, EL(7, 0, None, None, FAKE, None))
+    need = L.hln_csr_from_edges_batch_workspace_size(arr, 2)
+    assert need > 0
+    assert L.hln_csr_from_edges_batch(arr, 2, FAKE, need - 1, None) == HLN_ENOMEM
+    assert L.hln_csr_from_edges_batch(arr, 2, ctypes.c_void_p(0x100001), need, None) == HLN_EINVAL   # misaligned
+    assert L.hln_csr_from_edges_batch(arr, -1, FAKE, need, None) == HLN_EINVAL
+    assert L.hln_csr_from_edges_batch(None, 2, FAKE, need, None) == HLN_EINVAL
+    assert L.hln_csr_from_edges_batch(None, 0, None, 0, None) == 0                                   # nothing to do
+    for bad in [EL(0, 3, FAKE, FAKE, FAKE, FAKE), EL(5, -1, FAKE, FAKE, FAKE, FAKE),
+                EL(5, (1 << 30) + 1, FAKE, FAKE, FAKE, FAKE), EL(5, 3, None, FAKE, FAKE, FAKE),
+                EL(5, 3, FAKE, FAKE, None, FAKE)]:
+        b = (EL * 2)(ok, bad)
+        assert L.hln_csr_from_edges_batch(b, 2, FAKE, 1 << 40, None) == HLN_EINVAL
+    # the size query reads only n and m
+    assert L.hln_csr_from_edges_batch_workspace_size((EL * 1)(EL(5, 3, None, None, None, None)), 1) == \
+        L.hln_csr_from_edges_batch_workspace_size((EL * 1)(ok), 1)
+    assert L.hln_csr_from_edges_batch_workspace_size((EL * 1)(EL(0, 3, None, None, None, None)), 1) == 0
+    # totals above 2^31 - 1 arcs: split the batch
+    big = (EL * 3)(*[EL(10, 1 << 30, FAKE, FAKE, FAKE, FAKE)] * 3)
+    assert L.hln_csr_from_edges_batch(big, 3, FAKE, 1 << 40, None) == HLN_EUNSUPPORTED
+
+
+def test_batched_topk_argument_checks():
+    L = P.lib()
+    TP = P._lib.hln_topk_problem
+    S = (ctypes.c_void_p * 2)(0x100000, 0x100000)
+    R = (ctypes.c_void_p * 2)(0x200000, 0x200000)
+    sp, rp = ctypes.cast(S, ctypes.c_void_p), ctypes.cast(R, ctypes.c_void_p)
+    ok = TP(1, 100, 2, 10, sp, rp, FAKE, FAKE, FAKE)
+    arr = (TP * 1)(ok)
+    need = L.hln_compose_cc_topk_batch_workspace_size(arr, 1)
+    assert need > 0
+    assert L.hln_compose_cc_topk_batch(arr, 1, FAKE, need - 1, None) == HLN_ENOMEM
+    assert L.hln_compose_cc_topk_batch(None, 0, None, 0, None) == 0
+    for bad in [TP(2, 100, 2, 10, sp, rp, FAKE, FAKE, FAKE),      # naive is not a top-k mode
+                TP(0, 100, 2, 10, sp, rp, FAKE, FAKE, FAKE),      # WF ranks one graph
+                TP(1, 100, 2, 101, sp, rp, FAKE, FAKE, FAKE),     # k > n
+                TP(1, 100, 65, 10, sp, rp, FAKE, FAKE, FAKE),     # r > 64
+                TP(1, 0, 2, 0, sp, rp, FAKE, FAKE, FAKE),         # n = 0
+                TP(1, 100, 2, 10, sp, rp, None, FAKE, FAKE),      # ids NULL
+                TP(1, 100, 2, 10, None, rp, FAKE, FAKE, FAKE)]:   # S NULL
+        b = (TP * 2)(ok, bad)
+        assert L.hln_compose_cc_topk_batch(b, 2, FAKE, 1 << 40, None) == HLN_EINVAL
+
+
+def test_plan_set_width_host():
+    plan = P.Plan()
+    for n, w in [(3000, 8), (3000, 16), (3000, 32), (3000, 64), (70000, 512), (70000, 2048)]:
+        plan.set_width(n, w)
+    assert plan.width(70000) == 2048
+    for bad in [(3000, 128), (3000, 4), (3000, 8192), (0, 64)]:
+        with pytest.raises(P.HlnError):
+            plan.set_width(*bad)
+    plan.set_width(70000, 0)
+    assert plan.width(70000) == 4096
