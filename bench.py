@@ -34,6 +34,7 @@ METRIC = "GTEPS all-source BFS closeness (+% HBM roofline); top-K precision vs A
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_closeness_cfg2_traffic.json")
 TRAFFIC_FILE_CFG3 = os.path.join(ROOT, "profiles", "k_closeness_multi_cfg3_traffic.json")
+TRAFFIC_FILE_CFG4 = os.path.join(ROOT, "profiles", "k_closeness_cfg4_traffic.json")
 KERNEL_SRC = [os.path.join(ROOT, "paper_2207_11662_amd", "csrc", f) for f in ("hln_msbfs.hip", "hln_internal.hpp")]
 BATCH_SRC = [os.path.join(ROOT, "paper_2207_11662_amd", "csrc", "hln_batch.hip")]
 
@@ -652,6 +653,12 @@ def run_cfg4(args):
     durations = [[events[s][gi][0].elapsed_time(events[s][gi][1]) / 1e3 for gi in range(G)] for s in range(args.steps)]
     dur_total = sum(sum(d) for d in durations)
     achieved = sum(bytes_per_launch) * args.steps / dur_total / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE_CFG4):
+        with open(TRAFFIC_FILE_CFG4) as f:
+            tr = json.load(f)
+        if tr.get("kernel_sha") == kernel_hash() and tr.get("width") == W:
+            traffic = tr.get("bytes_per_launch")
     rec = {"metric": METRIC, "value": round(sum(teps_den) * args.steps / elapsed / 1e9, 3), "unit": "GTEPS",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(elapsed * 1000 / args.steps, 3), "higher_is_better": True, "scaling": "weak",
@@ -661,7 +668,7 @@ def run_cfg4(args):
                       "and_edges": int(len(A_eu)), "source_batch": W, "graphs": G, "sources_per_graph": ns,
                       "teps_edges_per_step": int(sum(teps_den))},
            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                         "kernel": "k_closeness (persistent multi-source BFS, listed sources)",
                         "avg_launch_ms": round(dur_total / (G * args.steps) * 1e3, 3),
                         "algorithmic_bytes_per_launch": bytes_per_launch,
