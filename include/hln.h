@@ -147,6 +147,27 @@ hln_status hln_compose_and(const hln_csr* layers, int32_t r, int32_t* out_row_pt
 hln_status hln_compose_or(const hln_csr* layers, int32_t r, int32_t* out_row_ptr, int32_t* out_col_idx,
                           int64_t capacity, void* workspace, size_t workspace_bytes, void* stream);
 
+/* hln_compose_and_batch: hln_compose_and of `count` problems in one set of
+ * launches (e.g. the AND aggregates of many HoMLNs, or of every layer subset
+ * of one); each problem's outputs are exactly those of the one-problem call,
+ * under its rules (1 <= r <= 64 layers of equal n, capacity >= the smallest
+ * layer's nnz, else HLN_ENOMEM naming the problem).  problems [host];
+ * layers [host] per problem.  The problem and layer tables are written by
+ * kernels from their launch arguments, so nothing is staged on the host and
+ * the call can be captured.  The sums of the smallest layers' nnz and of
+ * n + 1 must stay below 2^31 - 1 (HLN_EUNSUPPORTED).  count = 0 does
+ * nothing; the workspace size reads only r, n and nnz (0 when invalid). */
+typedef struct {
+    int32_t r;
+    const hln_csr* layers;     /* [host] r graphs */
+    int32_t* out_row_ptr;      /* [dev] n + 1, output */
+    int32_t* out_col_idx;      /* [dev] capacity, output */
+    int64_t capacity;
+} hln_and_problem;
+size_t hln_compose_and_batch_workspace_size(const hln_and_problem* problems, int32_t count);
+hln_status hln_compose_and_batch(const hln_and_problem* problems, int32_t count, void* workspace,
+                                 size_t workspace_bytes, void* stream);
+
 /* ------------------------------------------------------------------------
  * Exact closeness of one graph (Sec. 4, Eq. 1 with the Wasserman-Faust
  * normalisation used for disconnected graphs; one BFS per source).

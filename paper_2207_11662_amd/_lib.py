@@ -23,7 +23,8 @@ EXPORTS = [
     "hln_last_error", "hln_version", "hln_device_cu_count", "hln_device_status",
     "hln_csr_from_edges_workspace_size", "hln_csr_from_edges", "hln_csr_from_edges_batch_workspace_size",
     "hln_csr_from_edges_batch", "hln_csr_validate",
-    "hln_compose_workspace_size", "hln_compose_and", "hln_compose_or",
+    "hln_compose_workspace_size", "hln_compose_and", "hln_compose_or", "hln_compose_and_batch_workspace_size",
+    "hln_compose_and_batch",
     "hln_closeness_workspace_size", "hln_closeness_layer", "hln_closeness_estimate",
     "hln_compose_cc_topk_workspace_size", "hln_compose_cc_topk",
     "hln_compose_cc_topk_batch_workspace_size", "hln_compose_cc_topk_batch", "hln_compose_cc1_workspace_size", "hln_compose_cc1",
@@ -59,6 +60,11 @@ class hln_topk_problem(ctypes.Structure):
                 ("count", ctypes.c_void_p)]
 
 
+class hln_and_problem(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int32), ("layers", ctypes.c_void_p), ("out_row_ptr", ctypes.c_void_p),
+                ("out_col_idx", ctypes.c_void_p), ("capacity", ctypes.c_int64)]
+
+
 class hln_opts(ctypes.Structure):
     _fields_ = [("width_bits", ctypes.c_int32), ("direction", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("levels", ctypes.c_void_p), ("trace", ctypes.c_void_p), ("trace_cap", ctypes.c_int32)]
@@ -92,6 +98,8 @@ def lib():
         "hln_compose_workspace_size": ([csr_p, i32], sz),
         "hln_compose_and": ([csr_p, i32, P, P, i64, P, sz, P], st),
         "hln_compose_or": ([csr_p, i32, P, P, i64, P, sz, P], st),
+        "hln_compose_and_batch_workspace_size": ([ctypes.POINTER(hln_and_problem), i32], sz),
+        "hln_compose_and_batch": ([ctypes.POINTER(hln_and_problem), i32, P, sz, P], st),
         "hln_closeness_workspace_size": ([i32, i64, i32, opts_p], sz),
         "hln_closeness_layer": ([csr_p, P, i32, opts_p, P, P, P, P, P, sz, P], st),
         "hln_closeness_estimate": ([i32, i32, P, i32, P, P, P, P], st),
@@ -349,6 +357,43 @@ def hln_compose_and(layers, ws=None, out=None, stream=None) -> Graph:
 def hln_compose_or(layers, ws=None, out=None, stream=None) -> Graph:
     """Edges present in at least one layer; col_idx sized by the sum."""
     return _compose(lib().hln_compose_or, layers, sum(g.nnz for g in layers), ws, out, stream)
+
+
+class AndBatch:
+    """hln_compose_and of many layer sets in one call.  problems: a list of
+    layer lists (Graphs of equal n within a list); outs: optional
+    (row_ptr, col_idx) per problem, col_idx sized by its smallest layer.
+    The host-side table is built once and kept, so run() can be repeated
+    or captured; it returns one Graph per problem (nnz = the capacity)."""
+
+    def __init__(self, problems, outs=None, ws=None):
+        self.problems = [list(p) for p in problems]
+        dev = self.problems[0][0].row_ptr.device if self.problems else torch.device("cuda")
+        caps = [min(g.nnz for g in p) for p in self.problems]
+        if outs is None:
+            outs = [(torch.empty(p[0].n + 1, dtype=torch.int32, device=dev),
+                     torch.empty(max(c, 1), dtype=torch.int32, device=dev)) for p, c in zip(self.problems, caps)]
+        self.outs, self.caps = outs, caps
+        self._keep = [_layers_c(p) for p in self.problems]
+        self.arr = (hln_and_problem * max(len(self.problems), 1))()
+        for i, (lay, (rp, ci), c) in enumerate(zip(self._keep, outs, caps)):
+            self.arr[i] = hln_and_problem(len(self.problems[i]), ctypes.cast(lay, ctypes.c_void_p), _ptr(rp), _ptr(ci), c)
+        self.need = int(lib().hln_compose_and_batch_workspace_size(self.arr, len(self.problems)))
+        if ws is None or ws.numel() < self.need:
+            ws = workspace(self.need, dev) if self.need else None
+        self.ws = ws
+
+    def run(self, stream=None):
+        wsp, wsn = (None, 0) if self.ws is None else (_ptr(self.ws), self.ws.numel())
+        check(lib().hln_compose_and_batch(self.arr, len(self.problems), wsp, wsn, _stream(stream)))
+        return [Graph(rp, ci[:c], c) for (rp, ci), c in zip(self.outs, self.caps)]
+
+
+def hln_compose_and_batch(problems, ws=None, outs=None, stream=None) -> list:
+    """AND aggregates of many layer sets in one call (see AndBatch)."""
+    if not problems:
+        return []
+    return AndBatch(problems, outs=outs, ws=ws).run(stream)
 
 
 # ---------------------------------------------------------------------------

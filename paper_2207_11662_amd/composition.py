@@ -112,19 +112,15 @@ def summarise(records) -> dict:
 
 def batched_and_truth(layers, subsets, k: int, width_bits: int = 4096) -> dict:
     """The AND ground truths of all subsets at once: every subset's AND
-    graph, then the closeness of all of them through one plan call (graphs
-    above the LDS-tile limit share one partitioned persistent launch) and
-    their top-k sets through one batched selection call; timed as a whole
-    with HIP events.  Returns the time and each subset's top-k ids."""
+    graph (one batched composition call), then the closeness of all of them
+    through one plan call (graphs above the LDS-tile limit share one
+    partitioned persistent launch) and their top-k sets through one batched
+    selection call; timed as a whole with HIP events.  Returns the time and
+    each subset's top-k ids."""
     dev = layers[0].row_ptr.device
     n = layers[0].n
-    bufs, wss = [], []
-    for sub in subsets:
-        gs = [layers[i] for i in sub]
-        bufs.append((torch.empty(n + 1, dtype=torch.int32, device=dev),
-                     torch.empty(min(g.nnz for g in gs), dtype=torch.int32, device=dev)))
-        wss.append(L.workspace(L.compose_workspace_size(gs), dev))
-    graphs = [L.Graph(rp, ci, ci.numel()) for rp, ci in bufs]
+    ands = L.AndBatch([[layers[i] for i in sub] for sub in subsets])
+    graphs = [L.Graph(rp, ci, ci.numel()) for rp, ci in ands.outs]
     plan = L.Plan()
     plan.set_width(n, width_bits)
     outs = L.Plan.outputs(graphs)
@@ -132,8 +128,7 @@ def batched_and_truth(layers, subsets, k: int, width_bits: int = 4096) -> dict:
     sel = L.TopkBatch([(L.HLN_RANK_WF, n, [o["S"]], [o["R"]], k) for o in outs])
 
     def run():
-        for sub, buf, w in zip(subsets, bufs, wss):
-            L.hln_compose_and([layers[i] for i in sub], ws=w, out=buf)
+        ands.run()
         plan.run(graphs, outs, ws=bws)
         sel.run()
 

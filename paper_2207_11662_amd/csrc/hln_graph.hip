@@ -267,6 +267,88 @@ __global__ void k_and_fill(LayerSet L, int p, const int32_t* __restrict__ flag, 
     for (long long u = t0; u <= L.n; u += stride) out_rp[u] = pos[L.rp[p][u]];
 }
 
+// ------------------------------------------------------- batched AND
+// Problem q keeps the arcs of its pivot layer (the one with the fewest arcs)
+// that every other layer of q holds.  Its pivot arcs are [e_off[q],
+// e_off[q+1]) of the concatenation and its row pointers [r_off[q],
+// r_off[q+1]) (n + 1 of them); its layers are lay[l_off .. l_off + r).
+struct AndProblem {
+    int32_t* out_rp;
+    int32_t* out_ci;
+    long long l_off;
+    int n, r, p;
+};
+struct LayerPtrs {
+    const int32_t* rp;
+    const int32_t* ci;
+};
+
+constexpr int kAndChunk = 24;
+constexpr int kLayChunk = 96;
+struct AndChunk {
+    AndProblem q[kAndChunk];
+    long long e_off[kAndChunk + 1], r_off[kAndChunk + 1];
+    int first, count;
+};
+struct LayChunk {
+    LayerPtrs l[kLayChunk];
+    long long first;
+    int count;
+};
+
+__global__ void k_put_and(AndChunk c, AndProblem* probs, long long* e_off, long long* r_off) {
+    const int i = threadIdx.x;
+    if (i < c.count) probs[c.first + i] = c.q[i];
+    if (i <= c.count) {
+        e_off[c.first + i] = c.e_off[i];
+        r_off[c.first + i] = c.r_off[i];
+    }
+}
+
+__global__ void k_put_lay(LayChunk c, LayerPtrs* lay) {
+    const int i = threadIdx.x;
+    if (i < c.count) lay[c.first + i] = c.l[i];
+}
+
+__global__ void k_ba_mark(const AndProblem* __restrict__ probs, const LayerPtrs* __restrict__ lay,
+                          const long long* __restrict__ e_off, int np, long long total, int32_t* flag) {
+    for (long long g = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
+         g += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const int q = list_of(e_off, np, g);
+        const AndProblem Q = probs[q];
+        const long long e = g - e_off[q];
+        const LayerPtrs P = lay[Q.l_off + Q.p];
+        const int u = row_of(P.rp, Q.n, e);
+        const int x = P.ci[e];
+        int keep = 1;
+        for (int l = 0; l < Q.r && keep; ++l) {
+            const LayerPtrs O = lay[Q.l_off + l];
+            if (l != Q.p && !in_row(O.rp, O.ci, u, x)) keep = 0;
+        }
+        flag[g] = keep;
+    }
+}
+
+__global__ void k_ba_fill(const AndProblem* __restrict__ probs, const LayerPtrs* __restrict__ lay,
+                          const long long* __restrict__ e_off, const long long* __restrict__ r_off, int np,
+                          long long total, long long total_rows, const int32_t* __restrict__ flag,
+                          const int32_t* __restrict__ pos) {
+    const long long stride = static_cast<long long>(gridDim.x) * blockDim.x;
+    const long long t0 = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (long long g = t0; g < total; g += stride)
+        if (flag[g]) {
+            const int q = list_of(e_off, np, g);
+            const AndProblem Q = probs[q];
+            Q.out_ci[pos[g] - pos[e_off[q]]] = lay[Q.l_off + Q.p].ci[g - e_off[q]];
+        }
+    for (long long j = t0; j < total_rows; j += stride) {
+        const int q = list_of(r_off, np, j);
+        const AndProblem Q = probs[q];
+        const long long u = j - r_off[q];
+        Q.out_rp[u] = pos[e_off[q] + lay[Q.l_off + Q.p].rp[u]] - pos[e_off[q]];
+    }
+}
+
 __global__ void k_or_mark(LayerSet L, int32_t* keep) {
     const long long total = L.base[L.r];
     for (long long g = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; g < total;
@@ -538,6 +620,50 @@ hln_status hln_csr_validate(const hln_csr* g, int32_t* result, void* stream) {
 
 namespace {
 
+struct AndSizes {
+    long long arcs = 0, rows = 0, layers = 0;
+};
+
+hln_status and_sizes(const hln_and_problem* pr, int32_t count, AndSizes& Z, bool check_ptrs) {
+    using hln::fail;
+    if (count < 0) return fail(HLN_EINVAL, "count must be >= 0");
+    if (count > 0 && !pr) return fail(HLN_EINVAL, "problems is NULL");
+    for (int q = 0; q < count; ++q) {
+        const hln_and_problem& P = pr[q];
+        if (!P.layers) return fail(HLN_EINVAL, "problem %d: layers is NULL", q);
+        LayerSet L;
+        const hln_status s = check_layers(P.layers, P.r, L);
+        if (s != HLN_OK) {
+            char why[200];
+            snprintf(why, sizeof why, "%s", hln_last_error());
+            return fail(s, "problem %d: %s", q, why);
+        }
+        int p = 0;
+        for (int l = 0; l < P.r; ++l)
+            if (P.layers[l].nnz < P.layers[p].nnz) p = l;
+        if (check_ptrs) {
+            if (!P.out_row_ptr || (P.capacity > 0 && !P.out_col_idx)) return fail(HLN_EINVAL, "problem %d: NULL output", q);
+            if (P.capacity < P.layers[p].nnz)
+                return fail(HLN_ENOMEM, "problem %d: output capacity %lld < bound %lld", q,
+                            static_cast<long long>(P.capacity), static_cast<long long>(P.layers[p].nnz));
+        }
+        Z.arcs += P.layers[p].nnz;
+        Z.rows += static_cast<long long>(L.n) + 1;
+        Z.layers += P.r;
+    }
+    if (Z.arcs >= (1ll << 31) - 1 || Z.rows >= (1ll << 31) - 1)
+        return fail(HLN_EUNSUPPORTED, "batch too large (pivot arcs %lld, rows %lld): split it", Z.arcs, Z.rows);
+    return HLN_OK;
+}
+
+size_t and_ws(int32_t count, const AndSizes& Z) {
+    using hln::Arena;
+    const size_t P1 = static_cast<size_t>(count) + 1;
+    return Arena::round(P1 * sizeof(AndProblem)) + 2 * Arena::round(P1 * 8) +
+           Arena::round(static_cast<size_t>(std::max<long long>(Z.layers, 1)) * sizeof(LayerPtrs)) +
+           2 * Arena::round(static_cast<size_t>(Z.arcs + 1) * 4) + hln::prim::scan_workspace(Z.arcs + 1);
+}
+
 size_t compose_ws(const LayerSet& L) {
     using hln::Arena;
     const long long total = L.base[L.r];
@@ -614,6 +740,81 @@ hln_status hln_compose_and(const hln_csr* layers, int32_t r, int32_t* out_row_pt
 hln_status hln_compose_or(const hln_csr* layers, int32_t r, int32_t* out_row_ptr, int32_t* out_col_idx,
                           int64_t capacity, void* workspace, size_t workspace_bytes, void* stream) {
     return compose(1, layers, r, out_row_ptr, out_col_idx, capacity, workspace, workspace_bytes, stream);
+}
+
+size_t hln_compose_and_batch_workspace_size(const hln_and_problem* problems, int32_t count) {
+    AndSizes Z;
+    if (and_sizes(problems, count, Z, false) != HLN_OK) return 0;
+    return and_ws(count, Z);
+}
+
+hln_status hln_compose_and_batch(const hln_and_problem* problems, int32_t count, void* workspace,
+                                 size_t workspace_bytes, void* stream) {
+    using hln::fail;
+    hln::clear_error();
+    AndSizes Z;
+    hln_status s = and_sizes(problems, count, Z, true);
+    if (s != HLN_OK) return s;
+    if (count == 0) return HLN_OK;
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % hln::Arena::kAlign)
+        return fail(HLN_EINVAL, "workspace NULL or not 256-byte aligned");
+    const size_t need = and_ws(count, Z);
+    if (workspace_bytes < need) return fail(HLN_ENOMEM, "workspace too small: %zu < %zu", workspace_bytes, need);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hln::Arena ar{static_cast<char*>(workspace), workspace_bytes};
+    AndProblem* probs = ar.take<AndProblem>(count + 1);
+    long long* e_off = ar.take<long long>(count + 1);
+    long long* r_off = ar.take<long long>(count + 1);
+    LayerPtrs* lay = ar.take<LayerPtrs>(std::max<long long>(Z.layers, 1));
+    int32_t* flag = ar.take<int32_t>(Z.arcs + 1);
+    int32_t* pos = ar.take<int32_t>(Z.arcs + 1);
+    void* sws = ar.base + ar.off;
+    const size_t sws_bytes = workspace_bytes - ar.off;
+
+    long long eo = 0, ro = 0, lo = 0;
+    for (int first = 0; first < count; first += kAndChunk) {
+        AndChunk c{};
+        c.first = first;
+        c.count = std::min(kAndChunk, count - first);
+        for (int i = 0; i <= c.count; ++i) {
+            c.e_off[i] = eo;
+            c.r_off[i] = ro;
+            if (i == c.count) break;
+            const hln_and_problem& P = problems[first + i];
+            int p = 0;
+            for (int l = 0; l < P.r; ++l)
+                if (P.layers[l].nnz < P.layers[p].nnz) p = l;
+            c.q[i] = AndProblem{P.out_row_ptr, P.out_col_idx, lo, P.layers[0].n, P.r, p};
+            eo += P.layers[p].nnz;
+            ro += static_cast<long long>(P.layers[0].n) + 1;
+            lo += P.r;
+        }
+        hipLaunchKernelGGL(k_put_and, dim3(1), dim3(64), 0, st, c, probs, e_off, r_off);
+    }
+    {
+        LayChunk c{};
+        c.first = 0;
+        c.count = 0;
+        for (int q = 0; q < count; ++q)
+            for (int l = 0; l < problems[q].r; ++l) {
+                c.l[c.count] = LayerPtrs{problems[q].layers[l].row_ptr, problems[q].layers[l].col_idx};
+                if (++c.count == kLayChunk) {
+                    hipLaunchKernelGGL(k_put_lay, dim3(1), dim3(128), 0, st, c, lay);
+                    c.first += c.count;
+                    c.count = 0;
+                }
+            }
+        if (c.count) hipLaunchKernelGGL(k_put_lay, dim3(1), dim3(128), 0, st, c, lay);
+    }
+    HLN_TRY_HIP(hipGetLastError());
+    if (Z.arcs > 0)
+        hipLaunchKernelGGL(k_ba_mark, dim3(grid_for(Z.arcs)), dim3(256), 0, st, probs, lay, e_off, count, Z.arcs, flag);
+    s = hln::prim::scan_exclusive<int32_t>(flag, pos, Z.arcs, sws, sws_bytes, st);
+    if (s != HLN_OK) return s;
+    hipLaunchKernelGGL(k_ba_fill, dim3(grid_for(std::max(Z.arcs, Z.rows))), dim3(256), 0, st, probs, lay, e_off, r_off,
+                       count, Z.arcs, Z.rows, flag, pos);
+    HLN_TRY_HIP(hipGetLastError());
+    return HLN_OK;
 }
 
 }  // extern "C"

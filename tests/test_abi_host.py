@@ -162,3 +162,24 @@ def test_plan_set_width_host():
             plan.set_width(*bad)
     plan.set_width(70000, 0)
     assert plan.width(70000) == 4096
+
+
+def test_batched_and_argument_checks():
+    L = P.lib()
+    AP = P._lib.hln_and_problem
+    a, b = _csr(10, 20), _csr(10, 30)
+    lay = (P._lib.hln_csr * 2)(a, b)
+    lp = ctypes.cast(lay, ctypes.c_void_p)
+    ok = AP(2, lp, FAKE, FAKE, 20)
+    need = L.hln_compose_and_batch_workspace_size((AP * 1)(ok), 1)
+    assert need > 0
+    assert L.hln_compose_and_batch((AP * 1)(ok), 1, FAKE, need - 1, None) == HLN_ENOMEM
+    assert L.hln_compose_and_batch((AP * 1)(AP(2, lp, FAKE, FAKE, 19)), 1, FAKE, 1 << 40, None) == HLN_ENOMEM
+    c = _csr(11, 20)
+    lay2 = (P._lib.hln_csr * 2)(a, c)
+    for bad in [AP(0, lp, FAKE, FAKE, 20), AP(65, lp, FAKE, FAKE, 20), AP(2, None, FAKE, FAKE, 20),
+                AP(2, lp, None, FAKE, 20), AP(2, ctypes.cast(lay2, ctypes.c_void_p), FAKE, FAKE, 20)]:
+        assert L.hln_compose_and_batch((AP * 2)(ok, bad), 2, FAKE, 1 << 40, None) == HLN_EINVAL
+    assert b"problem 1" in L.hln_last_error()
+    assert L.hln_compose_and_batch(None, 0, None, 0, None) == 0
+    assert L.hln_compose_and_batch(None, -1, None, 0, None) == HLN_EINVAL

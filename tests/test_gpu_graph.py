@@ -253,3 +253,71 @@ def test_compose_configs(cfg):
     for mode in ("and", "or"):
         rp_o, ci_o = O.compose(mode, layers)
         assert np.array_equal(got[mode][0], rp_o) and np.array_equal(got[mode][1], ci_o), mode
+
+
+def random_layer_sets(seed, count):
+    rng = np.random.default_rng(seed)
+    sets = []
+    for t in range(count):
+        n = int(rng.integers(2, 3000))
+        r = int(rng.integers(1, 7))
+        base = G.take_distinct(G.er_draw(n), min(n * 2, n * (n - 1) // 4), n, rng)
+        layers = []
+        for _ in range(r):
+            extra = G.take_distinct(G.er_draw(n), min(n, n * (n - 1) // 4), n, rng)
+            keep = base[rng.random(len(base)) < 0.7]
+            eu, ev = G.keys_to_edges(np.concatenate([keep, extra]), n)
+            layers.append(csr_np(n, eu, ev))
+        if t % 7 == 3:                                  # an empty layer: empty AND
+            layers.append(csr_np(n, np.zeros(0, np.int64), np.zeros(0, np.int64)))
+        sets.append(layers)
+    return sets
+
+
+def test_compose_and_batch_against_oracle_and_single_calls():
+    """Thirty layer sets of different sizes (1 to 7 layers, some with an
+    empty layer) in one call: every AND against the oracle and against the
+    one-problem call; then replayed from a hipGraph."""
+    sets = random_layer_sets(41, 30)
+    dev_sets = [[graph_dev(P, rp, ci) for rp, ci in layers] for layers in sets]
+    ab = P.AndBatch(dev_sets)
+    got = ab.run()
+    torch.cuda.synchronize()
+    P.device_status()
+    for i, (layers, g, gs) in enumerate(zip(sets, got, dev_sets)):
+        rp_o, ci_o = O.compose("and", layers)
+        rp = g.row_ptr.cpu().numpy()
+        assert np.array_equal(rp, rp_o), i
+        assert np.array_equal(g.col_idx[:int(rp[-1])].cpu().numpy(), ci_o), i
+        one = P.hln_compose_and(gs).trimmed()
+        torch.cuda.synchronize()
+        assert np.array_equal(one.row_ptr.cpu().numpy(), rp) and np.array_equal(one.col_idx.cpu().numpy(), ci_o)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        ab.run()
+    for rep in range(2):
+        for rp, ci in ab.outs:
+            rp.fill_(-5)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        P.device_status()
+        for i, (layers, (rp, ci)) in enumerate(zip(sets, ab.outs)):
+            rp_o, ci_o = O.compose("and", layers)
+            r = rp.cpu().numpy()
+            assert np.array_equal(r, rp_o) and np.array_equal(ci[:int(r[-1])].cpu().numpy(), ci_o), (rep, i)
+
+
+def test_compose_and_batch_errors():
+    L = P.lib()
+    assert P.hln_compose_and_batch([]) == []
+    assert L.hln_compose_and_batch(None, 0, None, 0, None) == 0
+    a = graph_dev(P, *csr_np(10, np.array([0, 1]), np.array([1, 2])))
+    b = graph_dev(P, *csr_np(11, np.array([0, 1]), np.array([1, 2])))
+    with pytest.raises(P.HlnError):                     # n differs inside a problem
+        P.hln_compose_and_batch([[a, a], [a, b]])
+    ab = P.AndBatch([[a, a]])
+    small = torch.zeros(256, dtype=torch.uint8, device="cuda")
+    assert L.hln_compose_and_batch(ab.arr, 1, P._lib._ptr(small), 256, None) == 2
+    ab.arr[0].capacity = a.nnz - 1                      # below the smallest layer's arcs
+    assert L.hln_compose_and_batch(ab.arr, 1, P._lib._ptr(ab.ws), ab.ws.numel(), None) == 2

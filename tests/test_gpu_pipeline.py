@@ -1,5 +1,5 @@
 """The batched step of config 3, end to end and captured as the bench
-captures it (batched ingest + AND + LDS-tile graphs, the persistent graphs
+captures it (batched ingest + batched AND + LDS-tile graphs, the persistent graphs
 through a second plan pinned to the same widths, batched CC2 top-10%), on
 eight HoMLNs at a tenth of config 3's sizes, replayed twice: every CSR, AND
 graph, S, R, closeness and CC2 top-10% set against the CPU oracle."""
@@ -38,12 +38,12 @@ def test_config3_step_captured_against_oracle():
                           sel=(torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.float64, device=dev),
                                torch.empty(1, dtype=torch.int32, device=dev))))
     iws = P.workspace(P.csr_from_edges_batch_workspace_size(ing_items))
-    cws = P.workspace(max(P.compose_workspace_size(it["graphs"]) for it in items))
+
+    ands = P.AndBatch([it["graphs"] for it in items], outs=[it["abuf"] for it in items])
 
     def ingest_compose():
         P.hln_csr_from_edges_batch(ing_items, ws=iws, outs=ing_outs)
-        for it in items:
-            P.hln_compose_and(it["graphs"], ws=cws, out=it["abuf"])
+        ands.run()
 
     outs = P.Plan.outputs(all_graphs, want_h2=False)
     ingest_compose()
