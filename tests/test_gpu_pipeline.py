@@ -16,8 +16,12 @@ pytestmark = pytest.mark.gpu
 P = pytest.importorskip("paper_2207_11662_amd")
 
 
-def test_config3_step_captured_against_oracle():
-    hs = C.config3(count=8, scale=0.1)
+def build_step(hs, tuned):
+    """The bench's config-3 step over the HoMLNs hs: three callables (batched
+    ingest + batched AND + tile graphs; the persistent graphs through a plan
+    pinned to the same widths; batched CC2 top-k) and their buffers.  tuned:
+    widths from the autotuner (as the bench); else the largest size class is
+    sent to the persistent kernel and the rest to tiles."""
     dev = torch.device("cuda")
     items, ing_items, ing_outs, all_graphs = [], [], [], []
     for h in hs:
@@ -49,9 +53,11 @@ def test_config3_step_captured_against_oracle():
     ingest_compose()
     torch.cuda.synchronize()
     plan = P.Plan()
-    # the largest size class goes to the persistent kernel, the rest to tiles
-    big = max(g.n for g in all_graphs)
-    plan.set_width(big, 4096)
+    if tuned:
+        plan.tune(all_graphs, outs)
+    else:
+        # the largest size class goes to the persistent kernel, the rest to tiles
+        plan.set_width(max(g.n for g in all_graphs), 4096)
     coop = [i for i, g in enumerate(all_graphs) if plan.width(g.n) >= 512]
     tile = [i for i, g in enumerate(all_graphs) if plan.width(g.n) < 512]
     assert coop and tile
@@ -73,6 +79,15 @@ def test_config3_step_captured_against_oracle():
     for f in parts:
         f()
     torch.cuda.synchronize()
+    P.device_status()
+    return dict(items=items, ing_outs=ing_outs, all_graphs=all_graphs, outs=outs, parts=parts, coop=coop)
+
+
+def test_config3_step_captured_against_oracle():
+    hs = C.config3(count=8, scale=0.1)
+    st = build_step(hs, tuned=False)
+    items, ing_outs, all_graphs, outs, parts, coop = (st[k] for k in ("items", "ing_outs", "all_graphs", "outs",
+                                                                       "parts", "coop"))
     caps = []
     for f in parts:
         g = torch.cuda.CUDAGraph()
@@ -121,3 +136,40 @@ def test_config3_step_captured_against_oracle():
             assert c == it["k"] and np.array_equal(it["sel"][0][:c].cpu().numpy(), top), (rep, hi)
             o += it["nl"] + 1
         say("replay", rep, "ok:", len(items), "HoMLNs,", len(all_graphs), "graphs,", len(coop), "persistent")
+
+
+def test_config3_full_size_sampled():
+    """All 64 HoMLNs of config 3 at full size, in the bench's launch
+    configuration (autotuned widths, the persistent graphs in one partitioned
+    multi-graph launch): every layer's CSR and every AND graph equal the
+    oracle's; on every graph, 6 sampled vertices' S and R equal the oracle's
+    BFS from them; the CC2 top-10% sets of the four smallest HoMLNs equal the
+    oracle's from its own all-source sums."""
+    hs = C.config3()
+    st = build_step(hs, tuned=True)
+    items, outs = st["items"], st["outs"]
+    say("graphs", len(st["all_graphs"]), "persistent", len(st["coop"]))
+    assert len(st["coop"]) > 100
+    rng = np.random.default_rng(77)
+    o = 0
+    small = set(np.argsort([it["n"] for it in items])[:4].tolist())
+    for hi, it in enumerate(items):
+        h, n = it["h"], it["n"]
+        layers = [O.csr_from_edges(n, eu, ev) for eu, ev in h.layers]
+        csrs = layers + [O.compose("and", layers)]
+        gs = it["graphs"] + [P.Graph(it["abuf"][0], it["abuf"][1], it["abuf"][1].numel())]
+        for gi, ((rp, ci), g) in enumerate(zip(csrs, gs)):
+            grp = g.row_ptr.cpu().numpy()
+            assert np.array_equal(grp, rp), (hi, gi)
+            assert np.array_equal(g.col_idx[:int(grp[-1])].cpu().numpy(), ci), (hi, gi)
+            src = np.sort(rng.choice(n, size=6, replace=False)).astype(np.int32)
+            S, R = O.bfs_sums(rp, ci, sources=src)
+            assert np.array_equal(outs[o + gi]["S"].cpu().numpy()[src], S), (hi, gi)
+            assert np.array_equal(outs[o + gi]["R"].cpu().numpy()[src], R), (hi, gi)
+        if hi in small:
+            sums = [O.bfs_sums(rp, ci) for rp, ci in layers]
+            est = O.cc2_est(n, [S for S, _ in sums], [R for _, R in sums])
+            top = O.topk_asc_i64(est, it["k"])
+            c = int(it["sel"][2].item())
+            assert c == it["k"] and np.array_equal(it["sel"][0][:c].cpu().numpy(), top), hi
+        o += it["nl"] + 1
