@@ -156,7 +156,8 @@ hln_status hln_compose_or(const hln_csr* layers, int32_t r, int32_t* out_row_ptr
  * kernels from their launch arguments, so nothing is staged on the host and
  * the call can be captured.  The sums of the smallest layers' nnz and of
  * n + 1 must stay below 2^31 - 1 (HLN_EUNSUPPORTED).  count = 0 does
- * nothing; the workspace size reads only r, n and nnz (0 when invalid). */
+ * nothing; the workspace size checks the layers as the call does (0 when a
+ * problem is invalid) but not the outputs or capacities. */
 typedef struct {
     int32_t r;
     const hln_csr* layers;     /* [host] r graphs */
