@@ -68,7 +68,10 @@ typedef struct {
     int32_t direction;    /* 0 = automatic per level, 1 = top-down only, 2 = bottom-up only */
     int32_t flags;        /* 0 or HLN_FLAG_PER_VERTEX (see hln_closeness_layer) */
     int32_t* levels;      /* [dev] nullable: per batch of width_bits sources, the BFS levels run
-                             (1 + the largest eccentricity among the batch's sources) */
+                             (1 + the largest eccentricity among the batch's sources).  All-source
+                             mode batches only the vertices that have arcs, in id order (one
+                             without arcs reaches only itself), so entries from
+                             ceil(#vertices with arcs / width_bits) on are not written */
     int64_t* trace;       /* [dev] nullable, zero-filled by the caller: per level run (in order, over
                              all batches) 4 int64: s_memrealtime ticks (100 MHz) when the level's
                              barrier completed, vertices given new bits, new (vertex, source) pairs,

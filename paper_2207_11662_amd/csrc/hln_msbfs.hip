@@ -34,7 +34,9 @@
 // once it holds all of them no other source of the batch can reach it.
 //
 // Accumulation:
-//   all sources (sources == NULL): the graph is undirected, so d(s,v) =
+//   all sources (sources == NULL): the batches take the vertices that have
+//     arcs, in id order (a vertex without arcs reaches only itself); the
+//     graph is undirected, so d(s,v) =
 //     d(v,s) and the vertex v accumulates S[v] += d*popc(new), R[v] +=
 //     popc(new); after all n sources S[v], R[v] are v's own sums.  H2[v]
 //     counts the new bits at d = 2.
@@ -180,6 +182,7 @@ struct Ctrl {
     unsigned long long farcs[3];           // frontier arc-words of the same phases
     unsigned long long probe_key;          // first batch's probe source: degree << 32 | ~position (max)
     unsigned long long gcm[64];            // this batch's sources in the largest component (bit per source)
+    int n_act;                        // all sources: vertices with arcs
 };
 
 // LDS frontier-list entries per block and phase; a phase that lists more in
@@ -223,6 +226,9 @@ struct BfsArgs {
     int32_t trace_cap;
     int32_t seg_len;                  // SEG
     int32_t alpha;                    // top-down when alpha * frontier arc-words < arcs of the graph
+    int32_t* perm;                    // all sources: the vertices with arcs, in id order (the batches' sources)
+    int32_t* iperm;                   // all sources: a vertex's position in perm, -1 without arcs
+    int32_t* bcount;                  // all sources: vertices with arcs per block range
     int32_t s32_levels;               // depth from which distance sums go to S with 64-bit atomics
 };
 
@@ -639,7 +645,23 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
         static_cast<Mask*>(a.flagA)[v] = 0;
         static_cast<Mask*>(a.flagB)[v] = 0;
     }
+    // All sources: the batches take only the vertices that have arcs (one
+    // without any reaches just itself: R = 1 and S = 0 as set above), in id
+    // order.  Block blk counts those of its range of ids here and ranks them
+    // in phase 1.
+    __shared__ int s_act[BLOCK / 64 + 1];
+    const long long id_chunk = (static_cast<long long>(n) + nblk - 1) / nblk;
+    const long long id_lo = min(static_cast<long long>(blk) * id_chunk, static_cast<long long>(n));
+    const long long id_hi = min(id_lo + id_chunk, static_cast<long long>(n));
+    if (!a.listed) {
+        if (threadIdx.x == 0) s_act[0] = 0;
+        __syncthreads();
+        int c = 0;
+        for (long long v = id_lo + threadIdx.x; v < id_hi; v += BLOCK) c += a.row_ptr[v + 1] != a.row_ptr[v] ? 1 : 0;
+        if (c) atomicAdd(&s_act[0], c);
+    }
     __syncthreads();
+    if (!a.listed && threadIdx.x == 0) a.bcount[blk] = s_act[0];
     if (threadIdx.x < kClasses && s_bins[threadIdx.x]) atomicAdd(&ctrl->bins[threadIdx.x], s_bins[threadIdx.x]);
     if (!gb.wait()) return false;
     if (load_agent_i32(a.fault) != 0) return false;              // uniform: read after the barrier
@@ -653,6 +675,39 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
             acc += b;
         }
         store_agent_i32(&ctrl->n_seg, acc);
+    }
+    if (!a.listed) {
+        // this block's first position: the counts of the blocks before it
+        __shared__ int s_base_act;
+        if (threadIdx.x == 0) s_base_act = 0;
+        __syncthreads();
+        int o = 0;
+        for (unsigned b2 = threadIdx.x; b2 < blk; b2 += BLOCK) o += a.bcount[b2];
+        if (o) atomicAdd(&s_base_act, o);
+        __syncthreads();
+        int run = s_base_act;
+        if (blk == nblk - 1 && threadIdx.x == 0) store_agent_i32(&ctrl->n_act, run + a.bcount[blk]);
+        const int wave = threadIdx.x >> 6;
+        for (long long base = id_lo; base < id_hi; base += BLOCK) {
+            const long long v = base + threadIdx.x;
+            const bool act = v < id_hi && a.row_ptr[v + 1] != a.row_ptr[v];
+            const unsigned long long bal = __ballot(act);
+            const int before = __popcll(bal & ((1ull << lane) - 1ull));
+            if (lane == 0) s_act[wave] = __popcll(bal);
+            __syncthreads();
+            int woff = 0, tot = 0;
+            for (int w2 = 0; w2 < BLOCK / 64; ++w2) {
+                if (w2 < wave) woff += s_act[w2];
+                tot += s_act[w2];
+            }
+            if (v < id_hi) {
+                const int pos = run + woff + before;
+                a.iperm[v] = act ? pos : -1;
+                if (act) a.perm[pos] = static_cast<int32_t>(v);
+            }
+            run += tot;
+            __syncthreads();
+        }
     }
     if (!gb.wait()) return false;
 
@@ -691,14 +746,16 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
     if (!gb.wait()) return false;
     const long long n_seg = min(static_cast<long long>(load_agent_i32(&ctrl->n_seg)), a.seg_cap);
 
-    const int n_batches = (a.n_src + W - 1) / W;
+    // all sources: the batches run over the vertices with arcs (perm)
+    const int n_src_eff = a.listed ? a.n_src : load_agent_i32(&ctrl->n_act);
+    const int n_batches = (n_src_eff + W - 1) / W;
     const long long m_arcs = a.row_ptr[n];               // checked against nnz_cap in phase 0
     const unsigned long long gmask = (kLpv >= 64 ? ~0ull : ((1ull << kLpv) - 1ull)) << gbase;
     int trace_row = 0;
     int phase = 0;                                       // list slot of a phase: phase % 3
     for (int b = 0; b < n_batches; ++b) {
         const int src0 = b * W;
-        const int cnt = min(W, a.n_src - src0);
+        const int cnt = min(W, n_src_eff - src0);
 
         // ---- batch init: vis = fr = the batch's source bits; the sources'
         // segments form the first frontier list; no segment is saturated
@@ -715,7 +772,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
             for (long long i = tid; i < W; i += nthreads) {
                 bool in = false;
                 if (i < cnt) {
-                    const int src = a.listed ? a.sources[src0 + i] : static_cast<int>(src0 + i);
+                    const int src = a.listed ? a.sources[src0 + i] : a.perm[src0 + i];
                     if (b == 0) {
                         const unsigned long long deg = static_cast<unsigned long long>(a.row_ptr[src + 1] - a.row_ptr[src]);
                         __hip_atomic_fetch_max(&ctrl->probe_key, (deg << 32) | (0xffffffffull - static_cast<unsigned long long>(i)),
@@ -737,7 +794,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                 for (long long i = tid; i < static_cast<long long>(n) * NW; i += nthreads) {
                     const long long v = i / NW;
                     const int kk = static_cast<int>(i % NW);
-                    const long long bit = v - src0;
+                    const long long bit = static_cast<long long>(a.iperm[v]) - src0;
                     uint64_t w0 = 0;
                     if (bit >= 0 && bit < cnt && (bit >> 6) == kk) w0 = 1ull << (bit & 63);
                     a.vis[i] = w0;
@@ -745,10 +802,11 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                 // frontier words are read only where the word mask has the bit,
                 // so only the sources' own words are written
                 for (long long i = tid; i < cnt; i += nthreads)
-                    a.bufA[static_cast<size_t>(src0 + i) * NW + (i >> 6)] = 1ull << (i & 63);
+                    a.bufA[static_cast<size_t>(a.perm[src0 + i]) * NW + (i >> 6)] = 1ull << (i & 63);
                 for (long long v = tid; v < n; v += nthreads) {
+                    const int j = a.iperm[v] - src0;
                     static_cast<Mask*>(a.flagA)[v] =
-                        (v >= src0 && v < src0 + cnt) ? static_cast<Mask>(static_cast<Mask>(1) << ((v - src0) >> 6)) : Mask(0);
+                        (j >= 0 && j < cnt) ? static_cast<Mask>(static_cast<Mask>(1) << (j >> 6)) : Mask(0);
                     // the previous batch's 32-bit sums into S
                     const uint32_t x = a.S32[v];
                     if (x) {
@@ -757,7 +815,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                     }
                 }
                 for (long long i = tid_x; i < cnt; i += nthreads) {
-                    const int3 sg = vertex_segments(a, static_cast<int>(src0 + i));
+                    const int3 sg = vertex_segments(a, a.perm[src0 + i]);
                     if (sg.y > 0) frontier_note(s_fr, par, sg.x, sg.y, sg.z);
                 }
             } else {
@@ -960,9 +1018,10 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                     }
                 };
                 // Level 1 of an all-source batch at W = 4096: the frontier is the
-                // batch's sources src0 .. src0 + cnt - 1 with one bit each, so a
-                // neighbour's frontier word follows from its id: the level reads
-                // column ids only (no neighbour masks, no frontier words).
+                // batch's sources perm[src0 .. src0 + cnt - 1] with one bit each,
+                // so a neighbour's frontier word follows from its place in perm:
+                // the level reads column ids and iperm only (no neighbour masks,
+                // no frontier words).
                 bool level1_ids = false;
                 if constexpr (NW == 64) level1_ids = d == 1 && !a.listed;
                 if (level1_ids) {
@@ -972,7 +1031,8 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                         const int cidl = gl < len ? static_cast<int>(buf_u32(B.col, static_cast<uint32_t>(sg.y + gl) * 4u)) : -1;
                         const Mask flag_old = buf_mask<Mask>(B.flag_nx, sg.w == 1 ? static_cast<uint32_t>(sg.x) * static_cast<uint32_t>(sizeof(Mask))
                                                                                   : kNoWord);
-                        const int rel_l = cidl - src0;
+                        // the neighbour's bit: its place among the batches' sources
+                        const int rel_l = (cidl >= 0 ? a.iperm[cidl] : -1 - src0) - src0;
                         unsigned long long hits = __ballot(cidl >= 0 && rel_l >= 0 && rel_l < cnt);
                         uint64_t acc = 0;
                         while (hits) {
@@ -1323,6 +1383,8 @@ size_t workspace_bytes(int32_t n, int64_t nnz, int nw, int grid_cap) {
     b += Arena::round(seg_cap * sizeof(uint32_t));                    // saturated segments
     b += Arena::round(static_cast<size_t>(n) * sizeof(uint32_t));    // probe component membership
     b += Arena::round(static_cast<size_t>(grid_cap) * 2 * 64 * nw * sizeof(int64_t));  // per-source partials
+    b += 2 * Arena::round(static_cast<size_t>(n) * sizeof(int32_t));   // perm, iperm
+    b += Arena::round(static_cast<size_t>(grid_cap) * sizeof(int32_t)); // per-block counts
     return b;
 }
 
@@ -1361,6 +1423,9 @@ hln_status fill_args(BfsArgs& a, const hln_csr* g, const int32_t* sources, int32
     a.S32 = ar.take<uint32_t>(n);
     a.nnz_cap = g->nnz;
     a.part = ar.take<int64_t>(static_cast<size_t>(grid_cap) * 2 * 64 * nw);
+    a.perm = ar.take<int32_t>(n);
+    a.iperm = ar.take<int32_t>(n);
+    a.bcount = ar.take<int32_t>(grid_cap);
     a.S = S;
     a.R = R;
     a.H2 = h2;
@@ -1376,7 +1441,8 @@ hln_status fill_args(BfsArgs& a, const hln_csr* g, const int32_t* sources, int32
     if (const char* e = getenv("HLN_ALPHA")) a.alpha = std::max(1, atoi(e));
     a.s32_levels = kS32Levels;
     if (const char* e = getenv("HLN_S32_LEVELS")) a.s32_levels = std::min(kS32Levels, std::max(1, atoi(e)));
-    if (!a.ctrl || !a.bar || !a.part || !a.flagB || !a.seg_first || !a.S32 || !a.segsat || !a.member)
+    if (!a.ctrl || !a.bar || !a.part || !a.flagB || !a.seg_first || !a.S32 || !a.segsat || !a.member || !a.perm ||
+        !a.iperm || !a.bcount)
         return fail(HLN_ENOMEM, "workspace carve failed");
     return HLN_OK;
 }
