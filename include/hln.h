@@ -69,8 +69,9 @@ typedef struct {
     int32_t flags;        /* 0 or HLN_FLAG_PER_VERTEX (see hln_closeness_layer) */
     int32_t* levels;      /* [dev] nullable: per batch of width_bits sources, the BFS levels run
                              (1 + the largest eccentricity among the batch's sources).  All-source
-                             mode batches only the vertices that have arcs, in id order (one
-                             without arcs reaches only itself), so entries from
+                             mode batches only the vertices that have arcs (one without arcs
+                             reaches only itself), by degree class (more than 64 arcs, 64, 32-63,
+                             16-31, 8-15, 4-7, 2-3, 1) and ids ascending inside a class, so entries from
                              ceil(#vertices with arcs / width_bits) on are not written */
     int64_t* trace;       /* [dev] nullable, zero-filled by the caller: per level run (in order, over
                              all batches) 4 int64: s_memrealtime ticks (100 MHz) when the level's

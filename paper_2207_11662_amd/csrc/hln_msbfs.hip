@@ -189,6 +189,9 @@ struct Ctrl {
 // one block makes the next level bottom-up (such a frontier is far past the
 // top-down threshold anyway).
 constexpr int kFlCap = 4096;
+// Degree classes that order the all-source batches (segments of 64 arcs:
+// class 0 holds rows longer than a segment, class 7 rows of one arc).
+constexpr int kRankClasses = 8;
 
 struct BfsArgs {
     int32_t n;
@@ -228,7 +231,7 @@ struct BfsArgs {
     int32_t alpha;                    // top-down when alpha * frontier arc-words < arcs of the graph
     int32_t* perm;                    // all sources: the vertices with arcs, in id order (the batches' sources)
     int32_t* iperm;                   // all sources: a vertex's position in perm, -1 without arcs
-    int32_t* bcount;                  // all sources: vertices with arcs per block range
+    int32_t* bcount;                  // all sources: vertices with arcs per block range and degree class
     int32_t s32_levels;               // depth from which distance sums go to S with 64-bit atomics
 };
 
@@ -646,22 +649,29 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
         static_cast<Mask*>(a.flagB)[v] = 0;
     }
     // All sources: the batches take only the vertices that have arcs (one
-    // without any reaches just itself: R = 1 and S = 0 as set above), in id
-    // order.  Block blk counts those of its range of ids here and ranks them
-    // in phase 1.
-    __shared__ int s_act[BLOCK / 64 + 1];
+    // without any reaches just itself: R = 1 and S = 0 as set above), largest
+    // degree class first and in id order inside a class (batches of hubs end
+    // in fewer levels).  Block blk counts those of its range of ids per class
+    // here and ranks them in phase 1.
+    __shared__ int s_act[BLOCK / 64][kRankClasses];
+    __shared__ int s_cls[kRankClasses];
     const long long id_chunk = (static_cast<long long>(n) + nblk - 1) / nblk;
     const long long id_lo = min(static_cast<long long>(blk) * id_chunk, static_cast<long long>(n));
     const long long id_hi = min(id_lo + id_chunk, static_cast<long long>(n));
+    auto rank_class = [&](long long v) {
+        const int deg = a.row_ptr[v + 1] - a.row_ptr[v];
+        return deg > 0 ? min(seg_class(deg, seg_len), kRankClasses - 1) : -1;
+    };
     if (!a.listed) {
-        if (threadIdx.x == 0) s_act[0] = 0;
+        if (threadIdx.x < kRankClasses) s_cls[threadIdx.x] = 0;
         __syncthreads();
-        int c = 0;
-        for (long long v = id_lo + threadIdx.x; v < id_hi; v += BLOCK) c += a.row_ptr[v + 1] != a.row_ptr[v] ? 1 : 0;
-        if (c) atomicAdd(&s_act[0], c);
+        for (long long v = id_lo + threadIdx.x; v < id_hi; v += BLOCK) {
+            const int c = rank_class(v);
+            if (c >= 0) atomicAdd(&s_cls[c], 1);
+        }
     }
     __syncthreads();
-    if (!a.listed && threadIdx.x == 0) a.bcount[blk] = s_act[0];
+    if (!a.listed && threadIdx.x < kRankClasses) a.bcount[blk * kRankClasses + threadIdx.x] = s_cls[threadIdx.x];
     if (threadIdx.x < kClasses && s_bins[threadIdx.x]) atomicAdd(&ctrl->bins[threadIdx.x], s_bins[threadIdx.x]);
     if (!gb.wait()) return false;
     if (load_agent_i32(a.fault) != 0) return false;              // uniform: read after the barrier
@@ -677,35 +687,57 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
         store_agent_i32(&ctrl->n_seg, acc);
     }
     if (!a.listed) {
-        // this block's first position: the counts of the blocks before it
-        __shared__ int s_base_act;
-        if (threadIdx.x == 0) s_base_act = 0;
+        // this block's first position in each class: all vertices of the
+        // classes before it, then those of the blocks before it
+        __shared__ int s_tot[kRankClasses], s_before[kRankClasses], s_off[kRankClasses];
+        if (threadIdx.x < kRankClasses) s_tot[threadIdx.x] = s_before[threadIdx.x] = 0;
         __syncthreads();
-        int o = 0;
-        for (unsigned b2 = threadIdx.x; b2 < blk; b2 += BLOCK) o += a.bcount[b2];
-        if (o) atomicAdd(&s_base_act, o);
+        for (unsigned t = threadIdx.x; t < nblk * kRankClasses; t += BLOCK) {
+            const unsigned b2 = t / kRankClasses, c = t % kRankClasses;
+            const int x = a.bcount[t];
+            if (x) {
+                atomicAdd(&s_tot[c], x);
+                if (b2 < blk) atomicAdd(&s_before[c], x);
+            }
+        }
         __syncthreads();
-        int run = s_base_act;
-        if (blk == nblk - 1 && threadIdx.x == 0) store_agent_i32(&ctrl->n_act, run + a.bcount[blk]);
+        if (threadIdx.x == 0) {
+            int acc = 0;
+            for (int c = 0; c < kRankClasses; ++c) {
+                s_off[c] = acc + s_before[c];
+                acc += s_tot[c];
+            }
+            if (blk == 0) store_agent_i32(&ctrl->n_act, acc);
+        }
+        __syncthreads();
         const int wave = threadIdx.x >> 6;
         for (long long base = id_lo; base < id_hi; base += BLOCK) {
             const long long v = base + threadIdx.x;
-            const bool act = v < id_hi && a.row_ptr[v + 1] != a.row_ptr[v];
-            const unsigned long long bal = __ballot(act);
-            const int before = __popcll(bal & ((1ull << lane) - 1ull));
-            if (lane == 0) s_act[wave] = __popcll(bal);
+            const int cls = v < id_hi ? rank_class(v) : -1;
+            int before = 0;
+#pragma unroll
+            for (int c = 0; c < kRankClasses; ++c) {
+                const unsigned long long bal = __ballot(cls == c);
+                if (cls == c) before = __popcll(bal & ((1ull << lane) - 1ull));
+                if (lane == 0) s_act[wave][c] = __popcll(bal);
+            }
             __syncthreads();
-            int woff = 0, tot = 0;
-            for (int w2 = 0; w2 < BLOCK / 64; ++w2) {
-                if (w2 < wave) woff += s_act[w2];
-                tot += s_act[w2];
-            }
             if (v < id_hi) {
-                const int pos = run + woff + before;
-                a.iperm[v] = act ? pos : -1;
-                if (act) a.perm[pos] = static_cast<int32_t>(v);
+                int pos = -1;
+                if (cls >= 0) {
+                    int woff = 0;
+                    for (int w2 = 0; w2 < wave; ++w2) woff += s_act[w2][cls];
+                    pos = s_off[cls] + woff + before;
+                    a.perm[pos] = static_cast<int32_t>(v);
+                }
+                a.iperm[v] = pos;
             }
-            run += tot;
+            __syncthreads();
+            if (threadIdx.x < kRankClasses) {
+                int tot = 0;
+                for (int w2 = 0; w2 < BLOCK / 64; ++w2) tot += s_act[w2][threadIdx.x];
+                s_off[threadIdx.x] += tot;
+            }
             __syncthreads();
         }
     }
@@ -1384,7 +1416,7 @@ size_t workspace_bytes(int32_t n, int64_t nnz, int nw, int grid_cap) {
     b += Arena::round(static_cast<size_t>(n) * sizeof(uint32_t));    // probe component membership
     b += Arena::round(static_cast<size_t>(grid_cap) * 2 * 64 * nw * sizeof(int64_t));  // per-source partials
     b += 2 * Arena::round(static_cast<size_t>(n) * sizeof(int32_t));   // perm, iperm
-    b += Arena::round(static_cast<size_t>(grid_cap) * sizeof(int32_t)); // per-block counts
+    b += Arena::round(static_cast<size_t>(grid_cap) * kRankClasses * sizeof(int32_t)); // per-block class counts
     return b;
 }
 
@@ -1425,7 +1457,7 @@ hln_status fill_args(BfsArgs& a, const hln_csr* g, const int32_t* sources, int32
     a.part = ar.take<int64_t>(static_cast<size_t>(grid_cap) * 2 * 64 * nw);
     a.perm = ar.take<int32_t>(n);
     a.iperm = ar.take<int32_t>(n);
-    a.bcount = ar.take<int32_t>(grid_cap);
+    a.bcount = ar.take<int32_t>(static_cast<size_t>(grid_cap) * kRankClasses);
     a.S = S;
     a.R = R;
     a.H2 = h2;

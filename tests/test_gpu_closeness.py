@@ -149,7 +149,8 @@ def test_config2_full_size_sampled():
 def test_levels_per_batch(width):
     """The kernel's per-batch level count is 1 + the largest eccentricity of
     the batch's sources (the L_b of the byte model), from the oracle; the
-    all-source batches take the vertices that have arcs, in id order."""
+    all-source batches take the vertices that have arcs, largest degree class
+    first, ids ascending inside a class."""
     h = C.config1()
     n = h.n
     for rp, ci in [csr_np(n, *h.layers[0]), O.compose("and", [csr_np(n, *e) for e in h.layers])]:
@@ -159,8 +160,12 @@ def test_levels_per_batch(width):
         P.hln_closeness_layer(g, width_bits=width, levels=lv)
         torch.cuda.synchronize()
         _, _, _, ecc, _ = O.bfs_sums(rp, ci, extras=True)
-        # the batches run over the vertices that have arcs, in id order
-        act = np.nonzero(np.diff(rp))[0]
+        # the batches run over the vertices that have arcs: by degree class
+        # (rows longer than 64 arcs, then 32-64, 16-31, ..., 1), ids ascending
+        deg = np.diff(rp)
+        act = np.nonzero(deg)[0]
+        cls = np.where(deg[act] > 64, 0, 7 - np.floor(np.log2(np.maximum(deg[act], 1))).astype(np.int64))
+        act = act[np.lexsort((act, cls))]
         na = (len(act) + width - 1) // width
         ref = [1 + int(ecc[act[b * width:(b + 1) * width]].max()) for b in range(na)] + [0] * (nb - na)
         assert lv.cpu().numpy().tolist() == ref
