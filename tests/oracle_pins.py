@@ -197,6 +197,78 @@ def pin_networkx(o):
         assert np.array_equal(cc.view(np.int64), ref.view(np.int64)), (trial, cc, ref)
 
 
+def pin_networkx_config1(o):
+    """Closeness bit-identical to networkx.closeness_centrality on every
+    graph of the small three-layer HoMLN (1,000 vertices): its layers and
+    their AND and OR aggregates (Sec. 3.1), the aggregates built here with
+    Python set algebra.  The AND graph has hundreds of components, so the
+    Wasserman-Faust form (Sec. 4) is exercised throughout."""
+    import networkx as nx
+    from homln_inputs import configs as C
+    h = C.config1()
+    n = h.n
+    sets = [{(min(a, b), max(a, b)) for a, b in zip(eu.tolist(), ev.tolist()) if a != b} for eu, ev in h.layers]
+    graphs = [(eu, ev) for eu, ev in h.layers]
+    for agg in (set.intersection(*sets), set.union(*sets)):
+        pairs = sorted(agg)
+        graphs.append((np.array([a for a, _ in pairs], np.int64), np.array([b for _, b in pairs], np.int64)))
+    for gi, (eu, ev) in enumerate(graphs):
+        g = nx.Graph()
+        g.add_nodes_from(range(n))
+        g.add_edges_from(zip(np.asarray(eu).tolist(), np.asarray(ev).tolist()))
+        ref = nx.closeness_centrality(g)
+        ref = np.array([ref[i] for i in range(n)], np.float64)
+        rp, ci = csr_of(o, n, eu, ev)
+        S, R = o.bfs_sums(rp, ci)
+        cc = o.closeness_wf(n, S, R)
+        bad = np.nonzero(cc.view(np.int64) != ref.view(np.int64))[0]
+        assert len(bad) == 0, (gi, bad[:10])
+
+
+def pin_cc2_score(o):
+    """CC2's score (n-1)/est (Sec. 5.2, then Eq. 1) by two routes that do
+    not use the oracle's closeness: with identical connected layers the
+    estimate is the exact distance sum, so the score equals NetworkX's
+    closeness bit for bit (Sec. 4: the decoupled method is exact when the
+    layers agree); on arbitrary layers it equals (n-1)/P with P taken from
+    Floyd-Warshall distances, unreachable vertices at distance n (Sec. 5.1),
+    the largest over the layers (one IEEE division)."""
+    import networkx as nx
+    rng = np.random.default_rng(31)
+    for trial in range(12):
+        n = int(rng.integers(3, 45))
+        # a connected layer: a random spanning tree plus random edges
+        par = [int(rng.integers(0, i)) for i in range(1, n)]
+        eu = np.arange(1, n, dtype=np.int64)
+        ev = np.array(par, np.int64)
+        xu, xv = random_graph(rng, n, 0.08)
+        eu, ev = np.concatenate([eu, xu]), np.concatenate([ev, xv])
+        adj = adjacency_sets(n, eu, ev)
+        ref = nx.closeness_centrality(nx_graph(n, adj))
+        ref = np.array([ref[i] for i in range(n)], np.float64)
+        S, R = o.bfs_sums(*csr_of(o, n, eu, ev))
+        r = int(rng.integers(1, 4))
+        est = o.cc2_est(n, [S] * r, [R] * r)
+        sc = o.cc2_score(n, est)
+        assert np.array_equal(sc.view(np.int64), ref.view(np.int64)), (trial, sc, ref)
+    for trial in range(12):
+        n = int(rng.integers(2, 40))
+        r = int(rng.integers(2, 4))
+        Ps, Ss, Rs = [], [], []
+        for _l in range(r):
+            u, v = random_graph(rng, n, float(rng.choice([0.04, 0.1])))
+            adj = adjacency_sets(n, u, v)
+            D = floyd_warshall(n, adj)
+            Ps.append([int(np.where(np.isinf(D[x]), n, D[x]).sum()) for x in range(n)])
+            S, R = o.bfs_sums(*csr_of(o, n, u, v))
+            Ss.append(S)
+            Rs.append(R)
+        P = np.array(Ps, np.int64).max(0)
+        sc = o.cc2_score(n, o.cc2_est(n, Ss, Rs))
+        ref = np.array([(n - 1) / int(p) if p > 0 else 0.0 for p in P.tolist()], np.float64)
+        assert np.array_equal(sc.view(np.int64), ref.view(np.int64)), (trial, sc, ref)
+
+
 def pin_networkx_printed(o):
     """Values NetworkX prints for P5 and K1,4 (stored fixture)."""
     with open(os.path.join(GOLDEN, "networkx_closeness_small.txt")) as f:
@@ -352,8 +424,6 @@ def pin_cc2_bounds(o):
         assert np.all(o.penalised(n, So, Ro) <= Ps.min(0))
         est_same = o.cc2_est(n, [sums[0][0]] * 2, [sums[0][1]] * 2)
         assert np.array_equal(est_same, o.penalised(n, *sums[0]))
-        sc = o.cc2_score(n, est)
-        assert np.array_equal(sc, (n - 1) / est.astype(np.float64))
 
 
 def pin_naive(o):
@@ -565,4 +635,4 @@ PINS = [pin_closed_forms, pin_disjoint_union, pin_floyd_warshall, pin_networkx, 
         pin_wiener_tree, pin_csr_normalisation, pin_compose_sets, pin_mean_exact, pin_above_mean,
         pin_topk, pin_cc2_worked_example, pin_cc2_bounds, pin_naive, pin_sample_sums,
         pin_sample_estimate_full_sample, pin_sample_estimate_bound, pin_cc1_brute_force, pin_cc1_vertex_transitive,
-        pin_cc1_properties]
+        pin_cc1_properties, pin_cc2_score, pin_networkx_config1]

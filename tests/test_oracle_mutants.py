@@ -33,6 +33,10 @@ MUTANTS = [
     ("topk-ascending", "if (x->s != y->s) return x->s > y->s ? -1 : 1;",
      "if (x->s != y->s) return x->s < y->s ? -1 : 1;"),
     ("cc2-min", "if (l == 0 || p > best) best = p;", "if (l == 0 || p < best) best = p;"),
+    ("cc2-score-n", "score[u] = est[u] > 0 ? (double)(n - 1) / (double)est[u] : 0.0;",
+     "score[u] = est[u] > 0 ? (double)n / (double)est[u] : 0.0;"),
+    ("cc2-score-wf", "score[u] = est[u] > 0 ? (double)(n - 1) / (double)est[u] : 0.0;",
+     "score[u] = est[u] > 0 ? ((double)(n - 1) / (double)est[u]) * ((double)(n - 1) / (double)n) : 0.0;"),
     ("cc2-unpenalised", "int64_t p = S[l][u] + (int64_t)n * (int64_t)(n - R[l][u]);", "int64_t p = S[l][u];"),
     ("naive-union", "in[u] = in[u] && keep[u];", "in[u] = (l == 0) ? keep[u] : (in[u] || keep[u]);"),
     ("sample-self-counted", "int32_t q = RQ[v] - self;", "int32_t q = RQ[v];"),
@@ -67,11 +71,13 @@ def test_mutant_is_caught(workdir, name, old, new):
     subprocess.check_call(["gcc", *O._CFLAGS, "-w", "-o", path_so, path_c])
     variant = O.Variant(path_so)
     caught = []
-    for pin in PINS:
+    for pin in PINS:               # the first pin that catches it is enough
         try:
             pin(variant)
         except AssertionError:
             caught.append(pin.__name__)
         except Exception as e:  # a crash in a pin also counts as detection
             caught.append("%s(%s)" % (pin.__name__, type(e).__name__))
+        if caught:
+            break
     assert caught, "planted mistake %s passed every pin" % name
