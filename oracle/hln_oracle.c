@@ -380,6 +380,25 @@ int32_t oracle_naive(int32_t n, int32_t r, const double* const* cc, int32_t* ids
     return c;
 }
 
+/* Naive composition (Sec. 4) applied to top-k sets: the intersection of
+ * the layers' top-k CC-node sets, each by the layer's own closeness (score
+ * descending, ties by ascending id).  ids ascending; returns how many (at
+ * most k). */
+int32_t oracle_naive_topk(int32_t n, int32_t r, const double* const* cc, int32_t k, int32_t* ids) {
+    int32_t* hits = (int32_t*)calloc((size_t)n + 1, sizeof(int32_t));
+    int32_t* top = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
+    if (!hits || !top) { free(hits); free(top); return -2; }
+    for (int32_t l = 0; l < r; ++l) {
+        int32_t c = oracle_topk_desc(n, cc[l], k, top);
+        if (c < 0) { free(hits); free(top); return c; }
+        for (int32_t i = 0; i < c; ++i) hits[top[i]] += 1;
+    }
+    int32_t c = 0;
+    for (int32_t u = 0; u < n; ++u) if (hits[u] == r) ids[c++] = u;
+    free(hits); free(top);
+    return c;
+}
+
 /* ------------------------------------------------------------------ */
 /* Closeness of every vertex estimated from a sample of sources (after  */
 /* Eppstein and Wang's sampling estimator of closeness, the linear-time */

@@ -66,6 +66,8 @@ def _bind(path: str):
     L.oracle_cc2_score.restype = None
     L.oracle_naive.argtypes = [i32, i32, P, P]
     L.oracle_naive.restype = i32
+    L.oracle_naive_topk.argtypes = [i32, i32, P, i32, P]
+    L.oracle_naive_topk.restype = i32
     L.oracle_sample_sums.argtypes = [i32, P, P, i32, P, P, P]
     L.oracle_sample_sums.restype = ctypes.c_int
     L.oracle_sample_sums_at.argtypes = [i32, P, P, P, i32, P, P, P]
@@ -265,6 +267,19 @@ def naive(n: int, cc_list):
     c = L.oracle_naive(n, r, ctypes.cast(arr, ctypes.c_void_p), _p(ids))
     if c < 0:
         raise ValueError("oracle_naive failed")
+    return ids[:c].copy()
+
+
+def naive_topk(n: int, cc_list, k: int):
+    """Intersection of the layers' top-k sets (ids ascending)."""
+    L = _load()
+    r = len(cc_list)
+    ccs = [_c(c, np.float64) for c in cc_list]
+    arr = (ctypes.c_void_p * r)(*[a.ctypes.data for a in ccs])
+    ids = np.zeros(max(n, 1), np.int32)
+    c = L.oracle_naive_topk(n, r, ctypes.cast(arr, ctypes.c_void_p), k, _p(ids))
+    if c < 0:
+        raise ValueError("oracle_naive_topk failed")
     return ids[:c].copy()
 
 

@@ -443,6 +443,24 @@ def pin_naive(o):
         assert o.naive(n, [ccs[0], ccs[0]]).tolist() == o.above_mean(ccs[0]).tolist()
 
 
+def pin_naive_topk(o):
+    """Naive composition of top-k sets: the intersection of the layers'
+    top-k sets (brute force: sort each layer by (-score, id), cut at k,
+    intersect); identical layers give that layer's top k; k = n keeps every
+    vertex, k = 0 none."""
+    rng = np.random.default_rng(31)
+    for _ in range(25):
+        n = int(rng.integers(1, 120))
+        r = int(rng.integers(1, 5))
+        ccs = [rng.integers(0, 7, size=n).astype(np.float64) / 5.0 for _l in range(r)]
+        k = int(rng.integers(0, n + 1))
+        tops = [set(sorted(range(n), key=lambda i, c=c: (-c[i], i))[:k]) for c in ccs]
+        assert o.naive_topk(n, ccs, k).tolist() == sorted(set.intersection(*tops))
+        assert o.naive_topk(n, [ccs[0], ccs[0]], k).tolist() == sorted(o.topk_desc(ccs[0], k).tolist())
+        assert o.naive_topk(n, ccs, n).tolist() == list(range(n))
+        assert o.naive_topk(n, ccs, 0).tolist() == []
+
+
 def pin_sample_sums(o):
     """Sample sums against Floyd-Warshall (sum and count over the sampled
     rows of each column), both the per-source and the per-vertex routes."""
@@ -635,4 +653,4 @@ PINS = [pin_closed_forms, pin_disjoint_union, pin_floyd_warshall, pin_networkx, 
         pin_wiener_tree, pin_csr_normalisation, pin_compose_sets, pin_mean_exact, pin_above_mean,
         pin_topk, pin_cc2_worked_example, pin_cc2_bounds, pin_naive, pin_sample_sums,
         pin_sample_estimate_full_sample, pin_sample_estimate_bound, pin_cc1_brute_force, pin_cc1_vertex_transitive,
-        pin_cc1_properties, pin_cc2_score, pin_networkx_config1]
+        pin_cc1_properties, pin_cc2_score, pin_networkx_config1, pin_naive_topk]

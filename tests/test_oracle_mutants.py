@@ -39,6 +39,10 @@ MUTANTS = [
      "score[u] = est[u] > 0 ? ((double)(n - 1) / (double)est[u]) * ((double)(n - 1) / (double)n) : 0.0;"),
     ("cc2-unpenalised", "int64_t p = S[l][u] + (int64_t)n * (int64_t)(n - R[l][u]);", "int64_t p = S[l][u];"),
     ("naive-union", "in[u] = in[u] && keep[u];", "in[u] = (l == 0) ? keep[u] : (in[u] || keep[u]);"),
+    ("naive-topk-any-layer", "for (int32_t u = 0; u < n; ++u) if (hits[u] == r) ids[c++] = u;",
+     "for (int32_t u = 0; u < n; ++u) if (hits[u] >= 1) ids[c++] = u;"),
+    ("naive-topk-k-plus-1", "int32_t c = oracle_topk_desc(n, cc[l], k, top);",
+     "int32_t c = oracle_topk_desc(n, cc[l], k + 1, top);"),
     ("sample-self-counted", "int32_t q = RQ[v] - self;", "int32_t q = RQ[v];"),
     ("sample-population-n", "double c = (double)(n_pop - 1) / (double)(n - 1);", "double c = 1.0;"),
     ("sample-sums-off-by-one", "SQ[u] += dist[u];", "SQ[u] += dist[u] + 1;"),
