@@ -93,6 +93,37 @@ int32_t hln_device_cu_count(void);
  * library's kernels since the last call (HLN_EDEVICE), else HLN_OK. */
 hln_status hln_device_status(void* stream);
 
+/* Co-residency of the persistent closeness kernels.  Their level loop
+ * separates levels with grid barriers, so every block of a launch must be
+ * resident at once.  The grid is held to `bound` blocks per compute unit:
+ * the smaller of the runtime's occupancy answer and what the kernel's own
+ * resources allow on CDNA4 (4 SIMDs per compute unit with 512 VGPRs per lane
+ * each, allocated in granules of 8, at most 8 waves per SIMD; 160 KB of LDS
+ * per compute unit in granules of 512 bytes; a block of B threads takes
+ * ceil(ceil(B/64)/4) wave slots on every SIMD).
+ * hln_resident_blocks: that resource bound for a kernel using `vgprs` VGPRs
+ *   per lane and `lds_bytes` of LDS per block of `block_threads` threads
+ *   (pure arithmetic, no device needed; 0 for invalid arguments).
+ * hln_closeness_kernel_residency: info [host] 5 int32 for the kernel that
+ *   hln_closeness_layer (mode 0: all-source or per-vertex sums; 1: listed
+ *   sources with per-source sums) or hln_closeness_batch (the multi-graph
+ *   kernel, block 1024, widths 512-4096; mode 2: all sources, 3: listed
+ *   sources) runs at `width_bits`
+ *   with blocks of 256, 512 or 1024 threads: VGPRs per lane, static LDS
+ *   bytes per block, scratch bytes per lane (hipFuncGetAttributes), the
+ *   runtime's occupancy answer, and the bound used.
+ * The environment variable HLN_BLOCKS_PER_CU may lower the blocks per
+ * compute unit of these launches; a value above the bound makes the launch
+ * fail with HLN_EUNSUPPORTED.
+ * hln_last_launch_path: how this thread's last persistent launch went out:
+ *   0 none yet, 1 a cooperative launch, 2 an ordinary kernel node inside a
+ *   stream capture where the runtime refused the cooperative one (the same
+ *   grid, within the bound; every wait in the kernel is bounded, so a grid
+ *   that did not all start would report fault code 1 instead of hanging). */
+int32_t hln_resident_blocks(int32_t vgprs, int32_t lds_bytes, int32_t block_threads);
+hln_status hln_closeness_kernel_residency(int32_t width_bits, int32_t block_threads, int32_t mode, int32_t* info);
+int32_t hln_last_launch_path(void);
+
 /* ------------------------------------------------------------------------
  * Layer ingest (Sec. 1, Problem Statement; Sec. 4: undirected layers).
  * ------------------------------------------------------------------------
@@ -229,18 +260,28 @@ hln_status hln_closeness_estimate(int32_t n, int32_t n_pop, const int32_t* sourc
  *                the distance sum with unreachable vertices at distance n
  *                (Sec. 5.1); score = (n-1)/est (Sec. 5.2, Algorithm 1, then
  *                Eq. 1); ranking by est ascending is the same order.
- * HLN_RANK_NAIVE r >= 1 layers, k must be -1: intersection of the layers'
- *                above-average CC-node sets (Sec. 4, naive composition).
+ * HLN_RANK_NAIVE r >= 1 layers: the naive composition (Sec. 4), the
+ *                intersection of the layers' CC-node sets: their above-
+ *                average sets (k = -1) or their top-k sets by each layer's
+ *                closeness, ties by ascending id (k >= 0).  Either way ids
+ *                ascending, score 0.0, count = the intersection's size
+ *                (at most k when k >= 0).
  * S, R [host] arrays of r device pointers to the layers' all-source outputs
  * of hln_closeness_layer (n entries each).
- * k >= 0: ids [dev] the k best vertices (score descending, ties by
- *   ascending id, Sec. 5.2 "top-k"), score [dev, nullable] their scores.
+ * k >= 0 (HLN_RANK_WF, HLN_RANK_CC2): ids [dev] the k best vertices (score
+ *   descending, ties by ascending id, Sec. 5.2 "top-k"), score [dev,
+ *   nullable] their scores.  mode | HLN_TOPK_SET: the same k vertices and
+ *   scores in ascending id order (the top-k as a set).  HLN_RANK_NAIVE with k >= 0: see above; ids and
+ *   score need room for k entries.
  * k = -1: every vertex whose score is >= the mean score (Sec. 4: "same or
  *   above average"), ids ascending; the mean is the sum over ids taken
  *   sequentially in chunks of 1024, chunk sums added in order, divided by n.
  *   ids and score need room for n entries.
  * count [dev] int32: number of ids written.  0 <= k <= n or k = -1. */
 typedef enum { HLN_RANK_WF = 0, HLN_RANK_CC2 = 1, HLN_RANK_NAIVE = 2 } hln_rank_mode;
+/* Flag OR-ed into a top-k mode (hln_compose_cc_topk) or score dtype
+ * (hln_topk): return the k best as ascending ids instead of rank order. */
+#define HLN_TOPK_SET 0x100
 size_t hln_compose_cc_topk_workspace_size(int32_t n);
 hln_status hln_compose_cc_topk(int32_t mode, int32_t n, int32_t r, const int64_t* const* S, const int32_t* const* R,
                                int32_t k, int32_t* ids, double* score, int32_t* count,
@@ -295,56 +336,80 @@ hln_status hln_compose_cc1(const hln_csr* layers, int32_t r, const int64_t* cons
 
 /* ------------------------------------------------------------------------
  * Batched closeness of many graphs (Sec. 3: every layer is analysed
- * independently and in parallel; the layers and AND / OR aggregates of many
- * HoMLNs in one persistent launch per source-width class).
+ * independently and in parallel; the Problem Statement, Sec. 1: the layers
+ * and any aggregates of many HoMLNs, each with all of its vertices or a
+ * list of them as sources, through one persistent launch per source-width
+ * class and accumulation mode).
  * ------------------------------------------------------------------------
  * A plan is an opaque host object: tuned source widths per graph-size class,
  * pinned staging for the per-call descriptors, and optionally one captured
  * hipGraph of a whole batch.  Plans are not thread-safe; destroy with
  * hln_plan_destroy (waits for its staging copies).
- * Graphs with n <= 65535 can run as LDS tiles (one workgroup keeps the
- * frontier, next and visited bitsets of the whole graph in LDS); larger
- * graphs, and graphs the tuner assigns to it, run through the persistent
- * kernel inside the same call: one cooperative launch per width, its grid
- * cut into partitions (4 by default) that run different graphs at once.
- * S[g], R[g], cc[g], h2[g]: host arrays of n_graphs device pointers (n_g
- * entries each); cc and h2 (arrays or entries) nullable.  Every source of
- * every graph is used; outputs as hln_closeness_layer's all-source mode.
+ * sources [host] NULL (every graph uses all its vertices as sources; n_src
+ *   may be NULL) or an array of n_graphs device pointers read with n_src
+ *   [host] n_graphs int32: n_src[g] = -1 for all of graph g's vertices
+ *   (sources[g] is not read), else 0 <= n_src[g] <= n distinct vertex ids
+ *   of graph g at sources[g] (NULL allowed when n_src[g] = 0; ids outside
+ *   [0, n) are a device-side fault).  The count decides, not the pointer.
+ * S[g], R[g], cc[g], h2[g]: host arrays of n_graphs device pointers.  All-
+ *   source graphs: n_g entries indexed by vertex, as hln_closeness_layer's
+ *   all-source mode.  Listed graphs: n_src[g] entries indexed by position
+ *   in sources[g], as hln_closeness_layer with listed sources; h2[g] must be
+ *   NULL (HLN_EUNSUPPORTED); n_src[g] = 0 writes nothing.  cc and h2 (arrays
+ *   or entries) nullable.
+ * All-source graphs with n <= 65535 can run as LDS tiles (one workgroup
+ * keeps the frontier, next and visited bitsets of the whole graph in LDS);
+ * larger graphs, graphs the tuner assigns to it and every listed graph run
+ * through the persistent kernel inside the same call: one cooperative launch
+ * per (width, mode), its grid cut into partitions (up to 4; one when a graph
+ * of the launch has more than 65,536 vertices) that run different graphs at
+ * once.  A listed graph takes its size class's tuned persistent width, else
+ * the narrowest of 512, 1024, 2048, 4096 holding all its sources.
  * hln_plan_tune times, for each log2(n) class present, the class's largest
  * graph with every LDS tile width that fits (64/32/16/8 bits per vertex)
  * and with the persistent kernel at 1024, 2048 and 4096 sources, and keeps
  * the fastest; it synchronises `stream` and overwrites that graph's S and
- * R.  hln_plan_width reports the width a graph of n vertices gets (untuned:
- * the widest fitting tile, else 4096).  hln_plan_set_width sets the choice
- * of n's log2 class by hand (a tuned plan saved and restored, or two plans
- * made to agree): 8, 16, 32 or 64 for LDS tiles (narrowed to the widest
- * that fits a graph, the persistent kernel at 4096 where none does), 512,
- * 1024, 2048 or 4096 for the persistent kernel, 0 for the untuned default;
- * any other width is HLN_EINVAL and changes nothing.
+ * R.  hln_plan_width reports the width an all-source graph of n vertices
+ * gets (untuned: the widest fitting tile, else 4096).  hln_plan_set_width
+ * sets the choice of n's log2 class by hand (a tuned plan saved and
+ * restored, or two plans made to agree): 8, 16, 32 or 64 for LDS tiles
+ * (narrowed to the widest that fits a graph, the persistent kernel at 4096
+ * where none does), 512, 1024, 2048 or 4096 for the persistent kernel, 0
+ * for the untuned default; any other width is HLN_EINVAL and changes
+ * nothing.
  * hln_plan_capture records the whole batch (staging copy, preparation,
  * tile launches, closeness pass) into a hipGraph owned by the plan, which
  * hln_plan_replay launches on `stream`; the captured buffers must stay
  * valid while replays are possible.  Capture needs a non-null stream.
  * hln_closeness_batch may also be called while the caller captures
  * `stream` into a graph of its own: call hln_plan_reserve for the same
- * graphs before that capture (it allocates the staging that the captured
- * copy reads; one such capture per plan). */
+ * graphs before each such capture.  It sets aside the pinned staging that
+ * the captured copy reads at every replay; the capture keeps that buffer
+ * until the plan is destroyed, so graphs captured earlier stay valid.  A
+ * capture without a reserved buffer is HLN_EINVAL. */
 typedef struct hln_plan hln_plan;
 hln_status hln_plan_create(hln_plan** plan);
 void hln_plan_destroy(hln_plan* plan);
 int32_t hln_plan_width(const hln_plan* plan, int32_t n);
 hln_status hln_plan_set_width(hln_plan* plan, int32_t n, int32_t width);
 size_t hln_closeness_batch_workspace_size(const hln_plan* plan, const hln_csr* graphs, int32_t n_graphs);
-hln_status hln_closeness_batch(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs, int64_t* const* S,
+hln_status hln_closeness_batch(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs,
+                               const int32_t* const* sources, const int32_t* n_src, int64_t* const* S,
                                int32_t* const* R, double* const* cc, int32_t* const* h2,
                                void* workspace, size_t workspace_bytes, void* stream);
 hln_status hln_plan_tune(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs, int64_t* const* S,
                          int32_t* const* R, void* workspace, size_t workspace_bytes, void* stream);
-hln_status hln_plan_capture(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs, int64_t* const* S,
+hln_status hln_plan_capture(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs,
+                            const int32_t* const* sources, const int32_t* n_src, int64_t* const* S,
                             int32_t* const* R, double* const* cc, int32_t* const* h2,
                             void* workspace, size_t workspace_bytes, void* stream);
 hln_status hln_plan_reserve(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs);
 hln_status hln_plan_replay(hln_plan* plan, void* stream);
+/* Persistent launches of the plan's last enqueue (hln_closeness_batch,
+ * hln_plan_capture or a tuning run): how many went out as cooperative
+ * launches and how many as ordinary kernel nodes inside a stream capture
+ * (see hln_last_launch_path).  cooperative, ordinary [host]. */
+hln_status hln_plan_launch_paths(const hln_plan* plan, int32_t* cooperative, int32_t* ordinary);
 
 /* ------------------------------------------------------------------------
  * Learned candidate proposer (not in the paper; its inputs are the Psi
@@ -371,7 +436,9 @@ hln_status hln_plan_replay(hln_plan* plan, void* stream);
  *   before the step.  Deterministic (block partials summed in order).
  * hln_topk: ids [dev] of the k largest scores (float64 dtype 0, float32
  *   dtype 1), descending, ties by ascending index; -0.0 ties with +0.0;
- *   scores must not be NaN.  0 <= k <= n.
+ *   scores must not be NaN.  0 <= k <= n.  dtype | HLN_TOPK_SET: the same k
+ *   ids written in ascending order (a candidate set whose later ranking
+ *   breaks ties by position then breaks them by vertex id).
  * hln_rank_labels: label [dev] float[n] = log((n+1)/(g+1)) / log(n+1)
  *   with g the number of vertices with a strictly larger score (computed in
  *   double, rounded to float): the log-rank the proposer is trained to

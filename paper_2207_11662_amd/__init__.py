@@ -9,5 +9,5 @@ from ._lib import (  # noqa: F401
     hln_csr_validate, hln_compose_and, hln_compose_or, hln_compose_and_batch, AndBatch,
     hln_compose_cc_topk, hln_compose_cc_topk_batch, TopkBatch, hln_compose_cc1, Plan,
     mlp_param_count, hln_proposer_features, hln_mlp_init, hln_mlp_forward, hln_mlp_train_step, hln_topk,
-    hln_rank_labels,
+    hln_rank_labels, closeness_kernel_residency, last_launch_path, HLN_TOPK_SET,
 )

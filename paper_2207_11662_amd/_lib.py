@@ -21,6 +21,7 @@ _STATUS = {0: "HLN_OK", 1: "HLN_EINVAL", 2: "HLN_ENOMEM", 3: "HLN_EDEVICE", 4: "
 # every symbol include/hln.h declares (checked by the tests)
 EXPORTS = [
     "hln_last_error", "hln_version", "hln_device_cu_count", "hln_device_status",
+    "hln_resident_blocks", "hln_closeness_kernel_residency", "hln_last_launch_path", "hln_plan_launch_paths",
     "hln_csr_from_edges_workspace_size", "hln_csr_from_edges", "hln_csr_from_edges_batch_workspace_size",
     "hln_csr_from_edges_batch", "hln_csr_validate",
     "hln_compose_workspace_size", "hln_compose_and", "hln_compose_or", "hln_compose_and_batch_workspace_size",
@@ -90,6 +91,10 @@ def lib():
         "hln_version": ([], i32),
         "hln_device_cu_count": ([], i32),
         "hln_device_status": ([P], st),
+        "hln_resident_blocks": ([i32, i32, i32], i32),
+        "hln_closeness_kernel_residency": ([i32, i32, i32, P], st),
+        "hln_last_launch_path": ([], i32),
+        "hln_plan_launch_paths": ([P, P, P], st),
         "hln_csr_from_edges_workspace_size": ([i32, i64], sz),
         "hln_csr_from_edges": ([i32, i64, P, P, P, P, P, sz, P], st),
         "hln_csr_from_edges_batch_workspace_size": ([ctypes.POINTER(hln_edge_list), i32], sz),
@@ -114,9 +119,9 @@ def lib():
         "hln_plan_width": ([P, i32], i32),
         "hln_plan_set_width": ([P, i32, i32], st),
         "hln_closeness_batch_workspace_size": ([P, csr_p, i32], sz),
-        "hln_closeness_batch": ([P, csr_p, i32, P, P, P, P, P, sz, P], st),
+        "hln_closeness_batch": ([P, csr_p, i32, P, P, P, P, P, P, P, sz, P], st),
         "hln_plan_tune": ([P, csr_p, i32, P, P, P, sz, P], st),
-        "hln_plan_capture": ([P, csr_p, i32, P, P, P, P, P, sz, P], st),
+        "hln_plan_capture": ([P, csr_p, i32, P, P, P, P, P, P, P, sz, P], st),
         "hln_plan_replay": ([P, P], st),
         "hln_plan_reserve": ([P, csr_p, i32], st),
         "hln_mlp_param_count": ([], i32),
@@ -533,6 +538,35 @@ class Plan:
         h2 = _ptr_array([o.get("h2") for o in outs]) if any(o.get("h2") is not None for o in outs) else None
         return arr, S, R, cc, h2
 
+    @staticmethod
+    def _sources(graphs, sources):
+        """(pointer array, n_src array) for per-graph listed sources (None
+        entries: all of that graph's vertices), or (None, None)."""
+        if sources is None or all(s is None for s in sources):
+            return None, None
+        assert len(sources) == len(graphs)
+        for s in sources:
+            if s is not None:
+                assert s.dtype == torch.int32 and s.is_cuda and s.is_contiguous()
+        ptrs = _ptr_array(sources)
+        # -1: all of the graph's vertices; an empty list (whose data pointer
+        # may be NULL) is 0 listed sources
+        counts = (ctypes.c_int32 * len(graphs))(*[-1 if s is None else int(s.numel()) for s in sources])
+        return ptrs, counts
+
+    @staticmethod
+    def outputs_listed(graphs, sources):
+        """Outputs of a call with listed sources: per listed graph S, R, cc
+        indexed by list position; per all-source graph as outputs()."""
+        out = []
+        for g, s in zip(graphs, sources):
+            k = g.n if s is None else int(s.numel())
+            dev = g.row_ptr.device
+            out.append({"S": torch.empty(max(k, 1), dtype=torch.int64, device=dev),
+                        "R": torch.empty(max(k, 1), dtype=torch.int32, device=dev),
+                        "cc": torch.empty(max(k, 1), dtype=torch.float64, device=dev), "h2": None})
+        return out
+
     def workspace_size(self, graphs) -> int:
         arr = _layers_c(graphs)
         return int(lib().hln_closeness_batch_workspace_size(self.h, arr, len(graphs)))
@@ -548,12 +582,15 @@ class Plan:
                         "h2": torch.empty(g.n, dtype=torch.int32, device=dev) if want_h2 else None})
         return out
 
-    def run(self, graphs, outs, ws=None, stream=None):
+    def run(self, graphs, outs, ws=None, stream=None, sources=None):
+        """hln_closeness_batch; sources: None, or one int32 device tensor of
+        listed source ids (or None for all vertices) per graph."""
         arr, S, R, cc, h2 = self._args(graphs, outs)
+        src, cnt = self._sources(graphs, sources)
         need = self.workspace_size(graphs)
         if ws is None or ws.numel() < need:
             ws = workspace(need, graphs[0].row_ptr.device)
-        check(lib().hln_closeness_batch(self.h, arr, len(graphs), S, R, cc, h2, _ptr(ws), ws.numel(),
+        check(lib().hln_closeness_batch(self.h, arr, len(graphs), src, cnt, S, R, cc, h2, _ptr(ws), ws.numel(),
                                         _stream(stream)))
         return ws
 
@@ -564,10 +601,11 @@ class Plan:
             ws = workspace(need, graphs[0].row_ptr.device)
         check(lib().hln_plan_tune(self.h, arr, len(graphs), S, R, _ptr(ws), ws.numel(), _stream(stream)))
 
-    def capture(self, graphs, outs, ws, stream):
+    def capture(self, graphs, outs, ws, stream, sources=None):
         arr, S, R, cc, h2 = self._args(graphs, outs)
-        self._keep = (graphs, outs, ws)       # captured buffers must outlive replays
-        check(lib().hln_plan_capture(self.h, arr, len(graphs), S, R, cc, h2, _ptr(ws), ws.numel(),
+        src, cnt = self._sources(graphs, sources)
+        self._keep = (graphs, outs, ws, sources)       # captured buffers must outlive replays
+        check(lib().hln_plan_capture(self.h, arr, len(graphs), src, cnt, S, R, cc, h2, _ptr(ws), ws.numel(),
                                      _stream(stream)))
 
     def reserve(self, graphs):
@@ -577,6 +615,25 @@ class Plan:
 
     def replay(self, stream=None):
         check(lib().hln_plan_replay(self.h, _stream(stream)))
+
+    def launch_paths(self):
+        """(cooperative, ordinary-in-capture) persistent launches of the
+        plan's last enqueue."""
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().hln_plan_launch_paths(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+
+def closeness_kernel_residency(width_bits: int, block: int, mode: int) -> dict:
+    """Registers, LDS, scratch, the runtime's occupancy answer and the
+    co-residency bound of one persistent closeness kernel (needs a GPU)."""
+    info = (ctypes.c_int32 * 5)()
+    check(lib().hln_closeness_kernel_residency(width_bits, block, mode, info))
+    return dict(zip(("vgprs", "lds", "scratch", "query", "bound"), list(info)))
+
+
+def last_launch_path() -> int:
+    return int(lib().hln_last_launch_path())
 
 
 # ---------------------------------------------------------------------------
@@ -622,11 +679,14 @@ def hln_mlp_train_step(params, m, v, step: int, lr: float, X, target, loss=None,
     return ws
 
 
-def hln_topk(score: torch.Tensor, k: int, ids=None, ws=None, stream=None) -> torch.Tensor:
+HLN_TOPK_SET = 0x100
+
+
+def hln_topk(score: torch.Tensor, k: int, ids=None, ws=None, stream=None, as_set: bool = False) -> torch.Tensor:
     """Indices of the k largest scores (float64 or float32), descending,
-    ties by ascending index."""
+    ties by ascending index; with `as_set` the same indices ascending."""
     n = score.numel()
-    dtype = 0 if score.dtype == torch.float64 else 1
+    dtype = (0 if score.dtype == torch.float64 else 1) | (HLN_TOPK_SET if as_set else 0)
     assert score.dtype in (torch.float64, torch.float32)
     need = int(lib().hln_topk_workspace_size(n))
     if ws is None or ws.numel() < need:

@@ -35,12 +35,23 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
+# The persistent closeness kernels' register and LDS use, as the compiler
+# reports it, is kept next to the library: the host tests check the
+# library's co-residency bound against the compiler's occupancy figures.
+RESOURCE_REPORT = os.path.join(HERE, "hln_msbfs.resource-usage.txt")
+_REPORTED = {"hln_msbfs.hip"}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    report = os.path.basename(src) in _REPORTED
+    cmd = [HIPCC, *FLAGS, *(["-Rpass-analysis=kernel-resource-usage"] if report else []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr[-6000:]))
+    if report:
+        with open(RESOURCE_REPORT, "w") as f:
+            f.write(r.stderr)
     return obj
 
 

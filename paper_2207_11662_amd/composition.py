@@ -78,8 +78,7 @@ def study_subset(n: int, layer_graphs, layer_outs, subset, k: int, plan: L.Plan,
     naive_above = _ids(L.hln_compose_cc_topk(L.HLN_RANK_NAIVE, n, Ss, Rs, -1, ws=ws))
     # naive top-k: the intersection of the layers' top-k sets (the naive rule
     # applied to top-k sets; it can hold fewer than k vertices)
-    tops = [set(cc_sets(L.HLN_RANK_WF, n, [S], [R], k, ws)[1].tolist()) for S, R in zip(Ss, Rs)]
-    naive_top = np.array(sorted(set.intersection(*tops)), dtype=np.int64)
+    naive_top = _ids(L.hln_compose_cc_topk(L.HLN_RANK_NAIVE, n, Ss, Rs, k, ws=ws))
     ids1, cnt1, _ = L.hln_compose_cc1(gs, Ss, Rs, cc1_tau)
     cc1_above = ids1[:int(cnt1.item())].cpu().numpy()
     return {"subset": list(subset), "and_arcs": int(g_and.nnz),

@@ -45,8 +45,19 @@ struct hln_plan {
     bool staged_pending = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    void* cap_pinned = nullptr;     // staging frozen into the captured graph
-    size_t cap_pinned_bytes = 0;
+    // Staging of captured calls: a capture's copy node reads its buffer at
+    // every replay, so each capture gets a buffer of its own.  `armed` is
+    // reserved for the next capture (hln_plan_reserve, or hln_plan_capture
+    // itself); a capture moves it to `own` (the plan's own graph, freed when
+    // that graph is replaced) or to `frozen` (a graph the caller captured,
+    // freed only when the plan is destroyed).
+    void* armed = nullptr;
+    size_t armed_bytes = 0;
+    void* own = nullptr;
+    std::vector<void*> frozen;
+    // persistent launches of the last enqueue (call, capture or tuning run):
+    // [1] cooperative, [2] ordinary kernel node inside a stream capture
+    int paths[3] = {0, 0, 0};
 };
 
 namespace {
@@ -316,7 +327,38 @@ int pow2_floor(int x) {
     while (p * 2 <= x) p *= 2;
     return p;
 }
-constexpr int kCoopWidths = 3;               // widths it runs: 1024, 2048, 4096
+constexpr int kCoopWidths = 4;               // widths it runs: 512, 1024, 2048, 4096
+constexpr int kCoopWidthList[kCoopWidths] = {512, 1024, 2048, 4096};
+// Graphs larger than this run on the whole grid (one partition): config 2's
+// five graphs of 10^5 vertices took 92.5 ms through one partition, 101.7 ms
+// through two and 128 ms through four (a quarter of the chip runs such a
+// graph 3.5x longer), while config 3's graphs of 10^4-5*10^4 vertices gain
+// from four.
+constexpr int kPartitionMaxN = 65536;
+
+// Width of a graph with listed sources (always the persistent kernel): its
+// size class's tuned persistent width, else the narrowest persistent width
+// holding all its sources in one batch (4096 at most).
+int listed_width(const hln_plan* plan, int n, int n_src) {
+    const int w = plan ? plan->width_for_class[log2_class(n)] : 0;
+    if (w >= 512) return w;
+    int x = 512;
+    while (x < 4096 && x < n_src) x *= 2;
+    return x;
+}
+
+// Graph g of a call takes a list of sources when the call has a source
+// table and n_src[g] >= 0 (-1: all of its vertices).  The count, not the
+// pointer, decides: an empty list may come with a NULL pointer.
+bool is_listed(const int32_t* const* sources, const int32_t* n_src, int g) {
+    return sources != nullptr && n_src != nullptr && n_src[g] >= 0;
+}
+
+int graph_width(const hln_plan* plan, const hln_csr* graphs, const int32_t* const* sources, const int32_t* n_src,
+                int g, size_t budget) {
+    if (is_listed(sources, n_src, g)) return listed_width(plan, graphs[g].n, n_src[g]);
+    return chosen_width(plan, graphs[g].n, budget);
+}
 
 // Workspace layout.  Sizes are worst cases over every width a graph could be
 // tuned to (tiles of 8 sources, the cooperative kernel at 4096), so the
@@ -365,7 +407,7 @@ hln_status plan_layout(const hln_plan* plan, const hln_csr* graphs, int32_t n_gr
         std::max(1, std::min({max_parts(), n_graphs, static_cast<int>(total_work / std::max(max_work, 1.0))})));
     L.coop_bytes = static_cast<size_t>(L.coop_slices) * L.coop_slice_bytes;
     L.margs_bytes = Arena::round(hln::multi_args_bytes(n_graphs));
-    L.mlist_bytes = Arena::round(sizeof(int) * (static_cast<size_t>(n_graphs) + kCoopWidths * (kPartsCap + 1)));
+    L.mlist_bytes = Arena::round(sizeof(int) * (static_cast<size_t>(n_graphs) + 2 * kCoopWidths * (kPartsCap + 1)));
     L.stage_bytes = L.desc_bytes + L.tiles_bytes + L.margs_bytes + L.mlist_bytes;
     L.total = L.stage_bytes + L.counters_bytes + L.heavy_bytes + L.vis_bytes + 2 * L.part_bytes + L.coop_bytes;
     return HLN_OK;
@@ -373,9 +415,9 @@ hln_status plan_layout(const hln_plan* plan, const hln_csr* graphs, int32_t n_gr
 
 // Host-side tables: descriptors and the tile order (per width class, graphs
 // by decreasing n * nnz, batches in order).
-void build_tables(const hln_plan* plan, const hln_csr* graphs, int32_t n_graphs, int64_t* const* S,
-                  int32_t* const* R, double* const* cc, int32_t* const* h2, const Layout& L, char* dev_base,
-                  TileGraph* desc, int2* tiles, int* first_tile) {
+void build_tables(const hln_plan* plan, const hln_csr* graphs, int32_t n_graphs, const int32_t* const* sources,
+                  const int32_t* n_src, int64_t* const* S, int32_t* const* R, double* const* cc, int32_t* const* h2,
+                  const Layout& L, char* dev_base, TileGraph* desc, int2* tiles, int* first_tile) {
     const size_t budget = lds_budget();
     uint32_t* arcs = reinterpret_cast<uint32_t*>(dev_base + L.stage_bytes + L.counters_bytes);
     long long off = 0;
@@ -390,7 +432,7 @@ void build_tables(const hln_plan* plan, const hln_csr* graphs, int32_t n_graphs,
         desc[g].cc = cc ? cc[g] : nullptr;
         desc[g].nnz = c.nnz;
         desc[g].n = c.n;
-        desc[g].width = chosen_width(plan, c.n, budget);
+        desc[g].width = graph_width(plan, graphs, sources, n_src, g, budget);
         desc[g].arcs = arcs + off;
         if (!is_coop(desc[g].width)) off += c.nnz;
         order[g] = g;
@@ -422,9 +464,10 @@ hln_status launch_tiles(const TileArgs& ta, int grid, size_t lds, hipStream_t st
     return HLN_OK;
 }
 
-hln_status enqueue_batch(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs, int64_t* const* S,
-                         int32_t* const* R, double* const* cc, int32_t* const* h2, void* workspace,
-                         size_t workspace_bytes, hipStream_t st, bool capture_staging) {
+hln_status enqueue_batch(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs, const int32_t* const* sources,
+                         const int32_t* n_src, int64_t* const* S, int32_t* const* R, double* const* cc,
+                         int32_t* const* h2, void* workspace, size_t workspace_bytes, hipStream_t st,
+                         bool own_capture) {
     using hln::fail;
     Layout L;
     hln_status s = plan_layout(plan, graphs, n_graphs, L);
@@ -432,20 +475,33 @@ hln_status enqueue_batch(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs
     if (!S || !R) return fail(HLN_EINVAL, "S and R arrays are required");
     for (int g = 0; g < n_graphs; ++g)
         if (!S[g] || !R[g]) return fail(HLN_EINVAL, "graph %d: NULL output", g);
+    if (sources) {
+        if (!n_src) return fail(HLN_EINVAL, "a source table needs n_src");
+        for (int g = 0; g < n_graphs; ++g) {
+            if (n_src[g] == -1) continue;                   // all of graph g's vertices
+            if (n_src[g] < -1 || n_src[g] > graphs[g].n)
+                return fail(HLN_EINVAL, "graph %d: n_src %d outside [-1, n = %d]", g, n_src[g], graphs[g].n);
+            if (n_src[g] > 0 && !sources[g]) return fail(HLN_EINVAL, "graph %d: %d listed sources at NULL", g, n_src[g]);
+            if (h2 && h2[g]) return fail(HLN_EUNSUPPORTED, "graph %d: h2 is produced in all-source mode only", g);
+            if (graphs[g].nnz >= (1LL << 29) || static_cast<long long>(graphs[g].n) * 512 >= (1LL << 31))
+                return fail(HLN_EUNSUPPORTED, "graph %d too large for the persistent kernel", g);
+        }
+    }
     if (!workspace || reinterpret_cast<uintptr_t>(workspace) % hln::Arena::kAlign)
         return fail(HLN_EINVAL, "workspace NULL or not 256-byte aligned");
     if (workspace_bytes < L.total) return fail(HLN_ENOMEM, "workspace too small: %zu < %zu", workspace_bytes, L.total);
     const size_t stage = L.stage_bytes;
     // inside a stream capture (ours or the caller's) the staging is the
-    // frozen buffer reserved beforehand: no allocation, no host wait
+    // buffer armed beforehand, which the capture then keeps: no allocation,
+    // no host wait
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HLN_TRY_HIP(hipStreamIsCapturing(st, &cap));
-    if (cap == hipStreamCaptureStatusActive) capture_staging = true;
-    void** pin = capture_staging ? &plan->cap_pinned : &plan->pinned;
-    size_t* pin_bytes = capture_staging ? &plan->cap_pinned_bytes : &plan->pinned_bytes;
-    if (capture_staging) {
-        if (*pin_bytes < stage)
-            return fail(HLN_EINVAL, "capturing: reserve the plan's staging first (hln_plan_reserve)");
+    const bool capturing = cap == hipStreamCaptureStatusActive || own_capture;
+    void** pin = capturing ? &plan->armed : &plan->pinned;
+    size_t* pin_bytes = capturing ? &plan->armed_bytes : &plan->pinned_bytes;
+    if (capturing) {
+        if (!plan->armed || *pin_bytes < stage)
+            return fail(HLN_EINVAL, "capturing: reserve staging for this capture first (hln_plan_reserve)");
     } else {
         if (plan->staged_pending) {
             HLN_TRY_HIP(hipEventSynchronize(plan->staged));   // the previous copy has read the staging
@@ -462,7 +518,7 @@ hln_status enqueue_batch(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs
     TileGraph* desc_h = static_cast<TileGraph*>(*pin);
     int2* tiles_h = reinterpret_cast<int2*>(static_cast<char*>(*pin) + L.desc_bytes);
     int first[5];
-    build_tables(plan, graphs, n_graphs, S, R, cc, h2, L, dev, desc_h, tiles_h, first);
+    build_tables(plan, graphs, n_graphs, sources, n_src, S, R, cc, h2, L, dev, desc_h, tiles_h, first);
 
     // Graphs on the cooperative kernel, grouped by width: each group is one
     // multi-graph launch whose partitions take its graphs longest work first
@@ -472,61 +528,72 @@ hln_status enqueue_batch(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs
     void* const args_h = static_cast<char*>(*pin) + L.desc_bytes + L.tiles_bytes;
     int* const lists_h = reinterpret_cast<int*>(static_cast<char*>(*pin) + L.desc_bytes + L.tiles_bytes + L.margs_bytes);
     struct CoopGroup {
-        int width, parts, pfirst_off;
+        int width;
+        bool per_source;
+        int parts, pfirst_off;
     };
     std::vector<CoopGroup> groups;
-    std::vector<int> single;                 // cooperative graphs at another width: one launch each
     {
-        static const int kWidths[kCoopWidths] = {1024, 2048, 4096};
+        auto listed = [&](int g) { return is_listed(sources, n_src, g); };
         auto work = [&](int g) {
-            return static_cast<double>(graphs[g].n) * static_cast<double>(graphs[g].nnz + graphs[g].n);
+            const double src = listed(g) ? static_cast<double>(n_src[g]) : static_cast<double>(graphs[g].n);
+            return src * static_cast<double>(graphs[g].nnz + graphs[g].n);
         };
         int plist_n = 0, pfirst_n = n_graphs;
-        for (int g = 0; g < n_graphs; ++g) {
-            const int w = desc_h[g].width;
-            if (is_coop(w) && w != 1024 && w != 2048 && w != 4096) single.push_back(g);
-        }
-        for (int wi = 0; wi < kCoopWidths; ++wi) {
-            std::vector<int> members;
-            double total = 0.0, mx = 0.0;
-            for (int g = 0; g < n_graphs; ++g)
-                if (desc_h[g].width == kWidths[wi]) {
+        for (int wi = 0; wi < kCoopWidths; ++wi)
+            for (int ps = 0; ps < 2; ++ps) {
+                const int width = kCoopWidthList[wi];
+                std::vector<int> members;
+                double total = 0.0, mx = 0.0;
+                int max_n = 0;
+                for (int g = 0; g < n_graphs; ++g) {
+                    if (desc_h[g].width != width || listed(g) != (ps == 1)) continue;
+                    if (listed(g) && n_src[g] == 0) continue;          // nothing to compute
                     members.push_back(g);
                     total += work(g);
                     mx = std::max(mx, work(g));
+                    max_n = std::max(max_n, graphs[g].n);
                 }
-            if (members.empty()) continue;
-            const int parts = pow2_floor(std::max(1, std::min({L.coop_slices, static_cast<int>(members.size()),
-                                                               static_cast<int>(total / std::max(mx, 1.0))})));
-            std::sort(members.begin(), members.end(), [&](int x, int y) {
-                return work(x) > work(y) || (work(x) == work(y) && x < y);
-            });
-            std::vector<std::vector<int>> bins(parts);
-            std::vector<double> load(parts, 0.0);
-            for (int g : members) {
-                const int q = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
-                bins[q].push_back(g);
-                load[q] += work(g);
-            }
-            int* pf = lists_h + pfirst_n;
-            for (int q = 0; q < parts; ++q) {
-                pf[q] = plist_n;
-                for (int g : bins[q]) {
-                    lists_h[plist_n++] = g;
-                    const hln_status r = hln::multi_fill(graphs[g], S[g], R[g], cc ? cc[g] : nullptr,
-                                                         h2 ? h2[g] : nullptr, kWidths[wi],
-                                                         coop_ws + static_cast<size_t>(q) * L.coop_slice_bytes,
-                                                         L.coop_slice_bytes, args_h, g);
-                    if (r != HLN_OK) return r;
+                if (members.empty()) continue;
+                int parts = pow2_floor(std::max(1, std::min({L.coop_slices, static_cast<int>(members.size()),
+                                                             static_cast<int>(total / std::max(mx, 1.0))})));
+                if (max_n > kPartitionMaxN) parts = 1;
+                std::sort(members.begin(), members.end(), [&](int x, int y) {
+                    return work(x) > work(y) || (work(x) == work(y) && x < y);
+                });
+                std::vector<std::vector<int>> bins(parts);
+                std::vector<double> load(parts, 0.0);
+                for (int g : members) {
+                    const int q = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+                    bins[q].push_back(g);
+                    load[q] += work(g);
                 }
+                int* pf = lists_h + pfirst_n;
+                for (int q = 0; q < parts; ++q) {
+                    pf[q] = plist_n;
+                    for (int g : bins[q]) {
+                        lists_h[plist_n++] = g;
+                        const hln_status r = hln::multi_fill(
+                            graphs[g], listed(g) ? sources[g] : nullptr, listed(g) ? n_src[g] : graphs[g].n, S[g],
+                            R[g], cc ? cc[g] : nullptr, h2 ? h2[g] : nullptr, width,
+                            coop_ws + static_cast<size_t>(q) * L.coop_slice_bytes, L.coop_slice_bytes, args_h, g);
+                        if (r != HLN_OK) return r;
+                    }
+                }
+                pf[parts] = plist_n;
+                groups.push_back(CoopGroup{width, ps == 1, parts, pfirst_n});
+                pfirst_n += parts + 1;
             }
-            pf[parts] = plist_n;
-            groups.push_back(CoopGroup{kWidths[wi], parts, pfirst_n});
-            pfirst_n += parts + 1;
-        }
     }
     HLN_TRY_HIP(hipMemcpyAsync(dev, *pin, stage, hipMemcpyHostToDevice, st));
-    if (!capture_staging) {
+    if (capturing) {
+        // the captured copy reads this buffer at every replay: it leaves the
+        // armed slot and stays allocated while the graph can run
+        if (own_capture) plan->own = plan->armed;
+        else plan->frozen.push_back(plan->armed);
+        plan->armed = nullptr;
+        plan->armed_bytes = 0;
+    } else {
         if (!plan->staged) HLN_TRY_HIP(hipEventCreateWithFlags(&plan->staged, hipEventDisableTiming));
         HLN_TRY_HIP(hipEventRecord(plan->staged, st));
         plan->staged_pending = true;
@@ -578,15 +645,12 @@ hln_status enqueue_batch(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs
     // the first slice
     const void* args_d = dev + L.desc_bytes + L.tiles_bytes;
     const int* lists_d = reinterpret_cast<const int*>(dev + L.desc_bytes + L.tiles_bytes + L.margs_bytes);
+    plan->paths[0] = plan->paths[1] = plan->paths[2] = 0;
     for (const CoopGroup& cg : groups) {
-        const hln_status r = hln::multi_launch(cg.width, args_d, lists_d, lists_d + cg.pfirst_off, cg.parts, st);
+        const hln_status r =
+            hln::multi_launch(cg.width, cg.per_source, args_d, lists_d, lists_d + cg.pfirst_off, cg.parts, st);
         if (r != HLN_OK) return r;
-    }
-    for (int g : single) {
-        hln_opts o{desc_h[g].width, 0, 0, nullptr, nullptr, 0};
-        hln_status r = hln_closeness_layer(&graphs[g], nullptr, graphs[g].n, &o, S[g], R[g], cc ? cc[g] : nullptr,
-                                           h2 ? h2[g] : nullptr, coop_ws, L.coop_slice_bytes, st);
-        if (r != HLN_OK) return r;
+        ++plan->paths[hln_last_launch_path() == 2 ? 2 : 1];
     }
     return HLN_OK;
 }
@@ -615,8 +679,18 @@ void hln_plan_destroy(hln_plan* plan) {
         (void)hipEventDestroy(plan->staged);
     }
     if (plan->pinned) (void)hipHostFree(plan->pinned);
-    if (plan->cap_pinned) (void)hipHostFree(plan->cap_pinned);
+    if (plan->armed) (void)hipHostFree(plan->armed);
+    if (plan->own) (void)hipHostFree(plan->own);
+    for (void* b : plan->frozen) (void)hipHostFree(b);
     delete plan;
+}
+
+hln_status hln_plan_launch_paths(const hln_plan* plan, int32_t* cooperative, int32_t* ordinary) {
+    hln::clear_error();
+    if (!plan || !cooperative || !ordinary) return hln::fail(HLN_EINVAL, "NULL argument");
+    *cooperative = plan->paths[1];
+    *ordinary = plan->paths[2];
+    return HLN_OK;
 }
 
 int32_t hln_plan_width(const hln_plan* plan, int32_t n) {
@@ -643,18 +717,19 @@ size_t hln_closeness_batch_workspace_size(const hln_plan* plan, const hln_csr* g
     return L.total;
 }
 
-hln_status hln_closeness_batch(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs, int64_t* const* S,
+hln_status hln_closeness_batch(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs,
+                               const int32_t* const* sources, const int32_t* n_src, int64_t* const* S,
                                int32_t* const* R, double* const* cc, int32_t* const* h2, void* workspace,
                                size_t workspace_bytes, void* stream) {
     hln::clear_error();
     if (!plan) return hln::fail(HLN_EINVAL, "plan is NULL");
-    return enqueue_batch(plan, graphs, n_graphs, S, R, cc, h2, workspace, workspace_bytes,
+    return enqueue_batch(plan, graphs, n_graphs, sources, n_src, S, R, cc, h2, workspace, workspace_bytes,
                          static_cast<hipStream_t>(stream), false);
 }
 
-hln_status hln_plan_capture(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs, int64_t* const* S,
-                            int32_t* const* R, double* const* cc, int32_t* const* h2, void* workspace,
-                            size_t workspace_bytes, void* stream) {
+hln_status hln_plan_capture(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs, const int32_t* const* sources,
+                            const int32_t* n_src, int64_t* const* S, int32_t* const* R, double* const* cc,
+                            int32_t* const* h2, void* workspace, size_t workspace_bytes, void* stream) {
     using hln::fail;
     hln::clear_error();
     if (!plan) return fail(HLN_EINVAL, "plan is NULL");
@@ -668,22 +743,20 @@ hln_status hln_plan_capture(hln_plan* plan, const hln_csr* graphs, int32_t n_gra
         HLN_TRY_HIP(hipGraphDestroy(plan->graph));
         plan->graph = nullptr;
     }
-    if (plan->cap_pinned) {
-        HLN_TRY_HIP(hipHostFree(plan->cap_pinned));
-        plan->cap_pinned = nullptr;
-        plan->cap_pinned_bytes = 0;
+    // only the replaced graph read the old staging
+    if (plan->own) {
+        HLN_TRY_HIP(hipHostFree(plan->own));
+        plan->own = nullptr;
     }
     // the staging buffer is allocated before capture begins (no allocation
     // inside a capture)
     {
-        Layout L;
-        hln_status s = plan_layout(plan, graphs, n_graphs, L);
-        if (s != HLN_OK) return s;
-        HLN_TRY_HIP(hipHostMalloc(&plan->cap_pinned, L.stage_bytes, hipHostMallocDefault));
-        plan->cap_pinned_bytes = L.stage_bytes;
+        const hln_status r = hln_plan_reserve(plan, graphs, n_graphs);
+        if (r != HLN_OK) return r;
     }
     HLN_TRY_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    hln_status s = enqueue_batch(plan, graphs, n_graphs, S, R, cc, h2, workspace, workspace_bytes, st, true);
+    hln_status s = enqueue_batch(plan, graphs, n_graphs, sources, n_src, S, R, cc, h2, workspace, workspace_bytes,
+                                 st, true);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(st, &g);
     if (s != HLN_OK) {
@@ -703,12 +776,13 @@ hln_status hln_plan_reserve(hln_plan* plan, const hln_csr* graphs, int32_t n_gra
     hln_status s = plan_layout(plan, graphs, n_graphs, L);
     if (s != HLN_OK) return s;
     const size_t stage = L.stage_bytes;
-    if (plan->cap_pinned_bytes >= stage) return HLN_OK;
-    if (plan->cap_pinned) HLN_TRY_HIP(hipHostFree(plan->cap_pinned));
-    plan->cap_pinned = nullptr;
-    plan->cap_pinned_bytes = 0;
-    HLN_TRY_HIP(hipHostMalloc(&plan->cap_pinned, stage, hipHostMallocDefault));
-    plan->cap_pinned_bytes = stage;
+    if (plan->armed && plan->armed_bytes >= stage) return HLN_OK;
+    // an armed buffer has not been captured yet, so nothing reads it
+    if (plan->armed) HLN_TRY_HIP(hipHostFree(plan->armed));
+    plan->armed = nullptr;
+    plan->armed_bytes = 0;
+    HLN_TRY_HIP(hipHostMalloc(&plan->armed, stage, hipHostMallocDefault));
+    plan->armed_bytes = stage;
     return HLN_OK;
 }
 
@@ -759,8 +833,8 @@ hln_status hln_plan_tune(hln_plan* plan, const hln_csr* graphs, int32_t n_graphs
             for (int rep_i = 0; rep_i < 2 && result == HLN_OK; ++rep_i) {   // first run warms up
                 if (hipEventRecord(e0, st) != hipSuccess) result = fail(HLN_EDEVICE, "event record failed");
                 if (result == HLN_OK)
-                    result = enqueue_batch(plan, &graphs[g], 1, &S[g], &R[g], nullptr, nullptr, workspace,
-                                           workspace_bytes, st, false);
+                    result = enqueue_batch(plan, &graphs[g], 1, nullptr, nullptr, &S[g], &R[g], nullptr, nullptr,
+                                           workspace, workspace_bytes, st, false);
                 if (result == HLN_OK && hipEventRecord(e1, st) != hipSuccess) result = fail(HLN_EDEVICE, "event record failed");
                 if (result == HLN_OK && hipEventSynchronize(e1) != hipSuccess) result = fail(HLN_EDEVICE, "event sync failed");
                 if (result == HLN_OK) (void)hipEventElapsedTime(&ms, e0, e1);

@@ -20,29 +20,58 @@ struct DeviceInfo {
     int cus = 0;
     int max_threads_per_cu = 0;
     size_t lds_per_block = 0;
+    size_t lds_per_cu = 0;
 };
 // Facts about the current device (cached per device).
 const DeviceInfo* device_info();
+
+// Co-residency of a kernel's blocks on one compute unit (CDNA4: 4 SIMDs of
+// 512 VGPRs per lane, allocated in granules of 8, at most 8 waves per SIMD;
+// LDS allocated per block in granules of 512 bytes).  A block of B threads
+// holds ceil(ceil(B/64) / 4) wave slots on each SIMD.
+int resident_blocks(int vgprs, size_t lds_bytes, int block, size_t lds_per_cu);
+
+// What a compiled kernel needs and how many of its blocks fit a compute
+// unit: vgprs and lds from hipFuncGetAttributes (VGPRs per lane, static
+// LDS per block; dynamic LDS is added by the caller through `dyn_lds`),
+// scratch bytes per lane, the runtime's occupancy answer (`query`) and the
+// bound a cooperative grid is held to: the smaller of that answer and
+// resident_blocks() of the kernel's own registers and LDS.
+struct Residency {
+    int vgprs = 0;
+    int lds = 0;
+    int scratch = 0;
+    int query = 0;
+    int bound = 0;
+};
+hln_status residency(const void* kernel, int block, size_t dyn_lds, Residency& r);
+
+// How the last persistent (grid-barrier) launch of this thread went out:
+// 1 cooperative launch, 2 ordinary launch inside a stream capture (the
+// runtime refused the cooperative one; the grid is within the residency
+// bound).
+void note_launch_path(int path);
 
 // Device address of the library's fault word on the current device; kernels
 // store a nonzero code there when a bounded wait runs out or an input is
 // out of range.  nullptr (with the error set) on failure.
 int* fault_word();
 
-// Several graphs' all-source closeness in one cooperative launch, for the
-// batched path (hln_msbfs.hip).  The caller stages an array of launch
-// arguments (multi_args_bytes(n) bytes, filled on the host by multi_fill for
-// each graph: its working set is carved from the workspace slice of the
-// partition that runs it, each slice multi_slice_bytes() for the largest
-// graph it serves) and, in device memory, the partitions' graph lists:
-// plist (argument indices) and pfirst (parts + 1 offsets into plist).  Only
-// widths 1024, 2048 and 4096 are supported.
+// Several graphs' closeness in one cooperative launch, for the batched path
+// (hln_msbfs.hip): all graphs of a launch either use every source (sums
+// per vertex) or a list of sources (sums per listed source, per_source).
+// The caller stages an array of launch arguments (multi_args_bytes(n)
+// bytes, filled on the host by multi_fill for each graph: its working set is
+// carved from the workspace slice of the partition that runs it, each slice
+// multi_slice_bytes() for the largest graph it serves) and, in device
+// memory, the partitions' graph lists: plist (argument indices) and pfirst
+// (parts + 1 offsets into plist).  Widths 512, 1024, 2048 and 4096.
 size_t multi_args_bytes(int n_graphs);
 size_t multi_slice_bytes(int32_t n, int64_t nnz, int width_bits);
-hln_status multi_fill(const hln_csr& g, int64_t* S, int32_t* R, double* cc, int32_t* h2, int width_bits, void* slice,
-                      size_t slice_bytes, void* args_host, int index);
-hln_status multi_launch(int width_bits, const void* args_dev, const int* plist_dev, const int* pfirst_dev, int parts,
-                        hipStream_t st);
+hln_status multi_fill(const hln_csr& g, const int32_t* sources, int32_t n_src, int64_t* S, int32_t* R, double* cc,
+                      int32_t* h2, int width_bits, void* slice, size_t slice_bytes, void* args_host, int index);
+hln_status multi_launch(int width_bits, bool per_source, const void* args_dev, const int* plist_dev,
+                        const int* pfirst_dev, int parts, hipStream_t st);
 
 // Bump allocator over a caller workspace (256-byte alignment).
 struct Arena {

@@ -329,6 +329,15 @@ unsigned grid_for(long long count, int block = 256) {
     return static_cast<unsigned>(std::max<long long>(1, std::min<long long>((count + block - 1) / block, 8192)));
 }
 
+// key = value = the id, for sorting a list of ids ascending
+__global__ void k_id_keys(int k, const int32_t* __restrict__ ids, unsigned long long* key, int32_t* val) {
+    for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < k;
+         i += static_cast<long long>(gridDim.x) * blockDim.x) {
+        key[i] = static_cast<unsigned long long>(static_cast<uint32_t>(ids[i]));
+        val[i] = ids[i];
+    }
+}
+
 size_t topk_ws(int32_t n) {
     if (n < 1) return 0;
     return hln::Arena::round(static_cast<size_t>(n) * 8) + hln::Arena::round(static_cast<size_t>(n) * 4) +
@@ -443,12 +452,27 @@ hln_status hln_topk(int32_t n, const void* score, int32_t dtype, int32_t k, int3
     hln::clear_error();
     if (k < 0 || k > n) return hln::fail(HLN_EINVAL, "k must be in [0, n]");
     if (!ids) return hln::fail(HLN_EINVAL, "ids is NULL");
+    const bool as_set = (dtype & HLN_TOPK_SET) != 0;
+    dtype &= ~HLN_TOPK_SET;
     unsigned long long* key;
     int32_t* val;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const hln_status s = sort_scores(n, score, dtype, workspace, workspace_bytes, st, &key, &val);
+    hln_status s = sort_scores(n, score, dtype, workspace, workspace_bytes, st, &key, &val);
     if (s != HLN_OK) return s;
     if (k > 0) hipLaunchKernelGGL(k_take_ids, dim3(grid_for(k)), dim3(256), 0, st, k, val, ids);
+    if (as_set && k > 1) {
+        // the same k ids in ascending order: one more radix sort, of the ids
+        // themselves, in the key and value arrays the ranking is done with
+        hipLaunchKernelGGL(k_id_keys, dim3(grid_for(k)), dim3(256), 0, st, k, ids, key, val);
+        int bits = 1;
+        while (bits < 31 && ((n - 1) >> bits) != 0) ++bits;
+        hln::Arena ar{static_cast<char*>(workspace), workspace_bytes};
+        (void)ar.take<unsigned long long>(n);
+        (void)ar.take<int32_t>(n);
+        s = hln::prim::sort_pairs(key, val, k, bits, ar.base + ar.off, workspace_bytes - ar.off, st);
+        if (s != HLN_OK) return s;
+        hipLaunchKernelGGL(k_take_ids, dim3(grid_for(k)), dim3(256), 0, st, k, val, ids);
+    }
     HLN_TRY_HIP(hipGetLastError());
     return HLN_OK;
 }

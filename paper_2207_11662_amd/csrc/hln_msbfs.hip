@@ -1263,14 +1263,16 @@ __global__ void k_zero_ctrl(Ctrl* c, unsigned long long* bar) {
     for (int i = threadIdx.x; i < hln::dev::kBarrierWords; i += blockDim.x) bar[i] = 0;
 }
 
-// Several graphs (all sources, per-vertex sums) in one cooperative launch:
+// Several graphs in one cooperative launch (all in the same accumulation
+// mode: all sources with per-vertex sums, or listed sources with per-source
+// sums):
 // the grid is cut into `parts` partitions, partition p holding the blocks b
 // with b % parts == p (blocks are dealt to the XCDs in turn, so with 8
 // partitions each keeps to one XCD and its L2).  A partition runs its list
 // of graphs one after another with the single-graph algorithm and a barrier
 // of its own, clearing its control block between two graphs.  All graphs of
 // a partition share one workspace slice.
-template <int NW, int BLOCK>
+template <int NW, int BLOCK, bool PER_SOURCE>
 __global__ __launch_bounds__(BLOCK) void k_closeness_multi(const BfsArgs* __restrict__ args,
                                                            const int* __restrict__ plist,
                                                            const int* __restrict__ pfirst, int parts) {
@@ -1294,7 +1296,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness_multi(const BfsArgs* __rest
             }
             if (!gb.wait()) return;
         }
-        if (!closeness_run<NW, BLOCK, false>(a, gb, blk, nblk)) return;
+        if (!closeness_run<NW, BLOCK, PER_SOURCE>(a, gb, blk, nblk)) return;
     }
 }
 
@@ -1315,58 +1317,82 @@ struct Layout {
     size_t seg_cap;
 };
 
-template <int NW, int BLOCK, bool PS>
-hln_status launch(const BfsArgs& args, int grid, hipStream_t stream) {
-    if (getenv("HLN_VERBOSE"))
-        fprintf(stderr, "[hln] closeness NW=%d block=%d per_source=%d n=%d n_src=%d grid=%d\n", NW, BLOCK,
-                PS ? 1 : 0, args.n, args.n_src, grid);
-    void* kargs[] = {const_cast<BfsArgs*>(&args)};
-    hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_closeness<NW, BLOCK, PS>), dim3(grid),
-                                              dim3(BLOCK), kargs, 0, stream);
+// A kernel with grid barriers needs every block of its grid resident at
+// once.  The cooperative launch is the runtime's guarantee of that; inside a
+// stream capture the runtime may refuse it, and the same grid then goes out
+// as an ordinary kernel node.  Either way the grid never exceeds the
+// residency bound (hln::residency: the occupancy query, and the blocks the
+// kernel's own VGPRs and LDS allow per compute unit, times the compute
+// units), and every wait in the kernel is bounded, so a grid that did not
+// all start ends with fault code 1 rather than hanging.
+hln_status launch_persistent(const void* f, int grid, int block, void** kargs, int bound_grid, hipStream_t stream) {
+    if (grid < 1 || grid > bound_grid)
+        return hln::fail(HLN_EUNSUPPORTED, "grid of %d blocks exceeds the co-residency bound %d", grid, bound_grid);
+    hipError_t e = hipLaunchCooperativeKernel(f, dim3(grid), dim3(block), kargs, 0, stream);
+    int path = 1;
     if (e != hipSuccess) {
-        // Inside a stream capture a cooperative launch may be refused; the
-        // same grid (one block per compute unit at most, well under what fits
-        // at once) is then launched as an ordinary kernel node.  Every wait in
-        // the kernel is bounded, so a grid that did not all start would end
-        // with fault code 1 rather than hang.
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
         if (hipStreamIsCapturing(stream, &cap) == hipSuccess && cap == hipStreamCaptureStatusActive) {
             (void)hipGetLastError();
-            hipLaunchKernelGGL((k_closeness<NW, BLOCK, PS>), dim3(grid), dim3(BLOCK), 0, stream, args);
-            e = hipGetLastError();
+            e = hipLaunchKernel(f, dim3(grid), dim3(block), kargs, 0, stream);
+            path = 2;
         }
     }
-    if (e != hipSuccess) return hln::fail(HLN_EDEVICE, "closeness launch failed: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return hln::fail(HLN_EDEVICE, "persistent launch failed: %s", hipGetErrorString(e));
+    hln::note_launch_path(path);
     return HLN_OK;
 }
 
-// Blocks per CU of a cooperative launch.  The occupancy query overstates
-// what becomes co-resident on this device (a grid at the reported limit did
-// not all start), so the grid stays at <= 2048 threads per CU / 2 by default.
 template <int NW, int BLOCK, bool PS>
-int max_grid(int cus) {
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_closeness<NW, BLOCK, PS>),
-                                                     BLOCK, 0) != hipSuccess || per_cu < 1)
-        per_cu = 1;
-    int cap = std::max(1, 1024 / BLOCK);
-    if (const char* e = getenv("HLN_BLOCKS_PER_CU")) cap = std::max(1, atoi(e));
-    return std::max(1, cus * std::min(per_cu, cap));
+const void* closeness_fn() {
+    return reinterpret_cast<const void*>(&k_closeness<NW, BLOCK, PS>);
+}
+
+// Blocks per compute unit of a persistent launch: the residency bound,
+// at most one 1024-thread block's worth of threads per CU by default (the
+// measured best: fewest barrier participants for the same waves).
+// HLN_BLOCKS_PER_CU overrides the default up to the bound; a value above
+// the bound is refused (0 is returned and the error set).
+int blocks_per_cu(const void* f, int block) {
+    hln::Residency r;
+    if (hln::residency(f, block, 0, r) != HLN_OK) return 0;
+    if (r.bound < 1) {
+        hln::fail(HLN_EUNSUPPORTED, "kernel does not fit a compute unit (%d VGPRs, %d B LDS, block %d)", r.vgprs,
+                  r.lds, block);
+        return 0;
+    }
+    int per_cu = std::min(r.bound, std::max(1, 1024 / block));
+    if (const char* e = getenv("HLN_BLOCKS_PER_CU")) {
+        const int want = atoi(e);
+        if (want < 1 || want > r.bound) {
+            hln::fail(HLN_EUNSUPPORTED, "HLN_BLOCKS_PER_CU=%d is outside [1, %d] (the co-residency bound: %d VGPRs, "
+                                        "%d B LDS, block %d)", want, r.bound, r.vgprs, r.lds, block);
+            return 0;
+        }
+        per_cu = want;
+    }
+    return per_cu;
 }
 
 template <int NW, int BLOCK>
 hln_status dispatch(const BfsArgs& a, bool ps, int want, int grid_cap, int cus, hipStream_t st) {
-    auto pick = [&](int maxg) { return std::max(1, std::min({want, maxg, grid_cap})); };
-    if (ps) return launch<NW, BLOCK, true>(a, pick(max_grid<NW, BLOCK, true>(cus)), st);
-    return launch<NW, BLOCK, false>(a, pick(max_grid<NW, BLOCK, false>(cus)), st);
+    const void* f = ps ? closeness_fn<NW, BLOCK, true>() : closeness_fn<NW, BLOCK, false>();
+    const int per_cu = blocks_per_cu(f, BLOCK);
+    if (per_cu < 1) return HLN_EUNSUPPORTED;
+    const int bound_grid = per_cu * cus;
+    const int grid = std::max(1, std::min({want, bound_grid, grid_cap}));
+    if (getenv("HLN_VERBOSE"))
+        fprintf(stderr, "[hln] closeness NW=%d block=%d per_source=%d n=%d n_src=%d grid=%d\n", NW, BLOCK,
+                ps ? 1 : 0, a.n, a.n_src, grid);
+    void* kargs[] = {const_cast<BfsArgs*>(&a)};
+    return launch_persistent(f, grid, BLOCK, kargs, bound_grid, st);
 }
 
 template <int NW, int BLOCK>
 bool fits(bool ps) {
-    int per_cu = 0;
-    const void* f = ps ? reinterpret_cast<const void*>(&k_closeness<NW, BLOCK, true>)
-                       : reinterpret_cast<const void*>(&k_closeness<NW, BLOCK, false>);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, BLOCK, 0) == hipSuccess && per_cu >= 1;
+    hln::Residency r;
+    const void* f = ps ? closeness_fn<NW, BLOCK, true>() : closeness_fn<NW, BLOCK, false>();
+    return hln::residency(f, BLOCK, 0, r) == HLN_OK && r.bound >= 1;
 }
 
 // Block size: 1024 threads by default (fewest barrier participants for the
@@ -1484,6 +1510,55 @@ hln_status fill_args(BfsArgs& a, const hln_csr* g, const int32_t* sources, int32
 
 extern "C" {
 
+hln_status hln_closeness_kernel_residency(int32_t width_bits, int32_t block_threads, int32_t mode, int32_t* info) {
+    using hln::fail;
+    hln::clear_error();
+    if (!info) return fail(HLN_EINVAL, "info is NULL");
+    hln_opts o{width_bits, 0, 0, nullptr, nullptr, 0};
+    const int nw = width_words(&o);
+    if (nw == 0) return fail(HLN_EINVAL, "bad width %d", width_bits);
+    if (mode < 0 || mode > 3) return fail(HLN_EINVAL, "mode must be 0, 1, 2 or 3");
+    if (block_threads != 256 && block_threads != 512 && block_threads != 1024)
+        return fail(HLN_EINVAL, "block must be 256, 512 or 1024");
+    const void* f = nullptr;
+    auto pick = [&](auto nwc) {
+        constexpr int N = decltype(nwc)::value;
+        if (mode >= 2) {
+            if constexpr (N == 8 || N == 16 || N == 32 || N == 64) {
+                if (block_threads == 1024)
+                    f = mode == 3 ? reinterpret_cast<const void*>(&k_closeness_multi<N, 1024, true>)
+                                  : reinterpret_cast<const void*>(&k_closeness_multi<N, 1024, false>);
+            }
+            return;
+        }
+        const bool ps = mode == 1;
+        switch (block_threads) {
+            case 256: f = ps ? closeness_fn<N, 256, true>() : closeness_fn<N, 256, false>(); break;
+            case 512: f = ps ? closeness_fn<N, 512, true>() : closeness_fn<N, 512, false>(); break;
+            default: f = ps ? closeness_fn<N, 1024, true>() : closeness_fn<N, 1024, false>(); break;
+        }
+    };
+    switch (nw) {
+        case 1: pick(std::integral_constant<int, 1>{}); break;
+        case 2: pick(std::integral_constant<int, 2>{}); break;
+        case 4: pick(std::integral_constant<int, 4>{}); break;
+        case 8: pick(std::integral_constant<int, 8>{}); break;
+        case 16: pick(std::integral_constant<int, 16>{}); break;
+        case 32: pick(std::integral_constant<int, 32>{}); break;
+        default: pick(std::integral_constant<int, 64>{}); break;
+    }
+    if (!f) return fail(HLN_EUNSUPPORTED, "no such kernel (multi-graph: widths 512-4096, block 1024)");
+    hln::Residency r;
+    const hln_status st = hln::residency(f, block_threads, 0, r);
+    if (st != HLN_OK) return st;
+    info[0] = r.vgprs;
+    info[1] = r.lds;
+    info[2] = r.scratch;
+    info[3] = r.query;
+    info[4] = r.bound;
+    return HLN_OK;
+}
+
 size_t hln_closeness_workspace_size(int32_t n, int64_t nnz, int32_t n_src, const hln_opts* opts) {
     (void)n_src;
     int nw = width_words(opts);
@@ -1564,38 +1639,24 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
 
 namespace {
 
-template <int NW>
+template <int NW, bool PS>
 hln_status launch_multi(const void* args_dev, const int* plist_dev, const int* pfirst_dev, int parts, int cus,
                         hipStream_t st) {
     constexpr int BLOCK = 1024;
-    const void* f = reinterpret_cast<const void*>(&k_closeness_multi<NW, BLOCK>);
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, BLOCK, 0) != hipSuccess || per_cu < 1)
-        return hln::fail(HLN_EUNSUPPORTED, "multi-graph kernel does not fit a compute unit");
+    const void* f = reinterpret_cast<const void*>(&k_closeness_multi<NW, BLOCK, PS>);
+    const int per_cu = blocks_per_cu(f, BLOCK);
+    if (per_cu < 1) return HLN_EUNSUPPORTED;
     // one block per compute unit, as the single-graph launch; a whole number
     // of rounds of partitions
     const int grid = std::max(parts, (cus / parts) * parts);
     if (getenv("HLN_VERBOSE"))
-        fprintf(stderr, "[hln] closeness multi NW=%d parts=%d grid=%d\n", NW, parts, grid);
+        fprintf(stderr, "[hln] closeness multi NW=%d per_source=%d parts=%d grid=%d\n", NW, PS ? 1 : 0, parts, grid);
     const BfsArgs* args = static_cast<const BfsArgs*>(args_dev);
     hipLaunchKernelGGL(k_zero_parts, dim3(parts), dim3(256), 0, st, args, plist_dev, pfirst_dev);
     HLN_TRY_HIP(hipGetLastError());
     void* kargs[] = {const_cast<BfsArgs**>(&args), const_cast<int**>(&plist_dev), const_cast<int**>(&pfirst_dev),
                      &parts};
-    hipError_t e = hipLaunchCooperativeKernel(f, dim3(grid), dim3(BLOCK), kargs, 0, st);
-    if (e != hipSuccess) {
-        // refused inside a stream capture: the same grid as an ordinary
-        // kernel node (see launch())
-        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(st, &cap) == hipSuccess && cap == hipStreamCaptureStatusActive) {
-            (void)hipGetLastError();
-            hipLaunchKernelGGL((k_closeness_multi<NW, BLOCK>), dim3(grid), dim3(BLOCK), 0, st, args, plist_dev,
-                               pfirst_dev, parts);
-            e = hipGetLastError();
-        }
-    }
-    if (e != hipSuccess) return hln::fail(HLN_EDEVICE, "multi-graph closeness launch failed: %s", hipGetErrorString(e));
-    return HLN_OK;
+    return launch_persistent(f, grid, BLOCK, kargs, per_cu * cus, st);
 }
 
 }  // namespace
@@ -1612,8 +1673,8 @@ size_t multi_slice_bytes(int32_t n, int64_t nnz, int width_bits) {
     return Arena::round(workspace_bytes(n, nnz, nw, grid_cap_for(di ? di->cus : 256)));
 }
 
-hln_status multi_fill(const hln_csr& g, int64_t* S, int32_t* R, double* cc, int32_t* h2, int width_bits, void* slice,
-                      size_t slice_bytes, void* args_host, int index) {
+hln_status multi_fill(const hln_csr& g, const int32_t* sources, int32_t n_src, int64_t* S, int32_t* R, double* cc,
+                      int32_t* h2, int width_bits, void* slice, size_t slice_bytes, void* args_host, int index) {
     hln_opts o{width_bits, 0, 0, nullptr, nullptr, 0};
     const int nw = width_words(&o);
     if (nw == 0) return fail(HLN_EINVAL, "unsupported width %d", width_bits);
@@ -1624,20 +1685,32 @@ hln_status multi_fill(const hln_csr& g, int64_t* S, int32_t* R, double* cc, int3
     if (!di) return HLN_EDEVICE;
     int* fault = fault_word();
     if (!fault) return HLN_EDEVICE;
+    if (sources && h2) return fail(HLN_EUNSUPPORTED, "h2 is produced in all-source mode only");
     BfsArgs* a = static_cast<BfsArgs*>(args_host) + index;
-    return fill_args(*a, &g, nullptr, g.n, false, nw, &o, S, R, cc, h2, slice, slice_bytes, grid_cap_for(di->cus),
-                     fault);
+    return fill_args(*a, &g, sources, sources ? n_src : g.n, false, nw, &o, S, R, cc, h2, slice, slice_bytes,
+                     grid_cap_for(di->cus), fault);
 }
 
-hln_status multi_launch(int width_bits, const void* args_dev, const int* plist_dev, const int* pfirst_dev, int parts,
-                        hipStream_t st) {
+hln_status multi_launch(int width_bits, bool per_source, const void* args_dev, const int* plist_dev,
+                        const int* pfirst_dev, int parts, hipStream_t st) {
     const DeviceInfo* di = device_info();
     if (!di) return HLN_EDEVICE;
     if (parts < 1 || parts > di->cus) return fail(HLN_EINVAL, "bad partition count %d", parts);
+    const int c = di->cus;
+    if (per_source) {
+        switch (width_bits) {
+            case 512: return launch_multi<8, true>(args_dev, plist_dev, pfirst_dev, parts, c, st);
+            case 1024: return launch_multi<16, true>(args_dev, plist_dev, pfirst_dev, parts, c, st);
+            case 2048: return launch_multi<32, true>(args_dev, plist_dev, pfirst_dev, parts, c, st);
+            case 4096: return launch_multi<64, true>(args_dev, plist_dev, pfirst_dev, parts, c, st);
+            default: return fail(HLN_EUNSUPPORTED, "multi-graph launch at width %d", width_bits);
+        }
+    }
     switch (width_bits) {
-        case 1024: return launch_multi<16>(args_dev, plist_dev, pfirst_dev, parts, di->cus, st);
-        case 2048: return launch_multi<32>(args_dev, plist_dev, pfirst_dev, parts, di->cus, st);
-        case 4096: return launch_multi<64>(args_dev, plist_dev, pfirst_dev, parts, di->cus, st);
+        case 512: return launch_multi<8, false>(args_dev, plist_dev, pfirst_dev, parts, c, st);
+        case 1024: return launch_multi<16, false>(args_dev, plist_dev, pfirst_dev, parts, c, st);
+        case 2048: return launch_multi<32, false>(args_dev, plist_dev, pfirst_dev, parts, c, st);
+        case 4096: return launch_multi<64, false>(args_dev, plist_dev, pfirst_dev, parts, c, st);
         default: return fail(HLN_EUNSUPPORTED, "multi-graph launch at width %d", width_bits);
     }
 }

@@ -2,6 +2,7 @@
 // fault word and the status query.
 #include "hln_internal.hpp"
 
+#include <algorithm>
 #include <cstdarg>
 #include <cstdio>
 #include <mutex>
@@ -50,6 +51,7 @@ const DeviceInfo* device_info() {
         d.cus = p.multiProcessorCount;
         d.max_threads_per_cu = p.maxThreadsPerMultiProcessor;
         d.lds_per_block = p.sharedMemPerBlock;
+        d.lds_per_cu = p.maxSharedMemoryPerMultiProcessor > 0 ? p.maxSharedMemoryPerMultiProcessor : 160 * 1024;
         d.device = dev;
     }
     return &d;
@@ -74,9 +76,53 @@ int* fault_word() {
     return g_fault_ptr[dev];
 }
 
+int resident_blocks(int vgprs, size_t lds_bytes, int block, size_t lds_per_cu) {
+    constexpr int kSimds = 4, kVgprFile = 512, kVgprGranule = 8, kMaxWavesPerSimd = 8;
+    constexpr size_t kLdsGranule = 512;
+    if (block < 1 || block > 1024 || vgprs < 0 || vgprs > kVgprFile) return 0;
+    const int waves = (block + 63) / 64;
+    const int slots = (waves + kSimds - 1) / kSimds;      // wave slots per SIMD per block
+    const int alloc = std::max(kVgprGranule, (vgprs + kVgprGranule - 1) / kVgprGranule * kVgprGranule);
+    const int waves_per_simd = std::min(kMaxWavesPerSimd, kVgprFile / alloc);
+    int blocks = waves_per_simd / slots;
+    if (lds_bytes > 0) {
+        const size_t a = (lds_bytes + kLdsGranule - 1) / kLdsGranule * kLdsGranule;
+        blocks = std::min<long long>(blocks, static_cast<long long>(lds_per_cu / a));
+    }
+    return blocks;
+}
+
+hln_status residency(const void* kernel, int block, size_t dyn_lds, Residency& r) {
+    const DeviceInfo* di = device_info();
+    if (!di) return HLN_EDEVICE;
+    hipFuncAttributes at{};
+    HLN_TRY_HIP(hipFuncGetAttributes(&at, kernel));
+    int q = 0;
+    HLN_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, kernel, block, dyn_lds));
+    r.vgprs = at.numRegs;
+    r.lds = static_cast<int>(at.sharedSizeBytes);
+    r.scratch = static_cast<int>(at.localSizeBytes);
+    r.query = q;
+    r.bound = std::min(q, resident_blocks(at.numRegs, at.sharedSizeBytes + dyn_lds, block, di->lds_per_cu));
+    return HLN_OK;
+}
+
+namespace {
+thread_local int t_launch_path = 0;
+}
+
+void note_launch_path(int path) { t_launch_path = path; }
+
 }  // namespace hln
 
 extern "C" {
+
+int32_t hln_resident_blocks(int32_t vgprs, int32_t lds_bytes, int32_t block_threads) {
+    if (lds_bytes < 0) return 0;
+    return hln::resident_blocks(vgprs, static_cast<size_t>(lds_bytes), block_threads, 160 * 1024);
+}
+
+int32_t hln_last_launch_path(void) { return hln::t_launch_path; }
 
 const char* hln_last_error(void) { return t_error; }
 

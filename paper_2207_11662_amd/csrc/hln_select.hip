@@ -8,8 +8,10 @@
 //                  distance sum S + n(n - R) (Sec. 5.1: unreachable at
 //                  distance n; Sec. 5.2, Algorithm 1), score = (n-1)/est
 //                  (Eq. 1 on the estimate).
-//   HLN_RANK_NAIVE r layers: the intersection of the layers' above-average
-//                  CC-node sets (Sec. 4); only with k = -1.
+//   HLN_RANK_NAIVE r layers: the intersection of the layers' CC-node sets
+//                  (Sec. 4): their above-average sets (k = -1) or their
+//                  top-k sets (k >= 0; the intersection may hold fewer than
+//                  k vertices).
 //
 // k >= 0: the k highest scores, ties by ascending vertex id, in rank order
 // (a stable radix sort of the score keys over vertices in id order).
@@ -220,6 +222,36 @@ __global__ void k_compact(int n, const int32_t* __restrict__ flag, const int32_t
     if (blockIdx.x == 0 && threadIdx.x == 0) *count = pos[n];
 }
 
+// key = value = the id, for sorting a list of ids ascending
+__global__ void k_id_keys(int k, const int32_t* __restrict__ ids, unsigned long long* key, int32_t* val) {
+    for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < k;
+         i += static_cast<long long>(gridDim.x) * blockDim.x) {
+        key[i] = static_cast<unsigned long long>(static_cast<uint32_t>(ids[i]));
+        val[i] = ids[i];
+    }
+}
+
+__global__ void k_zero_flags(int n, int32_t* flag) {
+    for (long long u = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; u < n;
+         u += static_cast<long long>(gridDim.x) * blockDim.x)
+        flag[u] = 0;
+}
+
+// one more layer's top-k set: flag[u] counts the layers whose top k hold u
+// (`order` is the layer's ranking, a permutation, so no two threads share u)
+__global__ void k_count_top(int k, const int32_t* __restrict__ order, int32_t* flag) {
+    for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < k;
+         i += static_cast<long long>(gridDim.x) * blockDim.x)
+        flag[order[i]] += 1;
+}
+
+// flag[u] = (u is in every layer's top-k set)
+__global__ void k_flag_all(int n, int r, int32_t* flag) {
+    for (long long u = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; u < n;
+         u += static_cast<long long>(gridDim.x) * blockDim.x)
+        flag[u] = flag[u] == r ? 1 : 0;
+}
+
 __global__ void k_take(int k, const int32_t* __restrict__ order, const double* __restrict__ score, int32_t* ids,
                        double* out_score, int32_t* count) {
     for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < k;
@@ -305,12 +337,15 @@ hln_status hln_compose_cc_topk(int32_t mode, int32_t n, int32_t r, const int64_t
                                size_t workspace_bytes, void* stream) {
     using hln::fail;
     hln::clear_error();
+    const bool as_set = (mode & HLN_TOPK_SET) != 0;
+    mode &= ~HLN_TOPK_SET;
     if (mode != HLN_RANK_WF && mode != HLN_RANK_CC2 && mode != HLN_RANK_NAIVE) return fail(HLN_EINVAL, "bad mode %d", mode);
+    if (as_set && (mode == HLN_RANK_NAIVE || k < 0))
+        return fail(HLN_EINVAL, "HLN_TOPK_SET applies to the k >= 0 form of HLN_RANK_WF and HLN_RANK_CC2");
     if (n < 1) return fail(HLN_EINVAL, "n must be >= 1");
     if (r < 1 || r > kMaxLayers) return fail(HLN_EINVAL, "r must be in [1, %d]", kMaxLayers);
     if (mode == HLN_RANK_WF && r != 1) return fail(HLN_EINVAL, "HLN_RANK_WF ranks one graph (r = 1)");
     if (k < -1 || k > n) return fail(HLN_EINVAL, "k must be -1 or in [0, n] (got %d)", k);
-    if (mode == HLN_RANK_NAIVE && k != -1) return fail(HLN_EINVAL, "HLN_RANK_NAIVE gives a set: k must be -1");
     if (!S || !R || !ids || !count) return fail(HLN_EINVAL, "NULL argument");
     SR L;
     L.r = r;
@@ -338,6 +373,29 @@ hln_status hln_compose_cc_topk(int32_t mode, int32_t n, int32_t r, const int64_t
     const unsigned g = grid_for(n);
     const unsigned gc = grid_for(chunks, 64);
 
+    if (mode == HLN_RANK_NAIVE && k >= 0) {
+        // each layer's top k by its own closeness (ties by id), counted per
+        // vertex; the vertices every layer holds, ids ascending
+        hipLaunchKernelGGL(k_zero_flags, dim3(g), dim3(256), 0, st, n, flag);
+        for (int l = 0; l < r; ++l) {
+            SR one;
+            one.r = 1;
+            one.S[0] = L.S[l];
+            one.R[0] = L.R[l];
+            hipLaunchKernelGGL(k_scores, dim3(g), dim3(256), 0, st, static_cast<int>(HLN_RANK_WF), n, one, sc, key,
+                               val);
+            hln_status s = hln::prim::sort_pairs(key, val, n, 63, sws, sws_bytes, st);
+            if (s != HLN_OK) return s;
+            if (k > 0) hipLaunchKernelGGL(k_count_top, dim3(grid_for(k)), dim3(256), 0, st, k, val, flag);
+        }
+        hipLaunchKernelGGL(k_flag_all, dim3(g), dim3(256), 0, st, n, r, flag);
+        hln_status s = hln::prim::scan_exclusive<int32_t>(flag, pos, n, sws, sws_bytes, st);
+        if (s != HLN_OK) return s;
+        hipLaunchKernelGGL(k_compact, dim3(g), dim3(256), 0, st, n, flag, pos, static_cast<const double*>(nullptr),
+                           ids, score, count);
+        HLN_TRY_HIP(hipGetLastError());
+        return HLN_OK;
+    }
     if (mode == HLN_RANK_NAIVE) {
         for (int l = 0; l < r; ++l) {
             hipLaunchKernelGGL(k_layer_cc, dim3(g), dim3(256), 0, st, n, L.S[l], L.R[l], sc);
@@ -362,6 +420,13 @@ hln_status hln_compose_cc_topk(int32_t mode, int32_t n, int32_t r, const int64_t
         hln_status s = hln::prim::sort_pairs(key, val, n, bits, sws, sws_bytes, st);
         if (s != HLN_OK) return s;
         hipLaunchKernelGGL(k_take, dim3(grid_for(std::max(k, 1))), dim3(256), 0, st, k, val, sc, ids, score, count);
+        if (as_set && k > 1) {
+            // the same k vertices in ascending id order, with their scores
+            hipLaunchKernelGGL(k_id_keys, dim3(grid_for(k)), dim3(256), 0, st, k, ids, key, val);
+            s = hln::prim::sort_pairs(key, val, k, bits_of(static_cast<unsigned long long>(n - 1)), sws, sws_bytes, st);
+            if (s != HLN_OK) return s;
+            hipLaunchKernelGGL(k_take, dim3(grid_for(k)), dim3(256), 0, st, k, val, sc, ids, score, count);
+        }
     } else {
         hipLaunchKernelGGL(k_chunk_sums, dim3(gc), dim3(64), 0, st, n, sc, part);
         hipLaunchKernelGGL(k_mean, dim3(1), dim3(64), 0, st, n, part, mean);

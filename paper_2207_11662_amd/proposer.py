@@ -114,11 +114,14 @@ class Query:
         features(layers, psi_outs, X=self.X, stream=stream)
 
     def candidates_from(self, score: torch.Tensor, stream=None):
-        L.hln_topk(score, self.n_cand, ids=self.cand, ws=self.ws_topk, stream=stream)
+        """The n_cand best-scored vertices, as ascending ids."""
+        L.hln_topk(score, self.n_cand, ids=self.cand, ws=self.ws_topk, stream=stream, as_set=True)
 
     def refine(self, stream=None):
         """Exact closeness of the candidates on the AND graph, then their
-        top k (positions into the candidate list in self.pos)."""
+        top k (positions into the candidate list in self.pos).  The
+        candidates are in ascending id order, so ties in exact closeness
+        are broken by vertex id, as in the exhaustive ranking."""
         L.hln_closeness_layer(self.g, self.cand[:self.n_cand], width_bits=self.width, out=self.bfs,
                               ws=self.ws_bfs, stream=stream)
         L.hln_topk(self.bfs["cc"], self.k, ids=self.pos, ws=self.ws_topk, stream=stream)

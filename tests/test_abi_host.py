@@ -99,7 +99,7 @@ def test_select_argument_checks():
     assert args(0, 2, 5) == HLN_EINVAL                    # WF ranks one graph
     assert args(0, 1, 101) == HLN_EINVAL                  # k > n
     assert args(0, 1, -2) == HLN_EINVAL
-    assert args(2, 2, 5) == HLN_EINVAL                    # naive needs k = -1
+    assert args(2, 2, 101) == HLN_EINVAL                  # naive top-k: k > n
     assert args(1, 2, 5, ws - 1) == HLN_ENOMEM
 
 
@@ -183,3 +183,71 @@ def test_batched_and_argument_checks():
     assert b"problem 1" in L.hln_last_error()
     assert L.hln_compose_and_batch(None, 0, None, 0, None) == 0
     assert L.hln_compose_and_batch(None, -1, None, 0, None) == HLN_EINVAL
+
+
+def _resource_report():
+    """The compiler's resource-usage remarks for hln_msbfs.hip (written by
+    the build next to the objects; compiled here if missing)."""
+    from paper_2207_11662_amd import build as B
+    if not os.path.exists(B.RESOURCE_REPORT):
+        os.makedirs(B.BUILD, exist_ok=True)
+        B._compile(os.path.join(B.CSRC, "hln_msbfs.hip"))
+    with open(B.RESOURCE_REPORT) as f:
+        return f.read()
+
+
+def closeness_kernels_from_report():
+    """{(kind, NW, BLOCK, PS): {'VGPRs', 'LDS', 'occ'}} for k_closeness and
+    k_closeness_multi, from the compiler's remarks."""
+    out, cur = {}, None
+    for line in _resource_report().splitlines():
+        m = re.search(r"Function Name: \S*?(k_closeness(?:_multi)?)ILi(\d+)ELi(\d+)(?:ELb([01]))?E", line)
+        if m:
+            cur = (m.group(1), int(m.group(2)), int(m.group(3)), int(m.group(4) or 0))
+            out[cur] = {}
+            continue
+        if "Function Name" in line:
+            cur = None
+            continue
+        m = re.search(r"remark:\s+(VGPRs|AGPRs|LDS Size \[bytes/block\]|Occupancy \[waves/SIMD\]): (\d+)", line)
+        if m and cur:
+            key = {"VGPRs": "VGPRs", "AGPRs": "AGPRs", "LDS Size [bytes/block]": "LDS",
+                   "Occupancy [waves/SIMD]": "occ"}[m.group(1)]
+            out[cur][key] = int(m.group(2))
+    return out
+
+
+def test_residency_bound_matches_the_compiler():
+    """The co-residency bound the persistent launches are held to
+    (hln_resident_blocks: VGPRs and LDS against CDNA4's register file and
+    LDS) equals, for every closeness kernel the library builds, the blocks
+    per compute unit that the compiler's own occupancy figure allows
+    (waves per SIMD / wave slots a block takes per SIMD).  The 256-thread
+    kernels use 135-190 VGPRs: at most 3 waves per SIMD, so 3 blocks per
+    compute unit, not the 7 an occupancy answer once claimed."""
+    L = P.lib()
+    ks = closeness_kernels_from_report()
+    assert len(ks) >= 42, len(ks)
+    for (kind, nw, block, ps), r in sorted(ks.items()):
+        assert r.get("AGPRs", 0) == 0
+        slots = ((block + 63) // 64 + 3) // 4
+        want = r["occ"] // slots
+        got = L.hln_resident_blocks(r["VGPRs"], r["LDS"], block)
+        assert got == want, (kind, nw, block, ps, r, got)
+        assert got >= 1, (kind, nw, block, ps)
+    # the 1024-thread kernels the library launches by default: one block per CU
+    assert all(L.hln_resident_blocks(r["VGPRs"], r["LDS"], b) == 1 for (k, nw, b, ps), r in ks.items() if b == 1024)
+    assert all(L.hln_resident_blocks(r["VGPRs"], r["LDS"], b) <= 3 for (k, nw, b, ps), r in ks.items() if b == 256)
+
+
+def test_resident_blocks_arithmetic():
+    L = P.lib()
+    assert L.hln_resident_blocks(64, 0, 256) == 8          # 8 waves per SIMD, one slot each
+    assert L.hln_resident_blocks(72, 0, 256) == 7
+    assert L.hln_resident_blocks(128, 0, 1024) == 1        # 4 waves per SIMD, a block takes 4
+    assert L.hln_resident_blocks(129, 0, 1024) == 0        # 136 VGPRs: 3 waves per SIMD
+    assert L.hln_resident_blocks(137, 0, 256) == 3
+    assert L.hln_resident_blocks(24, 40 * 1024, 64) == 4   # LDS-bound
+    assert L.hln_resident_blocks(24, 0, 64) == 8
+    assert L.hln_resident_blocks(-1, 0, 64) == 0
+    assert L.hln_resident_blocks(64, 0, 2048) == 0

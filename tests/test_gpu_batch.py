@@ -183,3 +183,127 @@ def test_plan_set_width_pins_the_choice():
         with pytest.raises(P.HlnError):
             plan.set_width(*bad)
     assert plan.width(3000) == 1024
+
+
+def check_listed(gnp, sources, outs, tag):
+    for i, ((rp, ci), src, o) in enumerate(zip(gnp, sources, outs)):
+        n = len(rp) - 1
+        if src is None:
+            S, R = O.bfs_sums(rp, ci)
+        else:
+            s = src.cpu().numpy()
+            if len(s) == 0:
+                continue
+            S, R = O.bfs_sums(rp, ci, sources=s)
+        cc = O.closeness_wf(n, S, R)
+        k = len(S)
+        assert np.array_equal(o["S"][:k].cpu().numpy(), S), (tag, i)
+        assert np.array_equal(o["R"][:k].cpu().numpy(), R), (tag, i)
+        assert np.array_equal(o["cc"][:k].cpu().numpy().view(np.int64), cc.view(np.int64)), (tag, i)
+
+
+def listed_case(seed):
+    """Graphs of many sizes, some with listed sources (hubs among them,
+    counts below, at and above one batch of every width, an empty list, a
+    whole-vertex-set list), the rest with all their vertices."""
+    sizes = [40, 700, 3000, 9000, 20000, 70000, 5000, 1200]
+    gnp = mixed_graphs(seed, sizes)
+    h = C.config2(scale=0.05)
+    gnp.append(csr_np(h.n, *h.layers[0]))
+    rng = np.random.default_rng(seed)
+    counts = [40, 65, None, 513, 4097, 300, 0, None, 2000]
+    sources = []
+    for (rp, ci), k in zip(gnp, counts):
+        n = len(rp) - 1
+        if k is None:
+            sources.append(None)
+            continue
+        hubs = np.argsort(-np.diff(rp))[:min(5, k)]
+        rest = rng.choice(n, size=min(n, k + 10), replace=False)
+        src = np.unique(np.concatenate([hubs, rest]))[:k]
+        rng.shuffle(src)                     # outputs follow the caller's order
+        sources.append(torch.from_numpy(src.astype(np.int32)).cuda())
+    return gnp, sources
+
+
+def test_batch_listed_sources():
+    """hln_closeness_batch with per-graph listed sources (outputs indexed by
+    list position) next to all-source graphs: one call, one persistent
+    launch per (width, mode) group; against the oracle."""
+    gnp, sources = listed_case(11)
+    graphs = [graph_dev(P, rp, ci) for rp, ci in gnp]
+    for plan_kind in ("untuned", "pinned512", "pinned4096"):
+        plan = P.Plan()
+        if plan_kind != "untuned":
+            w = int(plan_kind[6:])
+            for g in graphs:
+                plan.set_width(g.n, w)
+        say("listed batch", plan_kind, [None if s is None else s.numel() for s in sources])
+        outs = P.Plan.outputs_listed(graphs, sources)
+        plan.run(graphs, outs, sources=sources)
+        torch.cuda.synchronize()
+        P.device_status()
+        check_listed(gnp, sources, outs, plan_kind)
+        coop, ordinary = plan.launch_paths()
+        assert coop >= 1 and ordinary == 0
+
+
+def test_batch_listed_capture_replay():
+    gnp, sources = listed_case(12)
+    graphs = [graph_dev(P, rp, ci) for rp, ci in gnp]
+    plan = P.Plan()
+    outs = P.Plan.outputs_listed(graphs, sources)
+    ws = P.workspace(plan.workspace_size(graphs))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan.capture(graphs, outs, ws, stream, sources=sources)
+    for rep in range(2):
+        for o in outs:
+            o["S"].fill_(-1)
+            o["R"].fill_(-1)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            plan.replay(stream)
+        stream.synchronize()
+        P.device_status()
+        check_listed(gnp, sources, outs, "replay%d" % rep)
+    # a second capture of another batch into a graph of the caller's, with a
+    # staging buffer of its own: the plan's first graph still replays right
+    plan.reserve(graphs[:3])
+    outs2 = P.Plan.outputs_listed(graphs[:3], sources[:3])
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g2):
+        plan.run(graphs[:3], outs2, ws=ws, sources=sources[:3])
+    g2.replay()
+    torch.cuda.synchronize()
+    check_listed(gnp[:3], sources[:3], outs2, "caller-graph")
+    for o in outs:
+        o["S"].fill_(-1)
+    with torch.cuda.stream(stream):
+        plan.replay(stream)
+    stream.synchronize()
+    P.device_status()
+    check_listed(gnp, sources, outs, "replay-after-second-capture")
+
+
+def test_batch_listed_argument_errors():
+    gnp, sources = listed_case(13)
+    graphs = [graph_dev(P, rp, ci) for rp, ci in gnp]
+    plan = P.Plan()
+    outs = P.Plan.outputs_listed(graphs, sources)
+    bad = list(sources)
+    bad[0] = torch.arange(graphs[0].n + 1, dtype=torch.int32, device="cuda")      # n_src > n
+    with pytest.raises(P.HlnError):
+        plan.run(graphs, outs, sources=bad)
+    outs_h2 = [dict(o) for o in outs]
+    outs_h2[0]["h2"] = torch.empty(graphs[0].n, dtype=torch.int32, device="cuda")   # h2 with listed sources
+    with pytest.raises(P.HlnError) as e:
+        plan.run(graphs, outs_h2, sources=sources)
+    assert "h2" in str(e.value)
+    # capturing without reserved staging is refused
+    g = torch.cuda.CUDAGraph()
+    with pytest.raises(P.HlnError):
+        with torch.cuda.graph(g):
+            plan.run(graphs, outs, sources=sources)
+    torch.cuda.synchronize()
+    P.device_status()

@@ -119,10 +119,11 @@ def test_determinism():
 
 
 def test_config2_full_size_sampled():
-    """Full-size config-2 layer in the benchmark's launch configuration
-    (all sources, W = 512): sampled vertices against one oracle BFS each (by
-    symmetry S[v] is the BFS sum from v), R against union-find components
-    of every vertex."""
+    """Full-size config-2 layers at W = 512 (the narrower code path: 32-bit
+    word masks, lane groups of 8; the benchmark's own W = 4096 launch is
+    compared on every vertex in test_gpu_fullsize.py): sampled vertices
+    against one oracle BFS each (by symmetry S[v] is the BFS sum from v), R
+    against the connected components of every vertex."""
     import scipy.sparse as sp
     from scipy.sparse.csgraph import connected_components
     h = C.config2()

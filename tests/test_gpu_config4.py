@@ -1,8 +1,10 @@
 """Config 4 at full size: 6 R-MAT layers over 1,000,000 vertices and their
 AND graph, 16,384 seeded sources per graph, listed-source closeness at
-W = 512 (the launch configuration bench.py times).  Sampled sources are
+W = 512: the 7 graphs through one batched call (the launch configuration
+bench.py times) and one single-graph call each.  Sampled sources are
 checked against one oracle BFS each (S, R bit-exact, closeness bit-exact);
-R of every source is checked against the connected components."""
+R of every source is checked against the connected components; the batched
+and single-graph outputs are identical."""
 import numpy as np
 import pytest
 import torch
@@ -36,14 +38,25 @@ def test_config4_listed_sources_sampled(cfg4):
     dev_layers = PR.upload_homln(h)
     g_and = P.hln_compose_and(dev_layers).trimmed()
     graphs = dev_layers + [g_and]
+    srcs = [C.config4_sources(gi, np.diff(rp)) for gi, (rp, _) in enumerate(host)]
+    dsrc = [to_dev(s) for s in srcs]
+    say("batched call: 7 graphs, listed sources, W = 512")
+    plan = P.Plan()
+    plan.set_width(n, 512)
+    bouts = P.Plan.outputs_listed(graphs, dsrc)
+    plan.run(graphs, bouts, sources=dsrc)
+    torch.cuda.synchronize()
+    P.device_status()
     rng = np.random.default_rng(44)
     for gi, (g, (rp, ci)) in enumerate(zip(graphs, host)):
         assert g.nnz == len(ci)
-        src = C.config4_sources(gi, np.diff(rp))
+        src = srcs[gi]
         say("graph", gi, "sources", len(src))
-        out = P.hln_closeness_layer(g, sources=to_dev(src), width_bits=512)
+        out = P.hln_closeness_layer(g, sources=dsrc[gi], width_bits=512)
         torch.cuda.synchronize()
         P.device_status()
+        for key in ("S", "R", "cc"):
+            assert torch.equal(bouts[gi][key], out[key]), (gi, key)
         S_g = out["S"].cpu().numpy()
         R_g = out["R"].cpu().numpy()
         cc_g = out["cc"].cpu().numpy()

@@ -221,10 +221,15 @@ def test_topk_and_rank_labels(n, dtype, ties):
     s = s.astype(np.float64 if dtype == torch.float64 else np.float32)
     sd = torch.from_numpy(s).cuda()
     order = ref_order(s)
-    for k in sorted({0, 1, n // 2, n}):
+    for k in sorted({0, 1, 2, n // 2, n}):
+        if k > n:
+            continue
         ids = P.hln_topk(sd, k)
         torch.cuda.synchronize()
         assert np.array_equal(ids.cpu().numpy(), order[:k]), (n, k)
+        ids_set = P.hln_topk(sd, k, as_set=True)          # the same set, ascending ids
+        torch.cuda.synchronize()
+        assert np.array_equal(ids_set.cpu().numpy(), np.sort(order[:k])), (n, k)
     lab = P.hln_rank_labels(sd)
     torch.cuda.synchronize()
     exp = log_rank(s)

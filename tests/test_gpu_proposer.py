@@ -57,14 +57,18 @@ def test_query_returns_exact_values_of_its_candidates():
     (rp, ci), cc = and_truth(h5)
     cand = q.cand[:n_cand].cpu().numpy()
     assert len(set(cand.tolist())) == n_cand
+    # the candidates are the MLP's top n_cand, in ascending id order
+    assert np.all(np.diff(cand) > 0)
+    y = q.y.cpu().numpy()
+    assert np.array_equal(cand, np.sort(np.lexsort((np.arange(h5.n), -y.astype(np.float64)))[:n_cand]))
     # exact closeness of every candidate, bit for bit
     S, R = O.bfs_sums(rp, ci, sources=cand)[:2]
     cc_cand = O.closeness_wf(h5.n, S, R)
     assert np.array_equal(q.bfs["cc"].cpu().numpy().view(np.int64), cc_cand.view(np.int64))
     assert np.array_equal(cc_ids.view(np.int64), cc[ids].view(np.int64))
-    # the answer is the exact top k of the candidates (ties by position)
-    order = np.lexsort((np.arange(n_cand), -cc_cand))[:k]
-    assert np.array_equal(ids, cand[order])
+    # the answer is the exact top k of the candidates, ties by vertex id (the
+    # oracle's ranking of the candidates, which are in ascending id order)
+    assert np.array_equal(ids, cand[O.topk_desc(cc_cand, k)])
     truth = np.lexsort((np.arange(h5.n), -cc))[:k]
     prec = len(set(ids.tolist()) & set(truth.tolist())) / k
     thr = cc[truth[-1]]

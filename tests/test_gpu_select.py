@@ -73,6 +73,11 @@ def test_cc2_and_naive(ties):
         ccs = [O.closeness_wf(n, s, x) for s, x in sums]
         ids, _ = select(P.HLN_RANK_NAIVE, n, S_list, R_list, -1)
         assert np.array_equal(ids, O.naive(n, ccs))
+        for k in (0, 1, n // 10, n // 2, n):
+            say("naive top-k", n, r, k)
+            ids, sc = select(P.HLN_RANK_NAIVE, n, S_list, R_list, k)
+            assert np.array_equal(ids, O.naive_topk(n, ccs, k)), k
+            assert np.all(sc == 0.0)
 
 
 def test_end_to_end_config1():
