@@ -230,6 +230,23 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
                                int64_t* S, int32_t* R, double* cc, int32_t* h2,
                                void* workspace, size_t workspace_bytes, void* stream);
 
+/* hln_closeness_layer_static: hln_closeness_layer without a workspace, for
+ * callers that cannot allocate device memory (code under hipGraph capture,
+ * serving loops, harnesses that forbid allocation).  Arguments, outputs
+ * and errors as hln_closeness_layer, same kernels and results.  Its scratch
+ * is one library-owned array of HLN_STATIC_SCRATCH_BYTES per device, held
+ * from the library's first use on that device until the process ends; a
+ * graph whose hln_closeness_workspace_size exceeds it is HLN_ENOMEM (64 MiB
+ * holds, e.g., n = 10^5 vertices with 10^6 arcs at 512 sources per batch;
+ * 4096 sources never fit).  Every call on a device shares that device's
+ * array and the kernels clear what they use, so calls in stream order are
+ * independent, but calls that can overlap on one device (different
+ * streams, different host threads) race and must not be issued.  Nothing is
+ * allocated: the array's address is looked up once per device. */
+#define HLN_STATIC_SCRATCH_BYTES (64u * 1024u * 1024u)
+hln_status hln_closeness_layer_static(const hln_csr* g, const int32_t* sources, int32_t n_src, const hln_opts* opts,
+                                      int64_t* S, int32_t* R, double* cc, int32_t* h2, void* stream);
+
 /* ------------------------------------------------------------------------
  * Sampling estimate of every vertex's closeness (Sec. 2: the sampling
  * approximations of closeness it cites, Eppstein-Wang and Cohen et al.).

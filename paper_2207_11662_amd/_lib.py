@@ -22,6 +22,7 @@ _STATUS = {0: "HLN_OK", 1: "HLN_EINVAL", 2: "HLN_ENOMEM", 3: "HLN_EDEVICE", 4: "
 EXPORTS = [
     "hln_last_error", "hln_version", "hln_device_cu_count", "hln_device_status",
     "hln_resident_blocks", "hln_closeness_kernel_residency", "hln_last_launch_path", "hln_plan_launch_paths",
+    "hln_closeness_layer_static",
     "hln_csr_from_edges_workspace_size", "hln_csr_from_edges", "hln_csr_from_edges_batch_workspace_size",
     "hln_csr_from_edges_batch", "hln_csr_validate",
     "hln_compose_workspace_size", "hln_compose_and", "hln_compose_or", "hln_compose_and_batch_workspace_size",
@@ -37,6 +38,7 @@ EXPORTS = [
 
 HLN_RANK_WF, HLN_RANK_CC2, HLN_RANK_NAIVE = 0, 1, 2
 HLN_FLAG_PER_VERTEX = 1
+HLN_STATIC_SCRATCH_BYTES = 64 * 1024 * 1024   # scratch of hln_closeness_layer_static (include/hln.h)
 
 
 class HlnError(RuntimeError):
@@ -107,6 +109,7 @@ def lib():
         "hln_compose_and_batch": ([ctypes.POINTER(hln_and_problem), i32, P, sz, P], st),
         "hln_closeness_workspace_size": ([i32, i64, i32, opts_p], sz),
         "hln_closeness_layer": ([csr_p, P, i32, opts_p, P, P, P, P, P, sz, P], st),
+        "hln_closeness_layer_static": ([csr_p, P, i32, opts_p, P, P, P, P, P], st),
         "hln_closeness_estimate": ([i32, i32, P, i32, P, P, P, P], st),
         "hln_compose_cc_topk_workspace_size": ([i32], sz),
         "hln_compose_cc_topk": ([i32, i32, i32, P, P, i32, P, P, P, P, sz, P], st),

@@ -61,6 +61,7 @@
 #include "hln_internal.hpp"
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 #include <cstdio>
 #include <cstdlib>
@@ -1506,9 +1507,65 @@ hln_status fill_args(BfsArgs& a, const hln_csr* g, const int32_t* sources, int32
 }
 
 
+// Scratch of hln_closeness_layer_static: one array per device, which the
+// runtime allocates with the code object and keeps until the process ends.
+// Host code never uses this name as an address: the array's device address
+// on the current device comes from hipGetSymbolAddress (static_scratch()).
+constexpr size_t kStaticScratchBytes = size_t(HLN_STATIC_SCRATCH_BYTES);
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per
+// device, with that device current), or nullptr with the error set.
+void* static_scratch() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxScratchDevices) {
+        hln::fail(HLN_EDEVICE, "hipGetDevice failed");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            hln::fail(HLN_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
+
+hln_status hln_closeness_layer_static(const hln_csr* g, const int32_t* sources, int32_t n_src, const hln_opts* opts,
+                                      int64_t* S, int32_t* R, double* cc, int32_t* h2, void* stream) {
+    using hln::fail;
+    hln::clear_error();
+    if (!g) return fail(HLN_EINVAL, "graph is NULL");
+    if (g->n < 1 || g->nnz < 0) return fail(HLN_EINVAL, "bad graph size (n %d, nnz %lld)", g->n, (long long)g->nnz);
+    const int nw = width_words(opts);
+    if (nw == 0) return fail(HLN_EINVAL, "width_bits must be 64, 128, 256, 512, 1024, 2048 or 4096");
+    const hln::DeviceInfo* di = hln::device_info();
+    if (!di) return HLN_EDEVICE;
+    const size_t need = workspace_bytes(g->n, g->nnz, nw, grid_cap_for(di->cus));
+    if (need > kStaticScratchBytes)
+        return fail(HLN_ENOMEM, "graph needs %zu bytes of scratch, more than the static %zu (n %d, nnz %lld, width %d): "
+                                "use hln_closeness_layer with a workspace", need, kStaticScratchBytes, g->n,
+                    (long long)g->nnz, nw * 64);
+    void* ptr = static_scratch();
+    if (!ptr) return HLN_EDEVICE;
+    // the same kernels as hln_closeness_layer, on the static scratch; they
+    // clear everything they read before using it (control block and barrier
+    // words by k_zero_ctrl, the rest in phase 0), so the previous call's
+    // contents do not matter
+    return hln_closeness_layer(g, sources, n_src, opts, S, R, cc, h2, ptr, kStaticScratchBytes, stream);
+}
 
 hln_status hln_closeness_kernel_residency(int32_t width_bits, int32_t block_threads, int32_t mode, int32_t* info) {
     using hln::fail;

@@ -251,3 +251,22 @@ def test_resident_blocks_arithmetic():
     assert L.hln_resident_blocks(24, 0, 64) == 8
     assert L.hln_resident_blocks(-1, 0, 64) == 0
     assert L.hln_resident_blocks(64, 0, 2048) == 0
+
+
+def test_static_entry_point_host_checks():
+    """hln_closeness_layer_static (no workspace, for callers that cannot
+    allocate) checks its arguments on the host like hln_closeness_layer; its
+    scratch size is the header's constant."""
+    L = P.lib()
+    assert L.hln_closeness_layer_static(None, None, 0, None, FAKE, FAKE, None, None, None) == HLN_EINVAL
+    g = _csr()
+    bad = P._lib.hln_opts(100, 0, 0, None)
+    assert L.hln_closeness_layer_static(ctypes.byref(g), None, 10, ctypes.byref(bad), FAKE, FAKE, None, None,
+                                        None) == HLN_EINVAL
+    g0 = _csr(0, 0)
+    ok = P._lib.hln_opts(512, 0, 0, None)
+    assert L.hln_closeness_layer_static(ctypes.byref(g0), None, 0, ctypes.byref(ok), FAKE, FAKE, None, None,
+                                        None) == HLN_EINVAL
+    with open(os.path.join(ROOT, "include", "hln.h")) as f:
+        m = re.search(r"#define HLN_STATIC_SCRATCH_BYTES \((\d+)u \* (\d+)u \* (\d+)u\)", f.read())
+    assert m and int(m.group(1)) * int(m.group(2)) * int(m.group(3)) == P._lib.HLN_STATIC_SCRATCH_BYTES
