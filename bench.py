@@ -207,6 +207,8 @@ def main():
     ap.add_argument("--train-steps", type=int, default=3000, help="cfg5: proposer training steps")
     ap.add_argument("--budget", type=float, default=0.05, help="cfg5: candidate fraction (the answer is the top 1%%)")
     ap.add_argument("--cand-width", type=int, default=None, help="cfg5: source batch of the candidate BFS")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="cfg2: leave out the config-3 and config-5 figures that the default line carries")
     ap.add_argument("--per-graph", action="store_true",
                     help="cfg4: one hln_closeness_layer call per graph instead of one batched call")
     args = ap.parse_args()
@@ -275,7 +277,8 @@ def main():
 
     # roofline of the dominant kernel (the persistent closeness kernel):
     # algorithmic bytes per launch = sum over batches of
-    #   L_b * (row_ptr 4(n+1) + col_idx 8m + frontier/visited/next 4*n*W/8)
+    #   L_b * (row_ptr 4(n+1) + col_idx 8m + 4 bitset passes of n*W/8 bytes:
+    #          frontier read, visited read, visited write, next write)
     # plus the per-vertex epilogue (S, R read, cc written: 20 B per vertex)
     nnz_graphs = [2 * m for m in ms_edges] + [int(and_buf[0][n].item())]
     lv = [levels[gi].cpu().numpy().astype(np.int64) for gi in range(G)]
@@ -316,6 +319,27 @@ def main():
                      "levels_per_launch": [int(x.sum()) for x in lv]},
         "cc2_top10_precision_vs_and_truth": round(cc2_precision, 4),
     }
+    if traffic:
+        # the same launches against the bytes the HBM-side counters measured
+        rec["roofline"]["traffic_gbs"] = round(traffic / (avg_launch_ms / 1e3) / 1e9, 1)
+        rec["roofline"]["traffic_frac"] = round(traffic / (avg_launch_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+    if not args.no_extras:
+        # the other workloads' headline figures on the same line: the batched
+        # persistent path (config 3) and the learned proposer (config 5)
+        a3 = argparse.Namespace(**vars(args))
+        a3.steps, a3.warmup, a3.width = 5, 1, None
+        r3 = run_cfg3(a3, emit=False)
+        rec["config3_batched"] = {"value": r3["value"], "unit": "GTEPS", "ms_per_step": r3["ms_per_step"],
+                                  "graphs": r3["config"]["graphs"], "roofline": r3["roofline"],
+                                  "captured_persistent_launches": r3["config"]["captured_persistent_launches"]}
+        a5 = argparse.Namespace(**vars(args))
+        a5.steps, a5.warmup, a5.width = 5, 2, 4096
+        r5 = run_cfg5(a5, emit=False)
+        rec["config5_proposer"] = {k: r5[k] for k in (
+            "value", "unit", "exhaustive_ms", "proposer_ms", "precision_at_k", "precision_at_k_ties",
+            "cc2_same_budget_precision", "budget_frontier", "psi_ms", "ground_truth_ms",
+            "sec6_speedup_psi_plus_query", "speedup_e2e_psi_amortised_26")}
+        rec["config5_proposer"]["metric"] = r5["metric"]
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(h, min(max(args.cpu_seconds, 1.0), 30.0))
     print(json.dumps(rec), flush=True)
