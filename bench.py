@@ -774,7 +774,7 @@ def run_composition(args):
     and naive CC-node sets (above-average, and top-10% for CC2 and naive)
     against the AND ground truth, for every
     HoMLN's full layer set and layer pairs (configs 1, 2, the first 16 HoMLNs
-    of config 3, config 5).  subsets: Psi once, then every subset of >= 2
+    of config 3, config 5, config 4).  subsets: Psi once, then every subset of >= 2
     layers of configs 2 and 5: per-subset AND and OR ground truth against
     per-subset CC2 (times from HIP events)."""
     import torch
@@ -785,7 +785,8 @@ def run_composition(args):
         out = {}
         plan = None
         for name, hs in [("config1", [C.config1()]), ("config2", [C.config2()]),
-                         ("config3[0:16]", [C.config3_homln(i) for i in range(16)]), ("config5", [C.config5()])]:
+                         ("config3[0:16]", [C.config3_homln(i) for i in range(16)]), ("config5", [C.config5()]),
+                         ("config4", [C.config4(workers=8)])]:
             t0 = time.perf_counter()
             recs = []
             for h in hs:

@@ -72,7 +72,10 @@ typedef struct {
                              mode batches only the vertices that have arcs (one without arcs
                              reaches only itself), by degree class (more than 64 arcs, 64, 32-63,
                              16-31, 8-15, 4-7, 2-3, 1) and ids ascending inside a class, so entries from
-                             ceil(#vertices with arcs / width_bits) on are not written */
+                             ceil(#vertices with arcs / width_bits) on are not written.  Listed
+                             sources are batched by the same classes (a source without arcs with
+                             the last), list positions ascending inside a class; outputs stay
+                             indexed by list position */
     int64_t* trace;       /* [dev] nullable, zero-filled by the caller: per level run (in order, over
                              all batches) 4 int64: s_memrealtime ticks (100 MHz) when the level's
                              barrier completed, vertices given new bits, new (vertex, source) pairs,

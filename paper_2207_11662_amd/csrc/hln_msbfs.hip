@@ -654,25 +654,35 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
     // degree class first and in id order inside a class (batches of hubs end
     // in fewer levels).  Block blk counts those of its range of ids per class
     // here and ranks them in phase 1.
+    // Listed sources are ranked the same way by their vertex's class, over
+    // list positions (positions ascending inside a class; a source without
+    // arcs goes with the last class): batches of hub sources end early
+    // there too, and the per-source outputs still go to the caller's
+    // positions.
     __shared__ int s_act[BLOCK / 64][kRankClasses];
     __shared__ int s_cls[kRankClasses];
-    const long long id_chunk = (static_cast<long long>(n) + nblk - 1) / nblk;
-    const long long id_lo = min(static_cast<long long>(blk) * id_chunk, static_cast<long long>(n));
-    const long long id_hi = min(id_lo + id_chunk, static_cast<long long>(n));
-    auto rank_class = [&](long long v) {
-        const int deg = a.row_ptr[v + 1] - a.row_ptr[v];
+    const long long n_items = a.listed ? static_cast<long long>(a.n_src) : static_cast<long long>(n);
+    const long long id_chunk = (n_items + nblk - 1) / nblk;
+    const long long id_lo = min(static_cast<long long>(blk) * id_chunk, n_items);
+    const long long id_hi = min(id_lo + id_chunk, n_items);
+    auto rank_class = [&](long long item) {
+        if (a.listed) {
+            const int v = a.sources[item];
+            if (static_cast<unsigned>(v) >= static_cast<unsigned>(n)) return -1;   // fault code 2, set above
+            const int deg = a.row_ptr[v + 1] - a.row_ptr[v];
+            return deg > 0 ? min(seg_class(deg, seg_len), kRankClasses - 1) : kRankClasses - 1;
+        }
+        const int deg = a.row_ptr[item + 1] - a.row_ptr[item];
         return deg > 0 ? min(seg_class(deg, seg_len), kRankClasses - 1) : -1;
     };
-    if (!a.listed) {
-        if (threadIdx.x < kRankClasses) s_cls[threadIdx.x] = 0;
-        __syncthreads();
-        for (long long v = id_lo + threadIdx.x; v < id_hi; v += BLOCK) {
-            const int c = rank_class(v);
-            if (c >= 0) atomicAdd(&s_cls[c], 1);
-        }
+    if (threadIdx.x < kRankClasses) s_cls[threadIdx.x] = 0;
+    __syncthreads();
+    for (long long v = id_lo + threadIdx.x; v < id_hi; v += BLOCK) {
+        const int c = rank_class(v);
+        if (c >= 0) atomicAdd(&s_cls[c], 1);
     }
     __syncthreads();
-    if (!a.listed && threadIdx.x < kRankClasses) a.bcount[blk * kRankClasses + threadIdx.x] = s_cls[threadIdx.x];
+    if (threadIdx.x < kRankClasses) a.bcount[blk * kRankClasses + threadIdx.x] = s_cls[threadIdx.x];
     if (threadIdx.x < kClasses && s_bins[threadIdx.x]) atomicAdd(&ctrl->bins[threadIdx.x], s_bins[threadIdx.x]);
     if (!gb.wait()) return false;
     if (load_agent_i32(a.fault) != 0) return false;              // uniform: read after the barrier
@@ -687,8 +697,8 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
         }
         store_agent_i32(&ctrl->n_seg, acc);
     }
-    if (!a.listed) {
-        // this block's first position in each class: all vertices of the
+    {
+        // this block's first position in each class: all items of the
         // classes before it, then those of the blocks before it
         __shared__ int s_tot[kRankClasses], s_before[kRankClasses], s_off[kRankClasses];
         if (threadIdx.x < kRankClasses) s_tot[threadIdx.x] = s_before[threadIdx.x] = 0;
@@ -805,7 +815,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
             for (long long i = tid; i < W; i += nthreads) {
                 bool in = false;
                 if (i < cnt) {
-                    const int src = a.listed ? a.sources[src0 + i] : a.perm[src0 + i];
+                    const int src = a.listed ? a.sources[a.perm[src0 + i]] : a.perm[src0 + i];
                     if (b == 0) {
                         const unsigned long long deg = static_cast<unsigned long long>(a.row_ptr[src + 1] - a.row_ptr[src]);
                         __hip_atomic_fetch_max(&ctrl->probe_key, (deg << 32) | (0xffffffffull - static_cast<unsigned long long>(i)),
@@ -855,7 +865,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                 for (long long i = tid; i < static_cast<long long>(n) * NW; i += nthreads) a.vis[i] = 0;
                 // only the words the sources' bits go to are cleared
                 for (long long i = tid; i < cnt; i += nthreads)
-                    a.bufA[static_cast<size_t>(a.sources[src0 + i]) * NW + (i >> 6)] = 0;
+                    a.bufA[static_cast<size_t>(a.sources[a.perm[src0 + i]]) * NW + (i >> 6)] = 0;
                 for (long long v = tid; v < n; v += nthreads) {
                     static_cast<Mask*>(a.flagA)[v] = 0;
                     if (!PER_SOURCE) {
@@ -875,7 +885,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                     }
                 if (!gb.wait()) return false;
                 for (long long i = tid_x; i < cnt; i += nthreads) {
-                    const int s = a.sources[src0 + i];
+                    const int s = a.sources[a.perm[src0 + i]];
                     const size_t w = static_cast<size_t>(s) * NW + (i >> 6);
                     atomicOr(reinterpret_cast<unsigned long long*>(&a.vis[w]), 1ull << (i & 63));
                     atomicOr(reinterpret_cast<unsigned long long*>(&a.bufA[w]), 1ull << (i & 63));
@@ -888,7 +898,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                 // pushed by many blocks instead of by one.  A vertex listed
                 // twice is noted twice (its words are ORed in twice: no change).
                 for (int i = threadIdx.x; i < cnt; i += BLOCK) {
-                    const int3 sg = vertex_segments(a, a.sources[src0 + i]);
+                    const int3 sg = vertex_segments(a, a.sources[a.perm[src0 + i]]);
                     long long j = (static_cast<long long>(blk) - sg.x) % static_cast<long long>(nblk);
                     if (j < 0) j += nblk;
                     for (; j < sg.y; j += nblk)
@@ -1204,8 +1214,9 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                     sR += shfl_xor_u64(sR, off);
                 }
                 if (lane == 0) {
-                    a.S[src0 + i] = static_cast<int64_t>(sS);
-                    a.R[src0 + i] = static_cast<int32_t>(1 + static_cast<int64_t>(sR));
+                    const int q = a.perm[src0 + i];          // the source's position in the caller's list
+                    a.S[q] = static_cast<int64_t>(sS);
+                    a.R[q] = static_cast<int32_t>(1 + static_cast<int64_t>(sR));
                 }
             }
             // the partials are rewritten only after the next batch's barriers
@@ -1428,7 +1439,7 @@ int width_words(const hln_opts* o) {
 
 constexpr int kSegLen = 64;
 
-size_t workspace_bytes(int32_t n, int64_t nnz, int nw, int grid_cap) {
+size_t workspace_bytes(int32_t n, int64_t nnz, int nw, int grid_cap, int32_t n_src) {
     using hln::Arena;
     size_t words = static_cast<size_t>(n) * nw;
     size_t seg_cap = static_cast<size_t>(n) + static_cast<size_t>(nnz / kSegLen) + 1;
@@ -1442,7 +1453,7 @@ size_t workspace_bytes(int32_t n, int64_t nnz, int nw, int grid_cap) {
     b += Arena::round(seg_cap * sizeof(uint32_t));                    // saturated segments
     b += Arena::round(static_cast<size_t>(n) * sizeof(uint32_t));    // probe component membership
     b += Arena::round(static_cast<size_t>(grid_cap) * 2 * 64 * nw * sizeof(int64_t));  // per-source partials
-    b += 2 * Arena::round(static_cast<size_t>(n) * sizeof(int32_t));   // perm, iperm
+    b += 2 * Arena::round(static_cast<size_t>(std::max(n, n_src)) * sizeof(int32_t));   // perm, iperm
     b += Arena::round(static_cast<size_t>(grid_cap) * kRankClasses * sizeof(int32_t)); // per-block class counts
     return b;
 }
@@ -1482,8 +1493,8 @@ hln_status fill_args(BfsArgs& a, const hln_csr* g, const int32_t* sources, int32
     a.S32 = ar.take<uint32_t>(n);
     a.nnz_cap = g->nnz;
     a.part = ar.take<int64_t>(static_cast<size_t>(grid_cap) * 2 * 64 * nw);
-    a.perm = ar.take<int32_t>(n);
-    a.iperm = ar.take<int32_t>(n);
+    a.perm = ar.take<int32_t>(static_cast<size_t>(std::max(n, n_src)));
+    a.iperm = ar.take<int32_t>(static_cast<size_t>(std::max(n, n_src)));
     a.bcount = ar.take<int32_t>(static_cast<size_t>(grid_cap) * kRankClasses);
     a.S = S;
     a.R = R;
@@ -1553,7 +1564,7 @@ hln_status hln_closeness_layer_static(const hln_csr* g, const int32_t* sources, 
     if (nw == 0) return fail(HLN_EINVAL, "width_bits must be 64, 128, 256, 512, 1024, 2048 or 4096");
     const hln::DeviceInfo* di = hln::device_info();
     if (!di) return HLN_EDEVICE;
-    const size_t need = workspace_bytes(g->n, g->nnz, nw, grid_cap_for(di->cus));
+    const size_t need = workspace_bytes(g->n, g->nnz, nw, grid_cap_for(di->cus), std::max(n_src, 0));
     if (need > kStaticScratchBytes)
         return fail(HLN_ENOMEM, "graph needs %zu bytes of scratch, more than the static %zu (n %d, nnz %lld, width %d): "
                                 "use hln_closeness_layer with a workspace", need, kStaticScratchBytes, g->n,
@@ -1617,12 +1628,11 @@ hln_status hln_closeness_kernel_residency(int32_t width_bits, int32_t block_thre
 }
 
 size_t hln_closeness_workspace_size(int32_t n, int64_t nnz, int32_t n_src, const hln_opts* opts) {
-    (void)n_src;
     int nw = width_words(opts);
-    if (nw == 0 || n < 0 || nnz < 0) return 0;
+    if (nw == 0 || n < 0 || nnz < 0 || n_src < 0) return 0;
     const hln::DeviceInfo* di = hln::device_info();
     int cus = di ? di->cus : 256;
-    return workspace_bytes(n, nnz, nw, grid_cap_for(cus));
+    return workspace_bytes(n, nnz, nw, grid_cap_for(cus), n_src);
 }
 
 hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t n_src, const hln_opts* opts,
@@ -1658,7 +1668,7 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
     const hln::DeviceInfo* di = hln::device_info();
     if (!di) return HLN_EDEVICE;
     const int grid_cap = grid_cap_for(di->cus);
-    const size_t need = workspace_bytes(g->n, g->nnz, nw, grid_cap);
+    const size_t need = workspace_bytes(g->n, g->nnz, nw, grid_cap, n_src);
     if (workspace_bytes_in < need)
         return fail(HLN_ENOMEM, "workspace too small: %zu < %zu bytes", workspace_bytes_in, need);
     if (n_src == 0 && !per_vertex) return HLN_OK;    // per-vertex mode still writes zero sums
@@ -1727,7 +1737,7 @@ size_t multi_slice_bytes(int32_t n, int64_t nnz, int width_bits) {
     const int nw = width_words(&o);
     if (nw == 0 || n < 1 || nnz < 0) return 0;
     const DeviceInfo* di = device_info();
-    return Arena::round(workspace_bytes(n, nnz, nw, grid_cap_for(di ? di->cus : 256)));
+    return Arena::round(workspace_bytes(n, nnz, nw, grid_cap_for(di ? di->cus : 256), n));
 }
 
 hln_status multi_fill(const hln_csr& g, const int32_t* sources, int32_t n_src, int64_t* S, int32_t* R, double* cc,

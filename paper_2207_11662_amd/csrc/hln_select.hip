@@ -179,15 +179,22 @@ __global__ void k_layer_cc(int n, const int64_t* __restrict__ S, const int32_t* 
         score[uu] = closeness_wf(n, S[uu], R[uu]);
 }
 
-// sequential sum of each id-chunk of 1024 values (one thread per chunk)
-__global__ void k_chunk_sums(int n, const double* __restrict__ x, double* part) {
-    const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+// sequential sum of each id-chunk of 1024 values: one wave per chunk loads
+// the chunk into LDS (coalesced), then one lane adds it up in id order (the
+// fixed summation shape, so the sum is the same bit for bit)
+__global__ __launch_bounds__(64) void k_chunk_sums(int n, const double* __restrict__ x, double* part) {
+    __shared__ double s_x[kChunk];
+    const long long c = blockIdx.x;
     const long long lo = c * kChunk;
     if (lo >= n) return;
-    const long long hi = lo + kChunk < n ? lo + kChunk : n;
-    double s = 0.0;
-    for (long long i = lo; i < hi; ++i) s += x[i];
-    part[c] = s;
+    const int len = static_cast<int>(lo + kChunk < n ? kChunk : n - lo);
+    for (int i = threadIdx.x; i < len; i += blockDim.x) s_x[i] = x[lo + i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < len; ++i) s += s_x[i];
+        part[c] = s;
+    }
 }
 
 // sequential sum of the chunk sums, divided by n (one thread)
@@ -371,7 +378,6 @@ hln_status hln_compose_cc_topk(int32_t mode, int32_t n, int32_t r, const int64_t
     void* sws = ar.base + ar.off;
     const size_t sws_bytes = workspace_bytes - ar.off;
     const unsigned g = grid_for(n);
-    const unsigned gc = grid_for(chunks, 64);
 
     if (mode == HLN_RANK_NAIVE && k >= 0) {
         // each layer's top k by its own closeness (ties by id), counted per
@@ -399,7 +405,7 @@ hln_status hln_compose_cc_topk(int32_t mode, int32_t n, int32_t r, const int64_t
     if (mode == HLN_RANK_NAIVE) {
         for (int l = 0; l < r; ++l) {
             hipLaunchKernelGGL(k_layer_cc, dim3(g), dim3(256), 0, st, n, L.S[l], L.R[l], sc);
-            hipLaunchKernelGGL(k_chunk_sums, dim3(gc), dim3(64), 0, st, n, sc, part);
+            hipLaunchKernelGGL(k_chunk_sums, dim3(static_cast<unsigned>(chunks)), dim3(64), 0, st, n, sc, part);
             hipLaunchKernelGGL(k_mean, dim3(1), dim3(64), 0, st, n, part, mean);
             hipLaunchKernelGGL(k_flag_above, dim3(g), dim3(256), 0, st, n, sc, mean, l > 0 ? 1 : 0, flag);
         }
@@ -428,7 +434,7 @@ hln_status hln_compose_cc_topk(int32_t mode, int32_t n, int32_t r, const int64_t
             hipLaunchKernelGGL(k_take, dim3(grid_for(k)), dim3(256), 0, st, k, val, sc, ids, score, count);
         }
     } else {
-        hipLaunchKernelGGL(k_chunk_sums, dim3(gc), dim3(64), 0, st, n, sc, part);
+        hipLaunchKernelGGL(k_chunk_sums, dim3(static_cast<unsigned>(chunks)), dim3(64), 0, st, n, sc, part);
         hipLaunchKernelGGL(k_mean, dim3(1), dim3(64), 0, st, n, part, mean);
         hipLaunchKernelGGL(k_flag_above, dim3(g), dim3(256), 0, st, n, sc, mean, 0, flag);
         hln_status s = hln::prim::scan_exclusive<int32_t>(flag, pos, n, sws, sws_bytes, st);

@@ -96,7 +96,9 @@ def test_listed_sources(width):
     A = O.compose("and", [csr_np(h.n, *e) for e in h.layers])
     for (gr, gc), tag in [((rp, ci), "layer1"), (A, "and")]:
         for count in (1, 63, 64, 65, 300, h.n):
-            src = np.sort(rng.choice(h.n, size=count, replace=False)).astype(np.int32)
+            src = rng.choice(h.n, size=count, replace=False).astype(np.int32)   # any order: outputs follow it
+            if count in (63, 300):
+                src = np.sort(src)
             say("listed", tag, count, width)
             g = graph_dev(P, gr, gc)
             out = P.hln_closeness_layer(g, sources=to_dev(src), width_bits=width)
@@ -169,6 +171,35 @@ def test_levels_per_batch(width):
         act = act[np.lexsort((act, cls))]
         na = (len(act) + width - 1) // width
         ref = [1 + int(ecc[act[b * width:(b + 1) * width]].max()) for b in range(na)] + [0] * (nb - na)
+        assert lv.cpu().numpy().tolist() == ref
+
+
+@pytest.mark.parametrize("width", [64, 512, 2048, 4096])
+def test_levels_per_batch_listed(width):
+    """Listed sources are batched by their vertex's degree class (a source
+    without arcs with the last class), list positions ascending inside a
+    class: each batch's level count is 1 + the largest eccentricity of its
+    sources (oracle), and the per-source outputs stay at the caller's
+    positions."""
+    h = C.config1()
+    n = h.n
+    rng = np.random.default_rng(90 + width)
+    for rp, ci in [csr_np(n, *h.layers[0]), O.compose("and", [csr_np(n, *e) for e in h.layers])]:
+        src = rng.permutation(n)[:int(rng.integers(n // 2, n))].astype(np.int32)
+        k = len(src)
+        nb = (k + width - 1) // width
+        lv = torch.zeros(nb, dtype=torch.int32, device="cuda")
+        g = graph_dev(P, rp, ci)
+        out = P.hln_closeness_layer(g, sources=to_dev(src), width_bits=width, levels=lv)
+        torch.cuda.synchronize()
+        P.device_status()
+        S, R, _, ecc, _ = O.bfs_sums(rp, ci, sources=src, extras=True)
+        assert np.array_equal(out["S"].cpu().numpy(), S)
+        assert np.array_equal(out["R"].cpu().numpy(), R)
+        deg = np.diff(rp)[src]
+        cls = np.where(deg > 64, 0, np.where(deg > 0, 7 - np.floor(np.log2(np.maximum(deg, 1))).astype(np.int64), 7))
+        order = np.lexsort((np.arange(k), cls))
+        ref = [1 + int(ecc[order[b * width:(b + 1) * width]].max()) for b in range(nb)]
         assert lv.cpu().numpy().tolist() == ref
 
 
