@@ -142,34 +142,59 @@ def test_config3_full_size_sampled():
     """All 64 HoMLNs of config 3 at full size, in the bench's launch
     configuration (autotuned widths, the persistent graphs in one partitioned
     multi-graph launch): every layer's CSR and every AND graph equal the
-    oracle's; on every graph, 6 sampled vertices' S and R equal the oracle's
-    BFS from them; the CC2 top-10% sets of the four smallest HoMLNs equal the
+    oracle's; on every graph, 64 sampled vertices' S, R and closeness bits
+    equal the oracle's BFS from them and R of every vertex equals its
+    component's size; every vertex of every graph of seven HoMLNs (the four
+    smallest, whose graphs run as LDS tiles, and the three smallest with
+    graphs on the persistent kernel) and their CC2 top-10% sets equal the
     oracle's from its own all-source sums."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
     hs = C.config3()
     st = build_step(hs, tuned=True)
-    items, outs = st["items"], st["outs"]
-    say("graphs", len(st["all_graphs"]), "persistent", len(st["coop"]))
-    assert len(st["coop"]) > 100
+    items, outs, coop = st["items"], st["outs"], set(st["coop"])
+    say("graphs", len(st["all_graphs"]), "persistent", len(coop))
+    assert len(coop) > 100
     rng = np.random.default_rng(77)
-    o = 0
-    small = set(np.argsort([it["n"] for it in items])[:4].tolist())
+    # graph index ranges per HoMLN, and which HoMLNs get every vertex checked
+    first, o = [], 0
+    for it in items:
+        first.append(o)
+        o += it["nl"] + 1
+    order = np.argsort([it["n"] for it in items])
+    with_coop = [hi for hi in order if any(first[hi] + gi in coop for gi in range(items[hi]["nl"] + 1))]
+    full = set(order[:4].tolist()) | set(with_coop[:3])
+    say("every vertex for HoMLNs", sorted(int(x) for x in full))
     for hi, it in enumerate(items):
         h, n = it["h"], it["n"]
         layers = [O.csr_from_edges(n, eu, ev) for eu, ev in h.layers]
         csrs = layers + [O.compose("and", layers)]
         gs = it["graphs"] + [P.Graph(it["abuf"][0], it["abuf"][1], it["abuf"][1].numel())]
+        sums = []
         for gi, ((rp, ci), g) in enumerate(zip(csrs, gs)):
+            o = first[hi] + gi
             grp = g.row_ptr.cpu().numpy()
             assert np.array_equal(grp, rp), (hi, gi)
             assert np.array_equal(g.col_idx[:int(grp[-1])].cpu().numpy(), ci), (hi, gi)
-            src = np.sort(rng.choice(n, size=6, replace=False)).astype(np.int32)
-            S, R = O.bfs_sums(rp, ci, sources=src)
-            assert np.array_equal(outs[o + gi]["S"].cpu().numpy()[src], S), (hi, gi)
-            assert np.array_equal(outs[o + gi]["R"].cpu().numpy()[src], R), (hi, gi)
-        if hi in small:
-            sums = [O.bfs_sums(rp, ci) for rp, ci in layers]
-            est = O.cc2_est(n, [S for S, _ in sums], [R for _, R in sums])
+            S_g, R_g = outs[o]["S"].cpu().numpy(), outs[o]["R"].cpu().numpy()
+            cc_g = outs[o]["cc"].cpu().numpy()
+            if hi in full:
+                S, R = O.bfs_sums(rp, ci)
+                sums.append((S, R))
+                assert np.array_equal(S_g, S), (hi, gi)
+                assert np.array_equal(R_g, R), (hi, gi)
+                assert np.array_equal(cc_g.view(np.int64), O.closeness_wf(n, S, R).view(np.int64)), (hi, gi)
+            else:
+                src = np.sort(rng.choice(n, size=min(n, 64), replace=False)).astype(np.int32)
+                S, R = O.bfs_sums(rp, ci, sources=src)
+                assert np.array_equal(S_g[src], S), (hi, gi)
+                assert np.array_equal(R_g[src], R), (hi, gi)
+                assert np.array_equal(cc_g[src].view(np.int64), O.closeness_wf(n, S, R).view(np.int64)), (hi, gi)
+            adj = sp.csr_matrix((np.ones(len(ci), np.int8), ci, rp), shape=(n, n))
+            _, lab = connected_components(adj, directed=False)
+            assert np.array_equal(R_g, np.bincount(lab)[lab]), (hi, gi)
+        if hi in full:
+            est = O.cc2_est(n, [S for S, _ in sums[:-1]], [R for _, R in sums[:-1]])
             top = O.topk_asc_i64(est, it["k"])
             c = int(it["sel"][2].item())
             assert c == it["k"] and np.array_equal(it["sel"][0][:c].cpu().numpy(), top), hi
-        o += it["nl"] + 1
