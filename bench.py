@@ -521,7 +521,8 @@ def run_cfg3(args, emit=True):
                         "kernel": "k_closeness_multi (persistent multi-graph BFS, %d launch(es) per step at W = %s)"
                                   % (len(coop_widths), coop_widths),
                         "avg_batch_call_ms": round(dur * 1e3, 3),
-                        "algorithmic_bytes_per_step": int(coop_bytes)}}
+                        "algorithmic_bytes_per_step": int(coop_bytes),
+                        "traffic_frac": round(traffic / dur / 1e9 / HBM_PEAK_GBS, 4) if traffic and dur > 0 else None}}
     if emit:
         print(json.dumps(rec), flush=True)
     return rec
@@ -743,10 +744,10 @@ def run_cfg4(args):
     dur_total = sum(sum(d) for d in durations)
     achieved = sum(bytes_per_launch) * args.steps / dur_total / 1e9
     traffic = None
-    if os.path.exists(TRAFFIC_FILE_CFG4) and not batched:
+    if os.path.exists(TRAFFIC_FILE_CFG4):
         with open(TRAFFIC_FILE_CFG4) as f:
             tr = json.load(f)
-        if tr.get("kernel_sha") == kernel_hash() and tr.get("width") == W:
+        if tr.get("kernel_sha") == kernel_hash() and tr.get("width") == W and (tr.get("call") == "batched") == batched:
             traffic = tr.get("bytes_per_launch")
     rec = {"metric": METRIC, "value": round(sum(teps_den) * args.steps / elapsed / 1e9, 3), "unit": "GTEPS",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -760,6 +761,8 @@ def run_cfg4(args):
                       else "one hln_closeness_layer call per graph"},
            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                        "traffic_frac": (round(traffic / (dur_total / (launches * args.steps)) / 1e9 / HBM_PEAK_GBS, 4)
+                                         if isinstance(traffic, (int, float)) else None),
                         "kernel": "k_closeness_multi (7 graphs, listed sources)" if batched
                         else "k_closeness (persistent multi-source BFS, listed sources)",
                         "avg_launch_ms": round(dur_total / (launches * args.steps) * 1e3, 3),
