@@ -60,7 +60,7 @@ def test_config4_listed_sources_sampled(cfg4):
         S_g = out["S"].cpu().numpy()
         R_g = out["R"].cpu().numpy()
         cc_g = out["cc"].cpu().numpy()
-        pos = np.sort(rng.choice(len(src), size=24, replace=False))
+        pos = np.sort(rng.choice(len(src), size=160, replace=False))
         S, R = O.bfs_sums(rp, ci, sources=src[pos])
         cc = O.closeness_wf(n, S, R)
         assert np.array_equal(S_g[pos], S), gi

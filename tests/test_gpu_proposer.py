@@ -75,3 +75,43 @@ def test_query_returns_exact_values_of_its_candidates():
     prec_ties = float(np.mean(cc[ids] >= thr))
     say("n", h5.n, "candidates", n_cand, "k", k, "precision", prec, "tie-aware", prec_ties)
     assert prec_ties >= 0.3          # far above the 0.05 a random 5% candidate set gives
+
+
+@pytest.mark.timeout(900)
+def test_config5_precision_at_full_size():
+    """Config 5 at full size as the benchmark runs it: the MLP trained on
+    configs 1-3, 5% candidates, exact BFS of the candidates on the AND graph,
+    top 1% (2,000).  The answer's closeness values are the oracle's, and its
+    precision against the exhaustive ground truth (itself compared with the
+    oracle in test_gpu_fullsize.py) is at least 0.95, ties by vertex id."""
+    plan = P.Plan()
+    Xs, ys = [], []
+    for h in [C.config1(), C.config2()] + C.config3():
+        X, lab = PR.training_example(plan, h)
+        Xs.append(X)
+        ys.append(lab)
+    model = PR.Proposer(seed=0).fit(torch.cat(Xs), torch.cat(ys), steps=3000, lr=2e-3, batch=65536)
+    del Xs, ys
+    h5 = C.config5()
+    n = h5.n
+    layers = PR.upload_homln(h5)
+    outs = PR.psi(plan, layers)
+    g_and = P.hln_compose_and(layers).trimmed()
+    k = n // 100
+    q = PR.Query(g_and, n // 20, k, width_bits=4096)
+    q.run(model, layers, outs)
+    ex = P.hln_closeness_layer(g_and, None, width_bits=4096)
+    truth = P.hln_topk(ex["cc"], k)
+    torch.cuda.synchronize()
+    P.device_status()
+    ids, cc_ids = q.result()
+    truth = truth.cpu().numpy()
+    cc_all = ex["cc"].cpu().numpy()
+    assert np.array_equal(cc_ids.view(np.int64), cc_all[ids].view(np.int64))
+    # the answer's values against the oracle, one BFS per returned vertex
+    rp, ci = g_and.row_ptr.cpu().numpy(), g_and.col_idx.cpu().numpy()
+    S, R = O.bfs_sums(rp, ci, sources=ids.astype(np.int32))
+    assert np.array_equal(cc_ids.view(np.int64), O.closeness_wf(n, S, R).view(np.int64))
+    prec = len(set(ids.tolist()) & set(truth.tolist())) / k
+    say("config 5 precision@1% with 5% candidates:", prec)
+    assert prec >= 0.95
