@@ -212,8 +212,9 @@ hln_status hln_compose_and_batch(const hln_and_problem* problems, int32_t count,
  * normalisation used for disconnected graphs; one BFS per source).
  * ------------------------------------------------------------------------
  * sources [dev] NULL: every vertex is a source and the outputs are indexed
- *   by vertex (n_src must equal n).  Otherwise n_src distinct vertex ids and
- *   the outputs are indexed by position in `sources`.
+ *   by vertex (n_src must equal n), or, with n_src = 0, an empty list.
+ *   Otherwise n_src distinct vertex ids and the outputs are indexed by
+ *   position in `sources`.
  * S  [dev] int64: sum of hop distances to the reachable vertices.
  * R  [dev] int32: number of reachable vertices, the source included.
  * cc [dev] double, nullable: ((R-1)/S) * ((R-1)/(n-1)) rounded in that

@@ -1651,7 +1651,8 @@ hln_status hln_closeness_layer(const hln_csr* g, const int32_t* sources, int32_t
     if (n_src < 0) return fail(HLN_EINVAL, "n_src < 0");
     // per-vertex sums always take a list; an empty one may be NULL
     if (per_vertex && !sources && n_src > 0) return fail(HLN_EINVAL, "HLN_FLAG_PER_VERTEX needs listed sources");
-    if (!sources && !per_vertex && n_src != g->n)
+    // NULL with n_src == n is all-source; NULL with n_src == 0 an empty list (n >= 1)
+    if (!sources && !per_vertex && n_src != g->n && n_src != 0)
         return fail(HLN_EINVAL, "all-source mode needs n_src == n (%d != %d)", n_src, g->n);
     if ((sources || per_vertex) && h2) return fail(HLN_EUNSUPPORTED, "h2 is produced in all-source mode only");
     if (per_vertex && cc) return fail(HLN_EINVAL, "HLN_FLAG_PER_VERTEX gives sums only: cc must be NULL");

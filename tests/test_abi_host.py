@@ -58,6 +58,11 @@ def test_closeness_argument_checks():
     assert call(ws=ctypes.c_void_p(0x100001)) == HLN_EINVAL    # misaligned workspace
     g0 = _csr(0, 0)
     assert call(g=ctypes.byref(g0)) == HLN_EINVAL
+    # a bitset of n * W / 8 bytes must stay below 2^31 (32-bit buffer offsets)
+    big = _csr(1 << 22, 20)
+    w4096 = P._lib.hln_opts(4096, 0, 0, None)
+    assert call(g=ctypes.byref(big), n_src=1 << 22, opts=ctypes.byref(w4096)) == HLN_EUNSUPPORTED
+    assert b"2^31" in L.hln_last_error()
 
 
 def test_ingest_argument_checks():

@@ -1,5 +1,7 @@
 """Parity of hln_closeness_layer (HIP, through the C ABI) with the CPU oracle:
 S and R bit-exact, closeness bit-exact in FP64, 2-hop counts exact."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -53,6 +55,36 @@ def test_degenerate(width):
     for n, eu, ev in [(1, [], []), (5, [], []), (7, [2], [5])]:
         rp, ci = csr_np(n, np.array(eu, np.int64), np.array(ev, np.int64))
         check_all(n, rp, ci, width, "degenerate-n%d" % n)
+
+
+def test_empty_source_list():
+    """An empty source list (n_src = 0, with a NULL or a real pointer)
+    enqueues nothing and leaves the outputs alone; in per-vertex mode it
+    writes zero sums for every vertex."""
+    rp, ci = csr_np(9, np.array([0, 1, 2], np.int64), np.array([1, 2, 3], np.int64))
+    g = graph_dev(P, rp, ci)
+    L = P.lib()
+    o = P._lib.hln_opts(512, 0, 0, None)
+    S = torch.full((4,), -7, dtype=torch.int64, device="cuda")
+    R = torch.full((4,), -7, dtype=torch.int32, device="cuda")
+    need = P.closeness_workspace_size(9, len(ci), 0, 512)
+    ws = P.workspace(need)
+    gc = g.c()
+    real = to_dev(np.array([3], np.int32))
+    for src in (None, real.data_ptr()):
+        st = L.hln_closeness_layer(ctypes.byref(gc), src, 0, ctypes.byref(o), S.data_ptr(), R.data_ptr(), None, None,
+                                   ws.data_ptr(), ws.numel(), None)
+        assert st == 0, L.hln_last_error()
+    torch.cuda.synchronize()
+    P.device_status()
+    assert S.tolist() == [-7] * 4 and R.tolist() == [-7] * 4
+    out = P.hln_closeness_layer(g, sources=torch.empty(0, dtype=torch.int32, device="cuda"), width_bits=512)
+    assert out["S"].numel() == 0 and out["R"].numel() == 0 and out["cc"].numel() == 0
+    pv = P.hln_closeness_layer(g, sources=torch.empty(0, dtype=torch.int32, device="cuda"), width_bits=512,
+                               per_vertex=True)
+    torch.cuda.synchronize()
+    P.device_status()
+    assert pv["S"].cpu().tolist() == [0] * 9 and pv["R"].cpu().tolist() == [0] * 9
 
 
 @pytest.mark.parametrize("width", WIDTHS)
@@ -322,3 +354,53 @@ def test_saturation_probe_components(width):
     SQ, RQ = O.sample_sums(rp, ci, src)
     assert np.array_equal(pv["S"].cpu().numpy(), SQ)
     assert np.array_equal(pv["R"].cpu().numpy(), RQ)
+
+
+def test_largest_graph_at_width_4096():
+    """The largest vertex count W = 4096 allows: n = 2^22 - 1, so a bitset
+    is n * W / 8 = 2^31 - 512 bytes and the kernel's 32-bit buffer offsets
+    run almost to their end.  A sparse graph (a cycle through all but the
+    last 1,000 vertices, which stay isolated, plus random chords) with 4,100
+    listed sources in shuffled order: two batches, the second holding the
+    lowest-degree sources, among them isolated vertices at the very end of
+    the id range.  The oracle takes about 0.1 s of one core per source here,
+    so it checks 150 sampled list positions plus every position whose vertex
+    is one of the last ids; every isolated source has S = 0, R = 1 and
+    closeness 0.  One vertex more is refused (HLN_EUNSUPPORTED) before
+    anything is enqueued."""
+    n = (1 << 22) - 1
+    live = n - 1000
+    rng = np.random.default_rng(5)
+    base = np.arange(live, dtype=np.int64)
+    eu = np.concatenate([base, rng.integers(0, live, size=live)])
+    ev = np.concatenate([(base + 1) % live, rng.integers(0, live, size=live)])
+    keep = eu != ev
+    a, b = np.minimum(eu[keep], ev[keep]), np.maximum(eu[keep], ev[keep])
+    key = np.unique(a * n + b)
+    rp, ci = csr_np(n, key // n, key % n)
+    say("largest graph: n=%d arcs=%d" % (n, len(ci)))
+    tail = np.concatenate([np.arange(live - 5, live), np.arange(n - 5, n)])
+    src = np.unique(np.concatenate([rng.choice(live - 5, size=4090, replace=False), tail])).astype(np.int32)
+    rng.shuffle(src)
+    g = graph_dev(P, rp, ci)
+    out = P.hln_closeness_layer(g, sources=to_dev(src), width_bits=4096)
+    torch.cuda.synchronize()
+    P.device_status()
+    gS, gR, gcc = out["S"].cpu().numpy(), out["R"].cpu().numpy(), out["cc"].cpu().numpy()
+    iso = src >= live
+    assert iso.sum() == 5
+    assert np.all(gS[iso] == 0) and np.all(gR[iso] == 1) and np.all(gcc[iso] == 0.0)
+    pos = np.union1d(rng.choice(len(src), size=150, replace=False), np.nonzero(np.isin(src, tail))[0])
+    say("oracle: %d sampled sources" % len(pos))
+    S, R = O.bfs_sums(rp, ci, sources=src[pos])
+    assert np.array_equal(gS[pos], S)
+    assert np.array_equal(gR[pos], R)
+    assert np.array_equal(gcc[pos].view(np.int64), O.closeness_wf(n, S, R).view(np.int64))
+    del out
+    rp2 = np.append(rp, rp[-1]).astype(np.int32)           # one more (isolated) vertex: 2^22
+    g2 = P.Graph(to_dev(rp2), g.col_idx)
+    with pytest.raises(P.HlnError) as e:
+        P.hln_closeness_layer(g2, sources=to_dev(src[:10]), width_bits=4096)
+    assert e.value.status == 4          # HLN_EUNSUPPORTED
+    torch.cuda.synchronize()
+    P.device_status()
