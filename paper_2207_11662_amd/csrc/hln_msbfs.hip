@@ -212,7 +212,8 @@ struct BfsArgs {
     long long seg_cap;                // capacity of seg
     long long nnz_cap;                // arcs the caller declared (col_idx holds at least row_ptr[n] <= nnz_cap)
     int32_t* seg_first;               // n: index of the vertex's first segment
-    uint32_t* segsat;                 // seg_cap: 1 once the segment's vertex holds every bit it can get in the batch
+    uint32_t* segsat;                 // seg_cap: the level at which the segment's vertex came to hold every bit it
+                                      // can get in the batch (0: not yet)
     uint32_t* member;                 // n: 1 when the vertex lies in the probe source's component
     int64_t* part;                    // per-source mode: [grid][2][W] block partials
     int64_t* S;
@@ -381,11 +382,14 @@ __device__ __forceinline__ int3 finalize_vertex(const BfsArgs& a, const LevelBuf
     return make_int3(c, __popcll(static_cast<unsigned long long>(nmask)), sat);
 }
 
-// A saturated vertex: all its segments are skipped by later pull levels of
-// the batch (called by the lanes of its group).
+// A vertex saturated at level d: its segments record d, and later pull
+// levels of the batch read no ids, masks or frontier words for them (they
+// only clear the vertex's stale next-frontier word masks; at W = 4096 they
+// are left out altogether from level d + 3 on).  Called by the lanes of its
+// group.
 template <int LPV>
-__device__ __forceinline__ void mark_saturated(const BfsArgs& a, int first, int nseg, int gl) {
-    for (int j = gl; j < nseg; j += LPV) a.segsat[first + j] = 1u;
+__device__ __forceinline__ void mark_saturated(const BfsArgs& a, int first, int nseg, int gl, int d) {
+    for (int j = gl; j < nseg; j += LPV) a.segsat[first + j] = static_cast<uint32_t>(d);
 }
 
 // Gathering the frontier over a segment [lo, hi) for the word k of this
@@ -437,7 +441,6 @@ struct Gather {
         return ((cnt - 1) / LPV) * NW + ((cnt - 1) % LPV) / NPAR + 1;
     }
 
-    static constexpr int K0 = K;                         // the first chunk (issued with the visited word)
 
     // one chunk of KK gathers, starting at step q0, into v[] (no wait)
     template <int KK>
@@ -447,18 +450,20 @@ struct Gather {
         if constexpr (NW == 64) {
             // one group is the whole wave, so step t's neighbour id and mask are
             // wave-uniform: read them into scalar registers (no LDS round trip)
-            // and select each lane's word by the mask directly
+            // and select each lane's word by the mask directly.  Steps past the
+            // segment's end need no test: their id is -1, so their mask was
+            // loaded from an out-of-range offset and is zero (no lane loads).
+            (void)need;
             const uint64_t allowed = __ballot(!skip);
             const uint32_t koff = static_cast<uint32_t>(k) * 8u;
-            const int need_w = __builtin_amdgcn_readfirstlane(need);   // uniform: one group per wave
 #pragma unroll
             for (int q = 0; q < KK; ++q) {
                 const int t = q0 + q;
                 const int w = __builtin_amdgcn_readlane(cid[0], t);
                 const uint32_t mlo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(msk[0])), t));
                 const uint32_t mhi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(msk[0] >> 32)), t));
-                const uint64_t lanes = t < need_w ? (((static_cast<uint64_t>(mhi) << 32) | mlo) & allowed) : 0ull;
-                const uint32_t rowoff = static_cast<uint32_t>(w < 0 ? 0 : w) * (NW * 8u);
+                const uint64_t lanes = ((static_cast<uint64_t>(mhi) << 32) | mlo) & allowed;
+                const uint32_t rowoff = static_cast<uint32_t>(w) * (NW * 8u);
                 v[q] = buf_word(fr, select_lanes(lanes, rowoff + koff, kNoWord));
             }
             return;
@@ -484,24 +489,11 @@ struct Gather {
         return x;
     }
 
-    // the chunks after the first (steps K0 ...); skip as in round_or, from
-    // the OR so far
-    __device__ __forceinline__ static uint64_t rest_or(__amdgpu_buffer_rsrc_t fr, const int (&cid)[CH],
-                                                       const Mask (&msk)[CH], int k, int sub, int gbase,
-                                                       uint64_t vis_or_acc, int need) {
-        uint64_t x = 0;
-#pragma unroll
-        for (int q0 = K0; q0 < T; q0 += K) {
-            if (!__any(q0 < need)) break;
-            uint64_t v[K];
-            issue_chunk<K>(fr, cid, msk, k, sub, gbase, (vis_or_acc | x) == ~0ull, need, q0, v);
-            x |= or_all<K>(v);
-        }
-        return x;
-    }
-
     // skip: no gather at all in this round; later chunks also stop once
-    // prior | OR so far is all ones
+    // prior | OR so far is all ones.  At W = 4096 (one group per wave) a
+    // round's last chunk is issued at a quarter or half of its size when the
+    // segment needs no more further steps than that (a row of 1-2 arcs
+    // issues K / 4 gather instructions, one of 3-4 arcs K / 2, not K).
     __device__ __forceinline__ static uint64_t round_or(__amdgpu_buffer_rsrc_t fr, const int (&cid)[CH],
                                                         const Mask (&msk)[CH], int k, int sub, int gbase,
                                                         bool skip, int cnt, uint64_t prior) {
@@ -510,8 +502,23 @@ struct Gather {
 #pragma unroll
         for (int q0 = 0; q0 < T; q0 += K) {
             if (!__any(q0 < need)) break;
+            const bool sk = skip || (q0 > 0 && (prior | x) == ~0ull);
+            if constexpr (NW == 64 && K >= 4) {
+                if (!__any(q0 + K / 4 < need)) {
+                    uint64_t v[K / 4];
+                    issue_chunk<K / 4>(fr, cid, msk, k, sub, gbase, sk, need, q0, v);
+                    x |= or_all<K / 4>(v);
+                    break;
+                }
+                if (!__any(q0 + K / 2 < need)) {
+                    uint64_t v[K / 2];
+                    issue_chunk<K / 2>(fr, cid, msk, k, sub, gbase, sk, need, q0, v);
+                    x |= or_all<K / 2>(v);
+                    break;
+                }
+            }
             uint64_t v[K];
-            issue_chunk<K>(fr, cid, msk, k, sub, gbase, skip || (q0 > 0 && (prior | x) == ~0ull), need, q0, v);
+            issue_chunk<K>(fr, cid, msk, k, sub, gbase, sk, need, q0, v);
             x |= or_all<K>(v);
         }
         return x;
@@ -991,7 +998,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                             t_verts += 1;
                             const int3 sgv = vertex_segments(a, v);
                             if (gl == 0 && sgv.y > 0) frontier_note(s_fr, par, sgv.x, sgv.y, sgv.z * cw.y);
-                            if (cw.z) mark_saturated<kLpv>(a, sgv.x, sgv.y, gl);
+                            if (cw.z) mark_saturated<kLpv>(a, sgv.x, sgv.y, gl, d);
                         }
                     }
                 }
@@ -1020,7 +1027,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                             t_pairs += cw.x;
                             t_verts += 1;
                             if (gl == 0) frontier_note(s_fr, par, static_cast<int>(s), 1, (sg.z - sg.y) * cw.y);
-                            if (cw.z) mark_saturated<kLpv>(a, static_cast<int>(s), 1, gl);
+                            if (cw.z) mark_saturated<kLpv>(a, static_cast<int>(s), 1, gl, d);
                         }
                     } else {
                         // multi-segment row: merge, the last finisher finalises
@@ -1055,7 +1062,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                                 t_verts += 1;
                                 const int first = a.seg_first[v];
                                 if (gl == 0) frontier_note(s_fr, par, first, nseg, nseg * seg_len * cw.y);
-                                if (cw.z) mark_saturated<kLpv>(a, first, nseg, gl);
+                                if (cw.z) mark_saturated<kLpv>(a, first, nseg, gl, d);
                             }
                         }
                     }
@@ -1089,23 +1096,9 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                         finish(s1, sg, acc, vis_v, flag_old);
                     }
                 }
-                long long s = level1_ids ? n_seg : gid;
-                SegPre<NW> cur, nxt;
-                seg_prefetch<NW, PER_SOURCE>(B, rec_at(s), s < n_seg, sat_at(s), gl, cur);
-                seg_prefetch<NW, PER_SOURCE>(B, rec_at(s + ngroups), s + ngroups < n_seg, sat_at(s + ngroups), gl, nxt);
-                seg_flags<NW>(B, cur);
-                int4 rec2 = rec_at(s + 2 * ngroups);
-                bool sat2 = sat_at(s + 2 * ngroups);
-                while (s < n_seg) {
-                    const long long s1 = s + ngroups;
-                    const long long s2 = s1 + ngroups;
-                    const long long s3 = s2 + ngroups;
-                    const int4 rec3 = rec_at(s3);                                      // record, 3 ahead
-                    const bool sat3 = sat_at(s3);
-                    SegPre<NW> nn;
-                    seg_prefetch<NW, PER_SOURCE>(B, rec2, s2 < n_seg, sat2, gl, nn);    // ids, 2 ahead
-                    seg_flags<NW>(B, nxt);                                             // flags, 1 ahead
-
+                // one segment: the visited word and the frontier gathers, then
+                // its ending (cur holds what the pipeline prefetched for it)
+                auto visit = [&](long long s, const SegPre<NW>& cur) {
                     const int v = cur.sg.x;
                     const int nseg = cur.sg.w;
                     const size_t base = static_cast<size_t>(v) * NW + k;
@@ -1135,11 +1128,83 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                         }
                     }
                     finish(s, cur.sg, acc, vis_v, cur.flag_old);
-                    s = s1;
-                    cur = nxt;
-                    nxt = nn;
-                    rec2 = rec3;
-                    sat2 = sat3;
+                };
+                if constexpr (NW == 64) {
+                    // One group per wave: the wave takes its segments s = gid +
+                    // j * ngroups in windows of 64, lane j loading record and
+                    // saturation level of the window's segment j in one
+                    // instruction each, so no record is waited for inside the
+                    // sweep.  A segment saturated at level L still clears its
+                    // vertex's stale next-frontier word masks at levels L + 1
+                    // and L + 2 (no gathers); from L + 3 on it is left out.
+                    const int gid_u = __builtin_amdgcn_readfirstlane(static_cast<int>(gid));
+                    const int ng = static_cast<int>(ngroups);
+                    const int nsg = static_cast<int>(n_seg);
+                    const uint32_t dlev = static_cast<uint32_t>(d);
+                    for (int wb = level1_ids ? nsg : gid_u; wb < nsg; wb += 64 * ng) {
+                        const int my = wb + lane * ng;
+                        const bool ok = my < nsg;
+                        const uint32_t slev = buf_u32(B.segsat, ok ? static_cast<uint32_t>(my) * 4u : kNoWord);
+                        const int4 myrec = buf_i4(B.seg, ok ? static_cast<uint32_t>(my) * 16u : kNoWord);
+                        uint64_t todo = __ballot(ok && (slev == 0u || dlev <= slev + 2u));
+                        const uint64_t satm = __ballot(slev != 0u);
+                        // the next segment of the window into p (sp = nsg: none left)
+                        auto take = [&](SegPre<NW>& p, int& sp) {
+                            int4 rec = make_int4(0, 0, 0, 0);
+                            bool sat = false;
+                            sp = nsg;
+                            if (todo != 0) {
+                                const int j = __builtin_ctzll(todo);
+                                todo &= todo - 1;
+                                rec = make_int4(__builtin_amdgcn_readlane(myrec.x, j), __builtin_amdgcn_readlane(myrec.y, j),
+                                                __builtin_amdgcn_readlane(myrec.z, j), __builtin_amdgcn_readlane(myrec.w, j));
+                                sat = ((satm >> j) & 1ull) != 0;
+                                sp = wb + j * ng;
+                            }
+                            seg_prefetch<NW, PER_SOURCE>(B, rec, sp < nsg, sat, gl, p);
+                        };
+                        SegPre<NW> cur, nxt;
+                        int sc, sn;
+                        take(cur, sc);
+                        take(nxt, sn);
+                        seg_flags<NW>(B, cur);
+                        while (sc < nsg) {
+                            SegPre<NW> nn;
+                            int snn;
+                            take(nn, snn);                                 // ids, 2 ahead
+                            seg_flags<NW>(B, nxt);                         // flags, 1 ahead
+                            visit(sc, cur);
+                            sc = sn;
+                            cur = nxt;
+                            sn = snn;
+                            nxt = nn;
+                        }
+                    }
+                } else {
+                    long long s = level1_ids ? n_seg : gid;
+                    SegPre<NW> cur, nxt;
+                    seg_prefetch<NW, PER_SOURCE>(B, rec_at(s), s < n_seg, sat_at(s), gl, cur);
+                    seg_prefetch<NW, PER_SOURCE>(B, rec_at(s + ngroups), s + ngroups < n_seg, sat_at(s + ngroups), gl, nxt);
+                    seg_flags<NW>(B, cur);
+                    int4 rec2 = rec_at(s + 2 * ngroups);
+                    bool sat2 = sat_at(s + 2 * ngroups);
+                    while (s < n_seg) {
+                        const long long s1 = s + ngroups;
+                        const long long s2 = s1 + ngroups;
+                        const long long s3 = s2 + ngroups;
+                        const int4 rec3 = rec_at(s3);                                      // record, 3 ahead
+                        const bool sat3 = sat_at(s3);
+                        SegPre<NW> nn;
+                        seg_prefetch<NW, PER_SOURCE>(B, rec2, s2 < n_seg, sat2, gl, nn);    // ids, 2 ahead
+                        seg_flags<NW>(B, nxt);                                             // flags, 1 ahead
+
+                        visit(s, cur);
+                        s = s1;
+                        cur = nxt;
+                        nxt = nn;
+                        rec2 = rec3;
+                        sat2 = sat3;
+                    }
                 }
             }
             if (PER_SOURCE) {
