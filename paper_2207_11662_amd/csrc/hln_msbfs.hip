@@ -76,6 +76,12 @@ using hln::dev::store_agent_i32;
 #ifndef HLN_GATHER_CHUNK
 #define HLN_GATHER_CHUNK 8     // frontier gathers in flight per lane and chunk
 #endif
+#ifndef HLN_GATHER_CHUNK_W4096
+#define HLN_GATHER_CHUNK_W4096 8    // the same at W = 4096 (one group per wave)
+#endif
+
+// Arcs per segment (the unit of work of a lane group; longer rows are split).
+constexpr int kSegLen = 64;
 
 // Frontier gathers use raw buffer loads: 32-bit byte offsets (one VALU
 // operation per address) and an out-of-range offset for a lane that needs no
@@ -137,6 +143,26 @@ __device__ __forceinline__ uint32_t select_lanes(uint64_t lanes, uint32_t if_set
 __device__ __forceinline__ uint64_t buf_word(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     const hln_u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
     return (static_cast<uint64_t>(v.y) << 32) | v.x;
+}
+
+// Value of lane gbase + j of the group for every lane of the group; j is
+// uniform over the group.  A group of 64 lanes is the wave: one readlane.
+template <int LPV>
+__device__ __forceinline__ int group_bcast(int x, int gbase, int j) {
+    if constexpr (LPV == 64) return __builtin_amdgcn_readlane(x, j);
+    else return __shfl(x, gbase + j, 64);
+}
+
+// Sum of x over the 64 lanes of the wave, in every lane: DPP adds within
+// each row of 16 lanes (quad swaps, then rotations by 4 and 8), then the four
+// row totals read from lanes 0, 16, 32 and 48.  Every lane must be active.
+__device__ __forceinline__ int wave_sum_i32(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);    // quad_perm [1,0,3,2]
+    x += __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);    // quad_perm [2,3,0,1]
+    x += __builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false);   // row_ror:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false);   // row_ror:8
+    return __builtin_amdgcn_readlane(x, 0) + __builtin_amdgcn_readlane(x, 16) + __builtin_amdgcn_readlane(x, 32) +
+           __builtin_amdgcn_readlane(x, 48);
 }
 
 // Word masks of a frontier buffer: bit k set when word k of a vertex may be
@@ -226,10 +252,10 @@ struct BfsArgs {
     int* fault;
     uint64_t wait_ticks;              // bound of one barrier wait (s_memrealtime ticks)
     int32_t direction;                // 0 auto, 1 top-down only, 2 bottom-up only
+    int32_t seg_len;                  // SEG
     int32_t* levels;                  // nullable: levels run per batch
     int64_t* trace;                   // nullable: per level {ticks, vertices with new bits, new pairs, direction}
     int32_t trace_cap;
-    int32_t seg_len;                  // SEG
     int32_t alpha;                    // top-down when alpha * frontier arc-words < arcs of the graph
     int32_t* perm;                    // all sources: the vertices with arcs, in id order (the batches' sources)
     int32_t* iperm;                   // all sources: a vertex's position in perm, -1 without arcs
@@ -341,8 +367,12 @@ __device__ __forceinline__ int3 finalize_vertex(const BfsArgs& a, const LevelBuf
     // lanes with sub == 0 hold word k at group lane k
     const Mask nmask = static_cast<Mask>((__ballot(sub == 0 && nw != 0) >> gbase) & kWordMask);
     int c = sub == 0 ? __popcll(nw) : 0;
+    if constexpr (LPV == 64) {
+        c = wave_sum_i32(c);
+    } else {
 #pragma unroll
-    for (int off = 1; off < LPV; off <<= 1) c += shfl_xor_i32(c, off);
+        for (int off = 1; off < LPV; off <<= 1) c += shfl_xor_i32(c, off);
+    }
     // new bits go to the next frontier; words without new bits keep whatever
     // they held, as the word mask (exact, stored below when it changes) keeps
     // every reader off them
@@ -433,7 +463,7 @@ struct Gather {
     // is the number of arcs of this round that belong to the group's
     // segment.
     static constexpr int T = NW * CH;                    // (chunk, t) steps per round
-    static constexpr int KMAX = HLN_GATHER_CHUNK;
+    static constexpr int KMAX = NW == 64 ? HLN_GATHER_CHUNK_W4096 : HLN_GATHER_CHUNK;
     static constexpr int K = T < KMAX ? T : KMAX;
 
     __device__ __forceinline__ static int steps_needed(int cnt) {
@@ -953,7 +983,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                         const int wl = (c + gl < sg.z) ? a.col_idx[c + gl] : -1;
 #pragma unroll
                         for (int t = 0; t < NW; ++t) {
-                            const int w = __shfl(wl, gbase + t * Gather<NW>::NPAR + sub, 64);
+                            const int w = group_bcast<kLpv>(wl, gbase, t * Gather<NW>::NPAR + sub);
                             if (w >= 0 && x)
                                 __hip_atomic_fetch_or(reinterpret_cast<unsigned long long*>(&a.hacc[static_cast<size_t>(w) * NW + k]),
                                                       static_cast<unsigned long long>(x), __ATOMIC_RELAXED,
@@ -978,8 +1008,15 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                         const int j = __ffsll(static_cast<long long>(ball)) - 1;
                         ball &= ball - 1;
                         const int v = static_cast<int>(v0 + j);
-                        const int tj = __shfl(touched, gbase + j, 64);
-                        const Mask foj = shfl_mask(fo, gbase + j);
+                        const int tj = group_bcast<kLpv>(touched, gbase, j);
+                        Mask foj;
+                        if constexpr (kLpv == 64) {
+                            const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(fo)), j));
+                            const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(static_cast<uint64_t>(fo) >> 32)), j));
+                            foj = static_cast<Mask>((static_cast<uint64_t>(hi) << 32) | lo);
+                        } else {
+                            foj = shfl_mask(fo, gbase + j);
+                        }
                         const size_t base = static_cast<size_t>(v) * NW + k;
                         uint64_t acc = 0, vis_v = 0;
                         if (tj) {
@@ -1044,7 +1081,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                         int old = 0;
                         if (gl == 0)
                             old = __hip_atomic_fetch_add(&a.hcnt[v], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        old = __shfl(old, gbase, 64);
+                        old = group_bcast<kLpv>(old, gbase, 0);
                         if (old == nseg - 1) {
                             uint64_t full = 0;
                             if (sub == 0)
@@ -1136,7 +1173,9 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                     // instruction each, so no record is waited for inside the
                     // sweep.  A segment saturated at level L still clears its
                     // vertex's stale next-frontier word masks at levels L + 1
-                    // and L + 2 (no gathers); from L + 3 on it is left out.
+                    // and L + 2 (no gathers): a single-segment row's lane does
+                    // that itself, a longer row goes through the segment ending
+                    // (its segments are counted); from L + 3 on it is left out.
                     const int gid_u = __builtin_amdgcn_readfirstlane(static_cast<int>(gid));
                     const int ng = static_cast<int>(ngroups);
                     const int nsg = static_cast<int>(n_seg);
@@ -1146,7 +1185,12 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                         const bool ok = my < nsg;
                         const uint32_t slev = buf_u32(B.segsat, ok ? static_cast<uint32_t>(my) * 4u : kNoWord);
                         const int4 myrec = buf_i4(B.seg, ok ? static_cast<uint32_t>(my) * 16u : kNoWord);
-                        uint64_t todo = __ballot(ok && (slev == 0u || dlev <= slev + 2u));
+                        const bool clear_only = ok && slev != 0u && dlev <= slev + 2u;
+                        const bool own_clear = clear_only && myrec.w == 1;
+                        const uint32_t own_off = own_clear ? static_cast<uint32_t>(myrec.x) * static_cast<uint32_t>(sizeof(Mask))
+                                                           : kNoWord;
+                        const Mask own_old = buf_mask<Mask>(B.flag_nx, own_off);
+                        uint64_t todo = __ballot(ok && (slev == 0u || (clear_only && !own_clear)));
                         const uint64_t satm = __ballot(slev != 0u);
                         // the next segment of the window into p (sp = nsg: none left)
                         auto take = [&](SegPre<NW>& p, int& sp) {
@@ -1168,6 +1212,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                         take(cur, sc);
                         take(nxt, sn);
                         seg_flags<NW>(B, cur);
+                        buf_store_mask<Mask>(Mask(0), B.flag_nx, own_old != 0u ? own_off : kNoWord);
                         while (sc < nsg) {
                             SegPre<NW> nn;
                             int snn;
@@ -1501,8 +1546,6 @@ int width_words(const hln_opts* o) {
         default: return 0;
     }
 }
-
-constexpr int kSegLen = 64;
 
 size_t workspace_bytes(int32_t n, int64_t nnz, int nw, int grid_cap, int32_t n_src) {
     using hln::Arena;
