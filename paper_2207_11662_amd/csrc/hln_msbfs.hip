@@ -165,6 +165,20 @@ __device__ __forceinline__ int wave_sum_i32(int x) {
            __builtin_amdgcn_readlane(x, 48);
 }
 
+// Sum of x over each aligned group of LPV lanes (8, 16 or 32), in every
+// lane of the group: DPP quad swaps, then the half-row mirror (8 lanes), the
+// row mirror (16) and one cross-row exchange (32).
+template <int LPV>
+__device__ __forceinline__ int group_sum_i32(int x) {
+    static_assert(LPV == 8 || LPV == 16 || LPV == 32, "group of 8, 16 or 32 lanes");
+    x += __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);    // quad_perm [1,0,3,2]
+    x += __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);    // quad_perm [2,3,0,1]
+    x += __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false);   // row_half_mirror
+    if constexpr (LPV >= 16) x += __builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false);   // row_mirror
+    if constexpr (LPV >= 32) x += __shfl_xor(x, 16, 64);
+    return x;
+}
+
 // Word masks of a frontier buffer: bit k set when word k of a vertex may be
 // nonzero (32-bit for up to 32 words, 64-bit for 64).
 template <int NW>
@@ -367,12 +381,8 @@ __device__ __forceinline__ int3 finalize_vertex(const BfsArgs& a, const LevelBuf
     // lanes with sub == 0 hold word k at group lane k
     const Mask nmask = static_cast<Mask>((__ballot(sub == 0 && nw != 0) >> gbase) & kWordMask);
     int c = sub == 0 ? __popcll(nw) : 0;
-    if constexpr (LPV == 64) {
-        c = wave_sum_i32(c);
-    } else {
-#pragma unroll
-        for (int off = 1; off < LPV; off <<= 1) c += shfl_xor_i32(c, off);
-    }
+    if constexpr (LPV == 64) c = wave_sum_i32(c);
+    else c = group_sum_i32<LPV>(c);
     // new bits go to the next frontier; words without new bits keep whatever
     // they held, as the word mask (exact, stored below when it changes) keeps
     // every reader off them
