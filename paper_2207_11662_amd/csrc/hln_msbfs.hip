@@ -23,7 +23,8 @@
 // top-down when alpha * (frontier arc-words) < arcs of the graph (after
 // Beamer, Asanovic and Patterson, SC'12, with the bit-parallel frontier's
 // word count in the cost) and no block's list overflowed; the barrier's
-// releasing thread decides and every block receives the same bit.
+// releasing thread decides and every block receives the same bit.  At W =
+// 4096 the automatic choice is bottom-up at every level (alpha = 0).
 //
 // Saturation: a vertex that holds every source bit it can ever receive in
 // the batch gains nothing more, so later bottom-up levels skip its segments
@@ -270,7 +271,7 @@ struct BfsArgs {
     int32_t* levels;                  // nullable: levels run per batch
     int64_t* trace;                   // nullable: per level {ticks, vertices with new bits, new pairs, direction}
     int32_t trace_cap;
-    int32_t alpha;                    // top-down when alpha * frontier arc-words < arcs of the graph
+    int32_t alpha;                    // top-down when alpha * frontier arc-words < arcs of the graph (0: never)
     int32_t* perm;                    // all sources: the vertices with arcs, in id order (the batches' sources)
     int32_t* iperm;                   // all sources: a vertex's position in perm, -1 without arcs
     int32_t* bcount;                  // all sources: vertices with arcs per block range and degree class
@@ -335,7 +336,7 @@ struct Decide {
     int phase;
     __device__ bool operator()() const {
         const int slot = phase % 3;
-        if (direction == 2 || load_agent_i32(&ctrl->fbad[slot]) != 0) return false;
+        if (direction == 2 || alpha == 0 || load_agent_i32(&ctrl->fbad[slot]) != 0) return false;
         if (direction == 1) return true;
         const unsigned long long arcs = hln::dev::load_agent(&ctrl->farcs[slot]);
         return static_cast<long long>(arcs) * alpha < m_arcs;
@@ -1625,7 +1626,11 @@ hln_status fill_args(BfsArgs& a, const hln_csr* g, const int32_t* sources, int32
     a.trace = opts ? opts->trace : nullptr;
     a.trace_cap = opts ? opts->trace_cap : 0;
     a.seg_len = kSegLen;
-    a.alpha = 32;   // measured on configs 2-4 once saturated vertices skip their pull work
+    // Automatic direction: at W = 4096 every level runs bottom-up (its sweep
+    // leaves long-saturated segments out, so a nearly finished level costs
+    // less than a push's two barriers); narrower widths push when
+    // 32 * frontier arc-words < arcs (measured on configs 2-4).
+    a.alpha = nw == 64 ? 0 : 32;
     if (const char* e = getenv("HLN_ALPHA")) a.alpha = std::max(1, atoi(e));
     a.s32_levels = kS32Levels;
     if (const char* e = getenv("HLN_S32_LEVELS")) a.s32_levels = std::min(kS32Levels, std::max(1, atoi(e)));

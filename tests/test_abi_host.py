@@ -228,8 +228,8 @@ def test_residency_bound_matches_the_compiler():
     LDS) equals, for every closeness kernel the library builds, the blocks
     per compute unit that the compiler's own occupancy figure allows
     (waves per SIMD / wave slots a block takes per SIMD).  The 256-thread
-    kernels use 135-190 VGPRs: at most 3 waves per SIMD, so 3 blocks per
-    compute unit, not the 7 an occupancy answer once claimed."""
+    kernels use 115-190 VGPRs: at most 4 waves per SIMD, so at most 4
+    blocks per compute unit, not the 7 an occupancy answer once claimed."""
     L = P.lib()
     ks = closeness_kernels_from_report()
     assert len(ks) >= 42, len(ks)
@@ -242,7 +242,7 @@ def test_residency_bound_matches_the_compiler():
         assert got >= 1, (kind, nw, block, ps)
     # the 1024-thread kernels the library launches by default: one block per CU
     assert all(L.hln_resident_blocks(r["VGPRs"], r["LDS"], b) == 1 for (k, nw, b, ps), r in ks.items() if b == 1024)
-    assert all(L.hln_resident_blocks(r["VGPRs"], r["LDS"], b) <= 3 for (k, nw, b, ps), r in ks.items() if b == 256)
+    assert all(L.hln_resident_blocks(r["VGPRs"], r["LDS"], b) <= 4 for (k, nw, b, ps), r in ks.items() if b == 256)
 
 
 def test_resident_blocks_arithmetic():

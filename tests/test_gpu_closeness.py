@@ -289,6 +289,26 @@ def test_auto_direction_takes_both():
     assert np.median(pairs[dirs == 1]) < np.median(pairs[dirs == 0])
 
 
+def test_auto_direction_at_4096_is_bottom_up():
+    """At W = 4096 the automatic choice runs every level bottom-up (the
+    trace's direction column is all zero) and the sums stay exact."""
+    h = C.config2(scale=0.1)
+    rp, ci = csr_np(h.n, *h.layers[0])
+    g = graph_dev(P, rp, ci)
+    tr = torch.zeros((4096, 4), dtype=torch.int64, device="cuda")
+    lv = torch.zeros((h.n + 4095) // 4096, dtype=torch.int32, device="cuda")
+    out = P.hln_closeness_layer(g, width_bits=4096, want_h2=True, levels=lv, trace=tr)
+    torch.cuda.synchronize()
+    P.device_status()
+    rows = int(lv.sum().item())
+    t = tr[:rows].cpu().numpy()
+    assert rows > 0 and not t[:, 3].any()
+    S, R, H2, _, _ = O.bfs_sums(rp, ci, extras=True)
+    assert np.array_equal(out["S"].cpu().numpy(), S)
+    assert np.array_equal(out["R"].cpu().numpy(), R)
+    assert np.array_equal(out["h2"].cpu().numpy(), H2)
+
+
 @pytest.mark.parametrize("width", [64, 4096])
 def test_distance_sums_past_the_32_bit_window(width, monkeypatch):
     """Levels from HLN_S32_LEVELS on add to S with 64-bit atomics instead of
