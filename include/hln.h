@@ -65,9 +65,9 @@ typedef struct {
 typedef struct {
     int32_t width_bits;   /* sources per batch: 64, 128, 256, 512, 1024, 2048 or 4096; 0 = library default
                              (512); n * width_bits / 8 must be below 2^31 (HLN_EUNSUPPORTED otherwise) */
-    int32_t direction;    /* 0 = automatic per level (at width 4096 every level bottom-up; narrower
-                             widths top-down when 32 * frontier arc-words < arcs), 1 = top-down
-                             only, 2 = bottom-up only */
+    int32_t direction;    /* 0 = automatic per level (all sources at width 4096: every level
+                             bottom-up; listed sources or narrower widths: top-down when
+                             32 * frontier arc-words < arcs), 1 = top-down only, 2 = bottom-up only */
     int32_t flags;        /* 0 or HLN_FLAG_PER_VERTEX (see hln_closeness_layer) */
     int32_t* levels;      /* [dev] nullable: per batch of width_bits sources, the BFS levels run
                              (1 + the largest eccentricity among the batch's sources).  All-source

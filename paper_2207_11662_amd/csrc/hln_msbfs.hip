@@ -23,8 +23,9 @@
 // top-down when alpha * (frontier arc-words) < arcs of the graph (after
 // Beamer, Asanovic and Patterson, SC'12, with the bit-parallel frontier's
 // word count in the cost) and no block's list overflowed; the barrier's
-// releasing thread decides and every block receives the same bit.  At W =
-// 4096 the automatic choice is bottom-up at every level (alpha = 0).
+// releasing thread decides and every block receives the same bit.  With all
+// sources at W = 4096 the automatic choice is bottom-up at every level
+// (alpha = 0).
 //
 // Saturation: a vertex that holds every source bit it can ever receive in
 // the batch gains nothing more, so later bottom-up levels skip its segments
@@ -1626,11 +1627,13 @@ hln_status fill_args(BfsArgs& a, const hln_csr* g, const int32_t* sources, int32
     a.trace = opts ? opts->trace : nullptr;
     a.trace_cap = opts ? opts->trace_cap : 0;
     a.seg_len = kSegLen;
-    // Automatic direction: at W = 4096 every level runs bottom-up (its sweep
-    // leaves long-saturated segments out, so a nearly finished level costs
-    // less than a push's two barriers); narrower widths push when
-    // 32 * frontier arc-words < arcs (measured on configs 2-4).
-    a.alpha = nw == 64 ? 0 : 32;
+    // Automatic direction: with all sources at W = 4096 every level runs
+    // bottom-up (its sweep leaves long-saturated segments out, so a nearly
+    // finished level costs less than a push's two barriers, and level 1 reads
+    // ids only); listed sources and narrower widths push when 32 * frontier
+    // arc-words < arcs (a listed batch's first frontier is a few thousand
+    // vertices of a large graph).  Measured on configs 2-5.
+    a.alpha = (nw == 64 && !a.listed) ? 0 : 32;
     if (const char* e = getenv("HLN_ALPHA")) a.alpha = std::max(1, atoi(e));
     a.s32_levels = kS32Levels;
     if (const char* e = getenv("HLN_S32_LEVELS")) a.s32_levels = std::min(kS32Levels, std::max(1, atoi(e)));
