@@ -376,6 +376,42 @@ def test_saturation_probe_components(width):
     assert np.array_equal(pv["R"].cpu().numpy(), RQ)
 
 
+def test_all_sources_many_segments_per_wave():
+    """All sources at W = 4096 on a graph with more segments than 64 per wave
+    (n = 450,000: about 100 per wave of the 4,096 the grid holds), so the
+    sweep takes each wave's segments in several windows of 64: a sparse
+    random component over 400,000 vertices, a path of 10,000 vertices (deep
+    BFS, saturation over many levels) and 40,000 isolated vertices.  S, R, h2
+    and closeness bits of 96 sampled vertices against one oracle BFS each, R
+    of every vertex against the components."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    n, nr, npath = 450_000, 400_000, 10_000
+    rng = np.random.default_rng(11)
+    m = 2 * nr
+    eu = rng.integers(0, nr, size=m)
+    ev = rng.integers(0, nr, size=m)
+    pu = np.arange(nr, nr + npath - 1)
+    eu = np.concatenate([eu, pu])
+    ev = np.concatenate([ev, pu + 1])
+    keep = eu != ev
+    a, b = np.minimum(eu[keep], ev[keep]), np.maximum(eu[keep], ev[keep])
+    key = np.unique(a * n + b)
+    rp, ci = csr_np(n, key // n, key % n)
+    say("many windows: n=%d arcs=%d" % (n, len(ci)))
+    got = run_all(rp, ci, 4096)
+    sample = np.unique(np.concatenate([rng.choice(n, size=90, replace=False),
+                                       [0, nr, nr + npath // 2, nr + npath - 1, n - 1, n - 2]])).astype(np.int32)
+    S, R, H2, _, _ = O.bfs_sums(rp, ci, sources=sample, extras=True)
+    assert np.array_equal(got["S"][sample], S)
+    assert np.array_equal(got["R"][sample], R)
+    assert np.array_equal(got["h2"][sample], H2)
+    assert np.array_equal(got["cc"][sample].view(np.int64), O.closeness_wf(n, S, R).view(np.int64))
+    adj = sp.csr_matrix((np.ones(len(ci)), ci, rp), shape=(n, n))
+    _, lab = connected_components(adj, directed=False)
+    assert np.array_equal(got["R"], np.bincount(lab)[lab])
+
+
 def test_largest_graph_at_width_4096():
     """The largest vertex count W = 4096 allows: n = 2^22 - 1, so a bitset
     is n * W / 8 = 2^31 - 512 bytes and the kernel's 32-bit buffer offsets
