@@ -319,7 +319,9 @@ struct PhaseEnd {
     FrontierLds* f;
     Ctrl* ctrl;
     int phase;
+    bool on;                              // false: no level can run top-down, the lists are not kept
     __device__ void operator()() const {
+        if (!on) return;
         const int par = phase & 1;
         const int slot = phase % 3;
         if (f->arcs[par]) hln::dev::atomic_add_agent(&ctrl->farcs[slot], f->arcs[par]);
@@ -580,6 +582,7 @@ struct SegPre {
     MaskT<NW> fl[Gather<NW>::CH]; // frontier word masks of the neighbours in cid
     MaskT<NW> flag_old;          // word mask of the vertex's next-frontier slot
     bool sat;                    // the vertex holds every bit of the batch: no gathers
+    int ipv;                     // level 1 of an all-source batch: the vertex's place in the batches
 };
 
 template <int NW, bool PER_SOURCE>
@@ -841,6 +844,9 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
     // all sources: the batches run over the vertices with arcs (perm)
     const int n_src_eff = a.listed ? a.n_src : load_agent_i32(&ctrl->n_act);
     const int n_batches = (n_src_eff + W - 1) / W;
+    // frontier lists and their arc counts feed only the push decision: not
+    // kept when no level can run top-down
+    const bool lists = a.direction == 1 || (a.direction == 0 && a.alpha != 0);
     const long long m_arcs = a.row_ptr[n];               // checked against nnz_cap in phase 0
     const unsigned long long gmask = (kLpv >= 64 ? ~0ull : ((1ull << kLpv) - 1ull)) << gbase;
     int trace_row = 0;
@@ -908,7 +914,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                 }
                 for (long long i = tid_x; i < cnt; i += nthreads) {
                     const int3 sg = vertex_segments(a, a.perm[src0 + i]);
-                    if (sg.y > 0) frontier_note(s_fr, par, sg.x, sg.y, sg.z);
+                    if (lists && sg.y > 0) frontier_note(s_fr, par, sg.x, sg.y, sg.z);
                 }
             } else {
                 for (long long i = tid; i < static_cast<long long>(n) * NW; i += nthreads) a.vis[i] = 0;
@@ -946,7 +952,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                 // block (first + j) mod nblk, so a hub among the sources is
                 // pushed by many blocks instead of by one.  A vertex listed
                 // twice is noted twice (its words are ORed in twice: no change).
-                for (int i = threadIdx.x; i < cnt; i += BLOCK) {
+                for (int i = threadIdx.x; lists && i < cnt; i += BLOCK) {
                     const int3 sg = vertex_segments(a, a.sources[a.perm[src0 + i]]);
                     long long j = (static_cast<long long>(blk) - sg.x) % static_cast<long long>(nblk);
                     if (j < 0) j += nblk;
@@ -956,7 +962,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                 }
             }
             const hln::dev::BarrierResult br =
-                gb.sync(0, PhaseEnd{&s_fr, ctrl, phase}, Decide{ctrl, m_arcs, a.direction, a.alpha, phase});
+                gb.sync(0, PhaseEnd{&s_fr, ctrl, phase, lists}, Decide{ctrl, m_arcs, a.direction, a.alpha, phase});
             if (!br.ok) return false;
             push = br.decision;
             ++phase;
@@ -1046,7 +1052,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                             t_pairs += cw.x;
                             t_verts += 1;
                             const int3 sgv = vertex_segments(a, v);
-                            if (gl == 0 && sgv.y > 0) frontier_note(s_fr, par, sgv.x, sgv.y, sgv.z * cw.y);
+                            if (lists && gl == 0 && sgv.y > 0) frontier_note(s_fr, par, sgv.x, sgv.y, sgv.z * cw.y);
                             if (cw.z) mark_saturated<kLpv>(a, sgv.x, sgv.y, gl, d);
                         }
                     }
@@ -1075,7 +1081,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                             any = 1;
                             t_pairs += cw.x;
                             t_verts += 1;
-                            if (gl == 0) frontier_note(s_fr, par, static_cast<int>(s), 1, (sg.z - sg.y) * cw.y);
+                            if (lists && gl == 0) frontier_note(s_fr, par, static_cast<int>(s), 1, (sg.z - sg.y) * cw.y);
                             if (cw.z) mark_saturated<kLpv>(a, static_cast<int>(s), 1, gl, d);
                         }
                     } else {
@@ -1110,41 +1116,14 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                                 t_pairs += cw.x;
                                 t_verts += 1;
                                 const int first = a.seg_first[v];
-                                if (gl == 0) frontier_note(s_fr, par, first, nseg, nseg * seg_len * cw.y);
+                                if (lists && gl == 0) frontier_note(s_fr, par, first, nseg, nseg * seg_len * cw.y);
                                 if (cw.z) mark_saturated<kLpv>(a, first, nseg, gl, d);
                             }
                         }
                     }
                 };
-                // Level 1 of an all-source batch at W = 4096: the frontier is the
-                // batch's sources perm[src0 .. src0 + cnt - 1] with one bit each,
-                // so a neighbour's frontier word follows from its place in perm:
-                // the level reads column ids and iperm only (no neighbour masks,
-                // no frontier words).
                 bool level1_ids = false;
                 if constexpr (NW == 64) level1_ids = d == 1 && !a.listed;
-                if (level1_ids) {
-                    for (long long s1 = gid; s1 < n_seg; s1 += ngroups) {
-                        const int4 sg = rec_at(s1);
-                        const int len = sg.z - sg.y;
-                        const int cidl = gl < len ? static_cast<int>(buf_u32(B.col, static_cast<uint32_t>(sg.y + gl) * 4u)) : -1;
-                        const Mask flag_old = buf_mask<Mask>(B.flag_nx, sg.w == 1 ? static_cast<uint32_t>(sg.x) * static_cast<uint32_t>(sizeof(Mask))
-                                                                                  : kNoWord);
-                        // the neighbour's bit: its place among the batches' sources
-                        const int rel_l = (cidl >= 0 ? a.iperm[cidl] : -1 - src0) - src0;
-                        unsigned long long hits = __ballot(cidl >= 0 && rel_l >= 0 && rel_l < cnt);
-                        uint64_t acc = 0;
-                        while (hits) {
-                            const int t = __ffsll(static_cast<long long>(hits)) - 1;
-                            hits &= hits - 1;
-                            const int rel = __builtin_amdgcn_readlane(rel_l, t);
-                            if ((rel >> 6) == k) acc |= 1ull << (rel & 63);
-                        }
-                        uint64_t vis_v = 0;
-                        if (__ballot(acc != 0) != 0 || sg.w > 1) vis_v = a.vis[static_cast<size_t>(sg.x) * NW + k];
-                        finish(s1, sg, acc, vis_v, flag_old);
-                    }
-                }
                 // one segment: the visited word and the frontier gathers, then
                 // its ending (cur holds what the pipeline prefetched for it)
                 auto visit = [&](long long s, const SegPre<NW>& cur) {
@@ -1192,6 +1171,71 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                     const int ng = static_cast<int>(ngroups);
                     const int nsg = static_cast<int>(n_seg);
                     const uint32_t dlev = static_cast<uint32_t>(d);
+                    // Level 1 of an all-source batch: the frontier is the batch's
+                    // sources perm[src0 .. src0 + cnt - 1] with one bit each, so a
+                    // neighbour's frontier word follows from its place in perm and
+                    // the visited word from the vertex's own (the batch start left
+                    // only the sources' own bits): the level reads column ids and
+                    // iperm only, in the same window pipeline (ids two segments
+                    // ahead, the neighbours' places one ahead).
+                    for (int wb = level1_ids ? gid_u : nsg; wb < nsg; wb += 64 * ng) {
+                        const int my = wb + lane * ng;
+                        const bool ok = my < nsg;
+                        const int4 myrec = buf_i4(B.seg, ok ? static_cast<uint32_t>(my) * 16u : kNoWord);
+                        uint64_t todo = __ballot(ok);
+                        auto take1 = [&](SegPre<NW>& p, int& sp) {
+                            int4 rec = make_int4(0, 0, 0, 0);
+                            sp = nsg;
+                            if (todo != 0) {
+                                const int j = __builtin_ctzll(todo);
+                                todo &= todo - 1;
+                                rec = make_int4(__builtin_amdgcn_readlane(myrec.x, j), __builtin_amdgcn_readlane(myrec.y, j),
+                                                __builtin_amdgcn_readlane(myrec.z, j), __builtin_amdgcn_readlane(myrec.w, j));
+                                sp = wb + j * ng;
+                            }
+                            const bool valid = sp < nsg;
+                            p.sg = rec;
+                            p.sat = false;
+                            const int e = rec.y + gl;
+                            const uint32_t x = buf_u32(B.col, (valid && e < rec.z) ? static_cast<uint32_t>(e) * 4u : kNoWord);
+                            p.cid[0] = (valid && e < rec.z) ? static_cast<int>(x) : -1;
+                            p.flag_old = buf_mask<Mask>(B.flag_nx, (valid && rec.w == 1) ? static_cast<uint32_t>(rec.x) * static_cast<uint32_t>(sizeof(Mask))
+                                                                                       : kNoWord);
+                            p.ipv = valid ? a.iperm[rec.x] : -1;
+                            p.fl[0] = 0;
+                        };
+                        // the neighbours' places among the batches' sources (-1: no arc or no place)
+                        auto places = [&](SegPre<NW>& p) {
+                            p.fl[0] = static_cast<Mask>(static_cast<uint32_t>(p.cid[0] >= 0 ? a.iperm[p.cid[0]] : -1));
+                        };
+                        SegPre<NW> cur, nxt;
+                        int sc, sn;
+                        take1(cur, sc);
+                        take1(nxt, sn);
+                        places(cur);
+                        while (sc < nsg) {
+                            SegPre<NW> nn;
+                            int snn;
+                            take1(nn, snn);                                // ids, 2 ahead
+                            places(nxt);                                   // places, 1 ahead
+                            const int rel_l = static_cast<int>(static_cast<uint32_t>(cur.fl[0])) - src0;
+                            unsigned long long hits = __ballot(cur.cid[0] >= 0 && rel_l >= 0 && rel_l < cnt);
+                            uint64_t acc = 0;
+                            while (hits) {
+                                const int t = __ffsll(static_cast<long long>(hits)) - 1;
+                                hits &= hits - 1;
+                                const int rel = __builtin_amdgcn_readlane(rel_l, t);
+                                if ((rel >> 6) == k) acc |= 1ull << (rel & 63);
+                            }
+                            const int own = cur.ipv - src0;
+                            const uint64_t vis_v = (own >= 0 && own < cnt && (own >> 6) == k) ? (1ull << (own & 63)) : 0ull;
+                            finish(sc, cur.sg, acc, vis_v, cur.flag_old);
+                            sc = sn;
+                            cur = nxt;
+                            sn = snn;
+                            nxt = nn;
+                        }
+                    }
                     for (int wb = level1_ids ? nsg : gid_u; wb < nsg; wb += 64 * ng) {
                         const int my = wb + lane * ng;
                         const bool ok = my < nsg;
@@ -1291,7 +1335,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                 if (threadIdx.x == 0 && s_trace[0]) (void)trace_add(a.trace + 4 * trace_row, s_trace[0], s_trace[1]);
             }
             const hln::dev::BarrierResult br =
-                gb.sync(any, PhaseEnd{&s_fr, ctrl, phase}, Decide{ctrl, m_arcs, a.direction, a.alpha, phase});
+                gb.sync(any, PhaseEnd{&s_fr, ctrl, phase, lists}, Decide{ctrl, m_arcs, a.direction, a.alpha, phase});
             if (!br.ok) return false;
             if (a.trace && trace_row < a.trace_cap && blk == 0 && threadIdx.x == 0) {
                 a.trace[4 * trace_row] = static_cast<int64_t>(__builtin_amdgcn_s_memrealtime());
