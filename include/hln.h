@@ -74,7 +74,11 @@ typedef struct {
                              mode batches only the vertices that have arcs (one without arcs
                              reaches only itself), by degree class (more than 64 arcs, 64, 32-63,
                              16-31, 8-15, 4-7, 2-3, 1) and ids ascending inside a class, so entries from
-                             ceil(#vertices with arcs / width_bits) on are not written.  Listed
+                             ceil(#vertices with arcs / width_bits) on are not written; at width
+                             4096 the batches after the first take the remaining vertices by BFS
+                             distance from the first batch's highest-degree vertex (nearest first,
+                             distances above 30 together, unreached last; the order above among
+                             equals).  Listed
                              sources are batched by the same classes (a source without arcs with
                              the last), list positions ascending inside a class; outputs stay
                              indexed by list position */

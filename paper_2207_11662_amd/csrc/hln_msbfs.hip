@@ -623,6 +623,94 @@ __device__ __forceinline__ LevelBufs level_bufs(const BfsArgs& a, const uint64_t
     return B;
 }
 
+// Distance classes of the ranking after the first all-source batch.
+constexpr int kDistClasses = 32;
+
+__device__ __forceinline__ int dist_class(uint32_t member) {
+    return member == 0u ? kDistClasses - 1 : min(static_cast<int>(member) - 1, kDistClasses - 2);
+}
+
+// Re-ranks batch positions [W, n_act) by the distance class of their vertex
+// (member = 1 + distance from the first batch's probe, 0 outside its
+// component), stable: each block counts the classes of its range of
+// positions, then places them after every lower class and every earlier
+// block's equal ones (ballots rank them inside a block), writing the new
+// positions to iperm; perm is then rebuilt from iperm.  Called by every
+// block of the graph's grid.
+template <int BLOCK, class Barrier>
+__device__ bool rank_by_distance(const BfsArgs& a, Barrier& gb, const unsigned blk, const unsigned nblk, const int W,
+                                 const int n_act) {
+    __shared__ int s_cnt[kDistClasses], s_tot[kDistClasses], s_before[kDistClasses], s_off[kDistClasses];
+    __shared__ int s_wv[BLOCK / 64][kDistClasses];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const long long tail = static_cast<long long>(n_act) - W;
+    const long long chunk = (tail + nblk - 1) / nblk;
+    const long long q_lo = W + min(static_cast<long long>(blk) * chunk, tail);
+    const long long q_hi = W + min(static_cast<long long>(blk) * chunk + chunk, tail);
+    if (threadIdx.x < kDistClasses) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (long long q = q_lo + threadIdx.x; q < q_hi; q += BLOCK) atomicAdd(&s_cnt[dist_class(a.member[a.perm[q]])], 1);
+    __syncthreads();
+    if (threadIdx.x < kDistClasses) a.bcount[blk * kDistClasses + threadIdx.x] = s_cnt[threadIdx.x];
+    if (!gb.wait()) return false;
+    if (threadIdx.x < kDistClasses) s_tot[threadIdx.x] = s_before[threadIdx.x] = 0;
+    __syncthreads();
+    for (unsigned t = threadIdx.x; t < nblk * kDistClasses; t += BLOCK) {
+        const unsigned b2 = t / kDistClasses, c = t % kDistClasses;
+        const int x = a.bcount[t];
+        if (x) {
+            atomicAdd(&s_tot[c], x);
+            if (b2 < blk) atomicAdd(&s_before[c], x);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = W;
+#pragma unroll 1
+        for (int c = 0; c < kDistClasses; ++c) {
+            s_off[c] = acc + s_before[c];
+            acc += s_tot[c];
+        }
+    }
+    __syncthreads();
+    for (long long base = q_lo; base < q_hi; base += BLOCK) {
+        const long long q = base + threadIdx.x;
+        const int v = q < q_hi ? a.perm[q] : -1;
+        const int cls = v >= 0 ? dist_class(a.member[v]) : -1;
+        int before = 0;
+#pragma unroll 1
+        for (int c = 0; c < kDistClasses; ++c) {
+            const unsigned long long bal = __ballot(cls == c);
+            if (cls == c) before = __popcll(bal & ((1ull << lane) - 1ull));
+            if (lane == 0) s_wv[wave][c] = __popcll(bal);
+        }
+        __syncthreads();
+        if (cls >= 0) {
+            int woff = 0;
+#pragma unroll 1
+            for (int w2 = 0; w2 < wave; ++w2) woff += s_wv[w2][cls];
+            a.iperm[v] = s_off[cls] + woff + before;
+        }
+        __syncthreads();
+        if (threadIdx.x < kDistClasses) {
+            int tot = 0;
+#pragma unroll 1
+            for (int w2 = 0; w2 < BLOCK / 64; ++w2) tot += s_wv[w2][threadIdx.x];
+            s_off[threadIdx.x] += tot;
+        }
+        __syncthreads();
+    }
+    if (!gb.wait()) return false;
+    const long long tid = static_cast<long long>(blk) * BLOCK + threadIdx.x;
+    const long long nthreads = static_cast<long long>(nblk) * BLOCK;
+    for (long long v = tid; v < a.n; v += nthreads) {
+        const int q = a.iperm[v];
+        if (q >= W) a.perm[q] = static_cast<int32_t>(v);
+    }
+    return gb.wait();
+}
+
 // The whole computation for one graph, run by `nblk` blocks (this one is
 // `blk`) that synchronise through `gb`: the grid of k_closeness, or one
 // partition of the grid of k_closeness_multi.  Returns false when a barrier
@@ -679,6 +767,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
             if (a.H2) a.H2[v] = 0;
         }
         a.hcnt[v] = 0;
+        a.member[v] = 0u;
         const int e0 = a.row_ptr[v];
         const int e1 = a.row_ptr[v + 1];
         if (e0 < 0 || e1 < e0 || e1 > a.nnz_cap) {
@@ -968,6 +1057,12 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
             ++phase;
         }
         const uint64_t gcm_k = hln::dev::load_agent(&ctrl->gcm[k]);
+        // the first batch records in member, for every vertex its probe
+        // source (highest degree, first position on ties) reaches, 1 + the
+        // distance: at the start of level d, from the frontier of level d - 1
+        const int probe_pos = (b == 0 && n_batches > 1)
+            ? static_cast<int>(0xffffffffu - static_cast<unsigned>(hln::dev::load_agent(&ctrl->probe_key) & 0xffffffffull))
+            : -1;
 
         // ---- level loop; the barrier's OR tells every block whether any
         // vertex got a new bit, which ends this batch's BFS
@@ -985,6 +1080,12 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
             int any = 0;
             long long t_pairs = 0;
             int t_verts = 0;
+            if (probe_pos >= 0 && !PER_SOURCE && NW == 64 && !a.listed) {
+                const int kp = probe_pos >> 6;
+                for (long long v = tid; v < n; v += nthreads)
+                    if (((flag_fr[v] >> kp) & 1u) != 0 && ((fr[static_cast<size_t>(v) * NW + kp] >> (probe_pos & 63)) & 1ull) != 0)
+                        a.member[v] = static_cast<uint32_t>(d);
+            }
             const LevelBufs B = level_bufs<NW>(a, nx, flag_nx, flag_fr);
             if (push) {
                 // ---- top-down, part 1: each block ORs the frontier words of
@@ -1388,11 +1489,16 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
             // the partials are rewritten only after the next batch's barriers
         }
         if (b == 0 && n_batches > 1) {
-            // the probe's component: every vertex its bit reached in this batch
-            const unsigned pos = 0xffffffffu - static_cast<unsigned>(hln::dev::load_agent(&ctrl->probe_key) & 0xffffffffull);
-            for (long long v = tid; v < n; v += nthreads)
-                a.member[v] = ((a.vis[v * NW + (pos >> 6)] >> (pos & 63)) & 1ull) ? 1u : 0u;
-            if (!gb.wait()) return false;
+            // member now holds the probe's component (nonzero: 1 + the
+            // vertex's distance from the probe), complete since the batch's
+            // last level barrier.  All sources: the later batches take the remaining vertices by
+            // their distance from the probe (nearest first, distances past
+            // kDistClasses - 2 together, vertices outside its component last),
+            // keeping the degree-class order among equals.  A batch's level
+            // count is 1 + its sources' largest eccentricity, and vertices at
+            // one distance from a hub have close eccentricities.
+            if constexpr (!PER_SOURCE && NW == 64)
+                if (!a.listed && !rank_by_distance<BLOCK>(a, gb, blk, nblk, W, n_src_eff)) return false;
         }
     }
 
@@ -1618,7 +1724,7 @@ size_t workspace_bytes(int32_t n, int64_t nnz, int nw, int grid_cap, int32_t n_s
     b += Arena::round(static_cast<size_t>(n) * sizeof(uint32_t));    // probe component membership
     b += Arena::round(static_cast<size_t>(grid_cap) * 2 * 64 * nw * sizeof(int64_t));  // per-source partials
     b += 2 * Arena::round(static_cast<size_t>(std::max(n, n_src)) * sizeof(int32_t));   // perm, iperm
-    b += Arena::round(static_cast<size_t>(grid_cap) * kRankClasses * sizeof(int32_t)); // per-block class counts
+    b += Arena::round(static_cast<size_t>(grid_cap) * std::max(kRankClasses, kDistClasses) * sizeof(int32_t)); // per-block class counts
     return b;
 }
 
@@ -1659,7 +1765,7 @@ hln_status fill_args(BfsArgs& a, const hln_csr* g, const int32_t* sources, int32
     a.part = ar.take<int64_t>(static_cast<size_t>(grid_cap) * 2 * 64 * nw);
     a.perm = ar.take<int32_t>(static_cast<size_t>(std::max(n, n_src)));
     a.iperm = ar.take<int32_t>(static_cast<size_t>(std::max(n, n_src)));
-    a.bcount = ar.take<int32_t>(static_cast<size_t>(grid_cap) * kRankClasses);
+    a.bcount = ar.take<int32_t>(static_cast<size_t>(grid_cap) * std::max(kRankClasses, kDistClasses));
     a.S = S;
     a.R = R;
     a.H2 = h2;

@@ -34,3 +34,31 @@ def to_dev(a, dtype=torch.int32):
 
 def graph_dev(P, row_ptr, col_idx):
     return P.Graph(to_dev(row_ptr), to_dev(col_idx))
+
+
+def allsource_batch_order(row_ptr, col_idx, width: int):
+    """The order in which all-source batches take their sources: the
+    vertices that have arcs, by degree class (rows longer than 64 arcs, then
+    64, 32-63, ..., 1), ids ascending inside a class.  At W = 4096 with more
+    than one batch, the batches after the first take the remaining vertices
+    by their BFS distance from the first batch's highest-degree vertex (first
+    in that order on ties): nearest first, distances past 30 together, the
+    vertices it does not reach last, the order above among equals."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import shortest_path
+    rp = np.asarray(row_ptr, np.int64)
+    n = len(rp) - 1
+    deg = np.diff(rp)
+    act = np.nonzero(deg)[0]
+    cls = np.where(deg[act] > 64, 0, 7 - np.floor(np.log2(np.maximum(deg[act], 1))).astype(np.int64))
+    order = act[np.lexsort((act, cls))]
+    if width != 4096 or len(order) <= width:
+        return order
+    first = order[:width]
+    probe = int(first[np.argmax(deg[first])])
+    adj = csr_matrix((np.ones(len(col_idx), np.int8), np.asarray(col_idx), rp), shape=(n, n))
+    dist = shortest_path(adj, method="D", unweighted=True, directed=False, indices=probe)
+    tail = order[width:]
+    dt = dist[tail]
+    key = np.where(np.isinf(dt), 31, np.minimum(np.where(np.isinf(dt), 0, dt), 30)).astype(np.int64)
+    return np.concatenate([first, tail[np.argsort(key, kind="stable")]])

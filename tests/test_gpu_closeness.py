@@ -9,7 +9,7 @@ import torch
 from homln_inputs import configs as C
 from homln_inputs import generators as G
 from oracle import oracle as O
-from tests.gpu_common import csr_np, graph_dev, say, to_dev
+from tests.gpu_common import allsource_batch_order, csr_np, graph_dev, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -185,7 +185,8 @@ def test_levels_per_batch(width):
     """The kernel's per-batch level count is 1 + the largest eccentricity of
     the batch's sources (the L_b of the byte model), from the oracle; the
     all-source batches take the vertices that have arcs, largest degree class
-    first, ids ascending inside a class."""
+    first, ids ascending inside a class (at W = 4096 the batches after the
+    first by distance from the first batch's hub: allsource_batch_order)."""
     h = C.config1()
     n = h.n
     for rp, ci in [csr_np(n, *h.layers[0]), O.compose("and", [csr_np(n, *e) for e in h.layers])]:
@@ -195,12 +196,7 @@ def test_levels_per_batch(width):
         P.hln_closeness_layer(g, width_bits=width, levels=lv)
         torch.cuda.synchronize()
         _, _, _, ecc, _ = O.bfs_sums(rp, ci, extras=True)
-        # the batches run over the vertices that have arcs: by degree class
-        # (rows longer than 64 arcs, then 32-64, 16-31, ..., 1), ids ascending
-        deg = np.diff(rp)
-        act = np.nonzero(deg)[0]
-        cls = np.where(deg[act] > 64, 0, 7 - np.floor(np.log2(np.maximum(deg[act], 1))).astype(np.int64))
-        act = act[np.lexsort((act, cls))]
+        act = allsource_batch_order(rp, ci, width)
         na = (len(act) + width - 1) // width
         ref = [1 + int(ecc[act[b * width:(b + 1) * width]].max()) for b in range(na)] + [0] * (nb - na)
         assert lv.cpu().numpy().tolist() == ref

@@ -18,7 +18,7 @@ import torch
 import bench
 from homln_inputs import configs as C
 from oracle import oracle as O
-from tests.gpu_common import say
+from tests.gpu_common import allsource_batch_order, say
 
 pytestmark = pytest.mark.gpu
 
@@ -27,18 +27,10 @@ P = pytest.importorskip("paper_2207_11662_amd")
 W_BENCH = 4096          # the benchmark's source-batch width
 
 
-def batch_order(rp):
-    """Vertices with arcs in the order the all-source batches take them:
-    degree class (rows longer than 64 arcs, then 64, 32-63, ..., 1), ids
-    ascending inside a class."""
-    deg = np.diff(rp)
-    act = np.nonzero(deg)[0]
-    cls = np.where(deg[act] > 64, 0, 7 - np.floor(np.log2(np.maximum(deg[act], 1))).astype(np.int64))
-    return act[np.lexsort((act, cls))]
-
-
-def levels_ref(rp, ecc, width):
-    act = batch_order(rp)
+def levels_ref(rp, ci, ecc, width):
+    """Per-batch levels: 1 + the largest eccentricity of each batch's sources
+    in the all-source batch order (allsource_batch_order)."""
+    act = allsource_batch_order(rp, ci, width)
     nb = (len(rp) - 1 + width - 1) // width
     na = (len(act) + width - 1) // width
     return [1 + int(ecc[act[b * width:(b + 1) * width]].max()) for b in range(na)] + [0] * (nb - na)
@@ -96,7 +88,7 @@ def test_config2_bench_step_every_vertex(cfg2_step, gi):
     assert np.array_equal(got["h2"], ref["H2"]), ("h2", gi)
     assert np.array_equal(got["cc"].view(np.int64), ref["cc"].view(np.int64)), ("cc bits", gi)
     # levels per batch = 1 + the largest eccentricity of the batch's sources
-    assert host["levels"][gi].tolist() == levels_ref(rp, ref["ecc"], W_BENCH)
+    assert host["levels"][gi].tolist() == levels_ref(rp, ci, ref["ecc"], W_BENCH)
 
 
 def test_config2_bench_step_selection(cfg2_step):
