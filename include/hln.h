@@ -74,13 +74,14 @@ typedef struct {
                              mode batches only the vertices that have arcs (one without arcs
                              reaches only itself), by degree class (more than 64 arcs, 64, 32-63,
                              16-31, 8-15, 4-7, 2-3, 1) and ids ascending inside a class, so entries from
-                             ceil(#vertices with arcs / width_bits) on are not written; at width
-                             4096 the batches after the first take the remaining vertices by BFS
-                             distance from the first batch's highest-degree vertex (nearest first,
-                             distances above 30 together, unreached last; the order above among
-                             equals).  Listed
-                             sources are batched by the same classes (a source without arcs with
-                             the last), list positions ascending inside a class; outputs stay
+                             ceil(#vertices with arcs / width_bits) on are not written; with more
+                             than one batch, the batches after the first take the remaining
+                             vertices by BFS distance from the first batch's highest-degree
+                             vertex (nearest first, distances above 30 together, unreached last;
+                             the order above among equals).  Listed sources are batched by the
+                             same classes (a source without arcs with the last), list positions
+                             ascending inside a class, and the later batches by distance as above
+                             (with per-source outputs only below width 4096); outputs stay
                              indexed by list position */
     int64_t* trace;       /* [dev] nullable, zero-filled by the caller: per level run (in order, over
                              all batches) 4 int64: s_memrealtime ticks (100 MHz) when the level's

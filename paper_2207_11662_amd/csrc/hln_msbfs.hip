@@ -650,7 +650,10 @@ __device__ bool rank_by_distance(const BfsArgs& a, Barrier& gb, const unsigned b
     const long long q_hi = W + min(static_cast<long long>(blk) * chunk + chunk, tail);
     if (threadIdx.x < kDistClasses) s_cnt[threadIdx.x] = 0;
     __syncthreads();
-    for (long long q = q_lo + threadIdx.x; q < q_hi; q += BLOCK) atomicAdd(&s_cnt[dist_class(a.member[a.perm[q]])], 1);
+    // an item is a vertex (all sources) or a list position (listed sources)
+    auto vertex_of = [&](int item) { return a.listed ? a.sources[item] : item; };
+    for (long long q = q_lo + threadIdx.x; q < q_hi; q += BLOCK)
+        atomicAdd(&s_cnt[dist_class(a.member[vertex_of(a.perm[q])])], 1);
     __syncthreads();
     if (threadIdx.x < kDistClasses) a.bcount[blk * kDistClasses + threadIdx.x] = s_cnt[threadIdx.x];
     if (!gb.wait()) return false;
@@ -677,7 +680,7 @@ __device__ bool rank_by_distance(const BfsArgs& a, Barrier& gb, const unsigned b
     for (long long base = q_lo; base < q_hi; base += BLOCK) {
         const long long q = base + threadIdx.x;
         const int v = q < q_hi ? a.perm[q] : -1;
-        const int cls = v >= 0 ? dist_class(a.member[v]) : -1;
+        const int cls = v >= 0 ? dist_class(a.member[vertex_of(v)]) : -1;
         int before = 0;
 #pragma unroll 1
         for (int c = 0; c < kDistClasses; ++c) {
@@ -704,7 +707,8 @@ __device__ bool rank_by_distance(const BfsArgs& a, Barrier& gb, const unsigned b
     if (!gb.wait()) return false;
     const long long tid = static_cast<long long>(blk) * BLOCK + threadIdx.x;
     const long long nthreads = static_cast<long long>(nblk) * BLOCK;
-    for (long long v = tid; v < a.n; v += nthreads) {
+    const long long n_items = a.listed ? static_cast<long long>(a.n_src) : static_cast<long long>(a.n);
+    for (long long v = tid; v < n_items; v += nthreads) {
         const int q = a.iperm[v];
         if (q >= W) a.perm[q] = static_cast<int32_t>(v);
     }
@@ -1080,7 +1084,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
             int any = 0;
             long long t_pairs = 0;
             int t_verts = 0;
-            if (probe_pos >= 0 && !PER_SOURCE && NW == 64 && !a.listed) {
+            if (probe_pos >= 0) {
                 const int kp = probe_pos >> 6;
                 for (long long v = tid; v < n; v += nthreads)
                     if (((flag_fr[v] >> kp) & 1u) != 0 && ((fr[static_cast<size_t>(v) * NW + kp] >> (probe_pos & 63)) & 1ull) != 0)
@@ -1497,8 +1501,8 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
             // keeping the degree-class order among equals.  A batch's level
             // count is 1 + its sources' largest eccentricity, and vertices at
             // one distance from a hub have close eccentricities.
-            if constexpr (!PER_SOURCE && NW == 64)
-                if (!a.listed && !rank_by_distance<BLOCK>(a, gb, blk, nblk, W, n_src_eff)) return false;
+            if constexpr (!PER_SOURCE || NW < 64)
+                if (!rank_by_distance<BLOCK>(a, gb, blk, nblk, W, n_src_eff)) return false;
         }
     }
 

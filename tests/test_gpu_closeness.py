@@ -9,7 +9,7 @@ import torch
 from homln_inputs import configs as C
 from homln_inputs import generators as G
 from oracle import oracle as O
-from tests.gpu_common import allsource_batch_order, csr_np, graph_dev, say, to_dev
+from tests.gpu_common import allsource_batch_order, csr_np, graph_dev, listed_batch_order, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -185,8 +185,8 @@ def test_levels_per_batch(width):
     """The kernel's per-batch level count is 1 + the largest eccentricity of
     the batch's sources (the L_b of the byte model), from the oracle; the
     all-source batches take the vertices that have arcs, largest degree class
-    first, ids ascending inside a class (at W = 4096 the batches after the
-    first by distance from the first batch's hub: allsource_batch_order)."""
+    first, ids ascending inside a class, and the batches after the first by
+    distance from the first batch's hub (allsource_batch_order)."""
     h = C.config1()
     n = h.n
     for rp, ci in [csr_np(n, *h.layers[0]), O.compose("and", [csr_np(n, *e) for e in h.layers])]:
@@ -206,9 +206,10 @@ def test_levels_per_batch(width):
 def test_levels_per_batch_listed(width):
     """Listed sources are batched by their vertex's degree class (a source
     without arcs with the last class), list positions ascending inside a
-    class: each batch's level count is 1 + the largest eccentricity of its
-    sources (oracle), and the per-source outputs stay at the caller's
-    positions."""
+    class, and below W = 4096 the batches after the first by distance from
+    the first batch's hub (listed_batch_order): each batch's level count is 1
+    + the largest eccentricity of its sources (oracle), and the per-source
+    outputs stay at the caller's positions."""
     h = C.config1()
     n = h.n
     rng = np.random.default_rng(90 + width)
@@ -224,9 +225,7 @@ def test_levels_per_batch_listed(width):
         S, R, _, ecc, _ = O.bfs_sums(rp, ci, sources=src, extras=True)
         assert np.array_equal(out["S"].cpu().numpy(), S)
         assert np.array_equal(out["R"].cpu().numpy(), R)
-        deg = np.diff(rp)[src]
-        cls = np.where(deg > 64, 0, np.where(deg > 0, 7 - np.floor(np.log2(np.maximum(deg, 1))).astype(np.int64), 7))
-        order = np.lexsort((np.arange(k), cls))
+        order = listed_batch_order(rp, ci, src, width, by_distance=width < 4096)
         ref = [1 + int(ecc[order[b * width:(b + 1) * width]].max()) for b in range(nb)]
         assert lv.cpu().numpy().tolist() == ref
 
