@@ -37,11 +37,14 @@
 //
 // Accumulation:
 //   all sources (sources == NULL): the batches take the vertices that have
-//     arcs, in id order (a vertex without arcs reaches only itself); the
-//     graph is undirected, so d(s,v) =
-//     d(v,s) and the vertex v accumulates S[v] += d*popc(new), R[v] +=
-//     popc(new); after all n sources S[v], R[v] are v's own sums.  H2[v]
-//     counts the new bits at d = 2.
+//     arcs (a vertex without arcs reaches only itself); the graph is
+//     undirected, so d(s,v) = d(v,s) and the vertex v accumulates
+//     S[v] += d*popc(new), R[v] += popc(new); after all n sources S[v], R[v]
+//     are v's own sums.  H2[v] counts the new bits at d = 2.
+// Batch order: the first batch takes the sources of the largest degree
+// classes; the later ones by BFS distance from the first batch's hub, which
+// that batch measures (a batch runs 1 + its sources' largest eccentricity
+// levels, and vertices at one distance from a hub have close ones).
 //   listed sources: per-source counts c_i(d) = #{v : bit i new at d} are
 //     gathered per block in LDS and reduced over blocks at the batch end.
 //   listed sources, per-vertex sums (HLN_FLAG_PER_VERTEX): as for all
@@ -623,19 +626,20 @@ __device__ __forceinline__ LevelBufs level_bufs(const BfsArgs& a, const uint64_t
     return B;
 }
 
-// Distance classes of the ranking after the first all-source batch.
+// Distance classes of the ranking after the first batch.
 constexpr int kDistClasses = 32;
 
 __device__ __forceinline__ int dist_class(uint32_t member) {
     return member == 0u ? kDistClasses - 1 : min(static_cast<int>(member) - 1, kDistClasses - 2);
 }
 
-// Re-ranks batch positions [W, n_act) by the distance class of their vertex
-// (member = 1 + distance from the first batch's probe, 0 outside its
-// component), stable: each block counts the classes of its range of
-// positions, then places them after every lower class and every earlier
-// block's equal ones (ballots rank them inside a block), writing the new
-// positions to iperm; perm is then rebuilt from iperm.  Called by every
+// Re-ranks the batch positions [W, n_act) -- the items after the first
+// batch: vertices, or list positions of listed sources -- by the distance
+// class of their vertex (member = 1 + distance from the first batch's probe,
+// 0 outside its component), stable: each block counts the classes of its
+// range of positions, then places them after every lower class and every
+// earlier block's equal ones (ballots rank them inside a block), writing the
+// new positions to iperm; perm is then rebuilt from iperm.  Called by every
 // block of the graph's grid.
 template <int BLOCK, class Barrier>
 __device__ bool rank_by_distance(const BfsArgs& a, Barrier& gb, const unsigned blk, const unsigned nblk, const int W,
