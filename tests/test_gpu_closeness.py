@@ -230,6 +230,33 @@ def test_levels_per_batch_listed(width):
         assert lv.cpu().numpy().tolist() == ref
 
 
+@pytest.mark.parametrize("width", [64, 512])
+def test_levels_listed_duplicates_and_arcless(width):
+    """Listed sources with repeated vertices and vertices without arcs, over
+    a graph of several components: the per-source sums at every list
+    position (oracle), and the per-batch levels in the order
+    listed_batch_order gives (the later batches by distance from the first
+    batch's hub; a repeated vertex keeps its place among equals)."""
+    h = C.config1()
+    n = h.n
+    rp, ci = O.compose("and", [csr_np(n, *e) for e in h.layers])
+    deg = np.diff(rp)
+    rng = np.random.default_rng(5 + width)
+    pool = np.concatenate([rng.choice(n, size=300, replace=False), np.nonzero(deg == 0)[0][:40]])
+    src = rng.choice(pool, size=900, replace=True).astype(np.int32)
+    nb = (len(src) + width - 1) // width
+    lv = torch.zeros(nb, dtype=torch.int32, device="cuda")
+    g = graph_dev(P, rp, ci)
+    out = P.hln_closeness_layer(g, sources=to_dev(src), width_bits=width, levels=lv)
+    torch.cuda.synchronize()
+    P.device_status()
+    S, R, _, ecc, _ = O.bfs_sums(rp, ci, sources=src, extras=True)
+    assert np.array_equal(out["S"].cpu().numpy(), S)
+    assert np.array_equal(out["R"].cpu().numpy(), R)
+    order = listed_batch_order(rp, ci, src, width, by_distance=True)
+    assert lv.cpu().numpy().tolist() == [1 + int(ecc[order[b * width:(b + 1) * width]].max()) for b in range(nb)]
+
+
 @pytest.mark.parametrize("width", [64, 256, 2048, 4096])
 @pytest.mark.parametrize("direction", [1, 2], ids=["top_down", "bottom_up"])
 def test_forced_direction(direction, width):
