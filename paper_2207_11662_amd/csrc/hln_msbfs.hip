@@ -1543,10 +1543,22 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
     return true;
 }
 
+// The work index of block `blk` of `nblk` whose consecutive blocks cycle
+// through `xcds` XCDs (workgroups are dealt to the XCDs in turn): blocks on
+// one XCD take consecutive work indices, so at any moment an XCD's waves
+// hold neighbouring segments (vertices close in id, whose gathers share
+// lines where the graph's ids carry locality).  The identity when the blocks
+// do not divide evenly.
+__device__ __forceinline__ unsigned xcd_work_index(unsigned blk, unsigned nblk, unsigned xcds) {
+    if (xcds <= 1 || nblk % xcds != 0) return blk;
+    return (blk % xcds) * (nblk / xcds) + blk / xcds;
+}
+constexpr unsigned kXcds = 8;
+
 template <int NW, int BLOCK, bool PER_SOURCE>
 __global__ __launch_bounds__(BLOCK) void k_closeness(BfsArgs a) {
     hln::dev::GridBarrier gb{a.bar, a.fault, a.wait_ticks, 0u, 0u, 0u};
-    (void)closeness_run<NW, BLOCK, PER_SOURCE>(a, gb, blockIdx.x, gridDim.x);
+    (void)closeness_run<NW, BLOCK, PER_SOURCE>(a, gb, xcd_work_index(blockIdx.x, gridDim.x, kXcds), gridDim.x);
 }
 
 __global__ void k_zero_ctrl(Ctrl* c, unsigned long long* bar) {
@@ -1578,6 +1590,10 @@ __global__ __launch_bounds__(BLOCK) void k_closeness_multi(const BfsArgs* __rest
     if (i0 >= i1) return;
     const BfsArgs& first = args[plist[i0]];
     hln::dev::PartBarrier gb{first.bar, first.fault, first.wait_ticks, 0u, nblk, blk};
+    // a partition's blocks p, p + np, ... cycle through 8 / gcd(np, 8) XCDs
+    unsigned g8 = np;
+    for (unsigned r = kXcds; r != 0;) { const unsigned t = g8 % r; g8 = r; r = t; }
+    const unsigned work_blk = xcd_work_index(blk, nblk, kXcds / g8);
     for (int i = i0; i < i1; ++i) {
         const BfsArgs a = args[plist[i]];
         if (i > i0) {
@@ -1588,7 +1604,7 @@ __global__ __launch_bounds__(BLOCK) void k_closeness_multi(const BfsArgs* __rest
             }
             if (!gb.wait()) return;
         }
-        if (!closeness_run<NW, BLOCK, PER_SOURCE>(a, gb, blk, nblk)) return;
+        if (!closeness_run<NW, BLOCK, PER_SOURCE>(a, gb, work_blk, nblk)) return;
     }
 }
 
