@@ -1253,15 +1253,41 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                         // the first chunk does not wait for the visited word (no
                         // saturation test); later chunks and rounds use it
                         vis_v = a.vis[base];
-                        acc = Gather<NW>::round_or(fr_rsrc, cur.cid, cur.fl, k, sub, gbase, false, cur.sg.z - cur.sg.y,
-                                                   vis_v);
-                        for (int c = cur.sg.y + Gather<NW>::ROUND; c < cur.sg.z; c += Gather<NW>::ROUND) {
-                            int cid[Gather<NW>::CH];
-                            Mask msk[Gather<NW>::CH];
-                            Gather<NW>::load_ids(B.col, c, cur.sg.z, gl, cid);
-                            Gather<NW>::load_masks(B.flag_fr, cid, msk);
-                            acc |= Gather<NW>::round_or(fr_rsrc, cid, msk, k, sub, gbase, (vis_v | acc) == ~0ull,
-                                                        cur.sg.z - c, vis_v | acc);
+                        if constexpr (NW < 64) {
+                            // Segments longer than a round (ROUND arcs): each
+                            // round's column ids go out with the previous
+                            // round's gathers, so a further round waits for its
+                            // masks and its gathers only.
+                            constexpr int RD = Gather<NW>::ROUND;
+                            const int c1 = cur.sg.y + RD;
+                            int cidn[Gather<NW>::CH];
+                            const bool more = __any(c1 < cur.sg.z);
+                            if (more) Gather<NW>::load_ids(B.col, c1, cur.sg.z, gl, cidn);
+                            acc = Gather<NW>::round_or(fr_rsrc, cur.cid, cur.fl, k, sub, gbase, false, cur.sg.z - cur.sg.y,
+                                                       vis_v);
+                            if (more) {
+                                for (int c = c1; c < cur.sg.z; c += RD) {
+                                    Mask msk[Gather<NW>::CH];
+                                    Gather<NW>::load_masks(B.flag_fr, cidn, msk);
+                                    int cidnn[Gather<NW>::CH];
+                                    Gather<NW>::load_ids(B.col, c + RD, cur.sg.z, gl, cidnn);
+                                    acc |= Gather<NW>::round_or(fr_rsrc, cidn, msk, k, sub, gbase, (vis_v | acc) == ~0ull,
+                                                                cur.sg.z - c, vis_v | acc);
+#pragma unroll
+                                    for (int h = 0; h < Gather<NW>::CH; ++h) cidn[h] = cidnn[h];
+                                }
+                            }
+                        } else {
+                            acc = Gather<NW>::round_or(fr_rsrc, cur.cid, cur.fl, k, sub, gbase, false, cur.sg.z - cur.sg.y,
+                                                       vis_v);
+                            for (int c = cur.sg.y + Gather<NW>::ROUND; c < cur.sg.z; c += Gather<NW>::ROUND) {
+                                int cid[Gather<NW>::CH];
+                                Mask msk[Gather<NW>::CH];
+                                Gather<NW>::load_ids(B.col, c, cur.sg.z, gl, cid);
+                                Gather<NW>::load_masks(B.flag_fr, cid, msk);
+                                acc |= Gather<NW>::round_or(fr_rsrc, cid, msk, k, sub, gbase, (vis_v | acc) == ~0ull,
+                                                            cur.sg.z - c, vis_v | acc);
+                            }
                         }
                     }
                     finish(s, cur.sg, acc, vis_v, cur.flag_old);
