@@ -376,10 +376,12 @@ __device__ __forceinline__ int trace_add(int64_t* row, int verts, long long pair
 // component C (that of the first batch's probe source); a vertex holding one
 // of them lies in C, and once it holds all of them no other source of the
 // batch can ever reach it, so it can gain nothing more in this batch.
+// vis_all: every visited word is stored, not only those with new bits (the
+// first level of a batch whose start did not clear the visited bitset).
 template <int NW, bool PER_SOURCE>
 __device__ __forceinline__ int3 finalize_vertex(const BfsArgs& a, const LevelBufs& B, int v, int d, int k, int sub,
                                                 int gl, int gbase, uint64_t acc, uint64_t vis_v, int32_t* s_cnt,
-                                                MaskT<NW> flag_old, uint64_t gcm_k) {
+                                                MaskT<NW> flag_old, uint64_t gcm_k, bool vis_all = false) {
     using Mask = MaskT<NW>;
     constexpr int LPV = lpv<NW>();
     constexpr Mask kWordMask = static_cast<Mask>(NW >= 64 ? ~0ull : ((1ull << (NW & 63)) - 1ull));
@@ -394,7 +396,7 @@ __device__ __forceinline__ int3 finalize_vertex(const BfsArgs& a, const LevelBuf
     // they held, as the word mask (exact, stored below when it changes) keeps
     // every reader off them
     buf_store_u64_wt(nw, B.nx, (sub == 0 && nw != 0) ? woff : kNoWord);
-    buf_store_u64_wt(vis_v | nw, B.vis, (sub == 0 && nw != 0) ? woff : kNoWord);
+    buf_store_u64_wt(vis_v | nw, B.vis, (sub == 0 && (nw != 0 || vis_all)) ? woff : kNoWord);
     if (PER_SOURCE && sub == 0 && nw) {
         uint64_t b = nw;
         while (b) {
@@ -948,12 +950,19 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
     const unsigned long long gmask = (kLpv >= 64 ? ~0ull : ((1ull << kLpv) - 1ull)) << gbase;
     int trace_row = 0;
     int phase = 0;                                       // list slot of a phase: phase % 3
+    // All sources at W = 4096 with level 1 always bottom-up: level 1 visits
+    // every segment and knows each vertex's visited words without reading
+    // them (the vertex's own source bit), so it stores them all and the batch
+    // start does not clear the visited bitset.  Vertices without arcs are
+    // never read.
+    const bool l1_vis = NW == 64 && !a.listed && (a.alpha == 0 || a.direction == 2);
     for (int b = 0; b < n_batches; ++b) {
         const int src0 = b * W;
         const int cnt = min(W, n_src_eff - src0);
 
-        // ---- batch init: vis = fr = the batch's source bits; the sources'
-        // segments form the first frontier list; no segment is saturated
+        // ---- batch init: vis = fr = the batch's source bits (vis is left to
+        // level 1 when l1_vis holds); the sources' segments form the first
+        // frontier list; no segment is saturated
         bool push;
         {
             const int par = phase & 1;
@@ -986,7 +995,8 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                 __hip_atomic_store(&ctrl->farcs[nx_slot], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             if (!PER_SOURCE && !a.listed) {
-                for (long long i = tid; i < static_cast<long long>(n) * NW; i += nthreads) {
+                for (long long i = l1_vis ? static_cast<long long>(n) * NW : tid; i < static_cast<long long>(n) * NW;
+                     i += nthreads) {
                     const long long v = i / NW;
                     const int kk = static_cast<int>(i % NW);
                     const long long bit = static_cast<long long>(a.iperm[v]) - src0;
@@ -1080,6 +1090,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
         Mask* flag_nx = static_cast<Mask*>(a.flagB);
         for (int d = 1;; ++d) {
             const int par = phase & 1;                   // this phase's list; the previous one is par ^ 1
+            const bool vis1 = l1_vis && d == 1;
             if (blk == 0 && threadIdx.x == 0) {
                 const int nx_slot = (phase + 1) % 3;
                 store_agent_i32(&ctrl->fbad[nx_slot], 0);
@@ -1185,7 +1196,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                     for (int off = NW; off < kLpv; off <<= 1) acc |= shfl_xor_u64(acc, off);
                     if (nseg == 1) {
                         const int3 cw = finalize_vertex<NW, PER_SOURCE>(a, B, v, d, k, sub, gl, gbase, acc, vis_v,
-                                                                        s_cnt, flag_old, gcm_k);
+                                                                        s_cnt, flag_old, gcm_k, vis1);
                         if (cw.x) {
                             any = 1;
                             t_pairs += cw.x;
@@ -1219,7 +1230,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                             const Mask flag_old = flag_nx[v];
                             if (gl == 0) store_agent_i32(&a.hcnt[v], 0);
                             const int3 cw = finalize_vertex<NW, PER_SOURCE>(a, B, v, d, k, sub, gl, gbase, full, vis_v,
-                                                                            s_cnt, flag_old, gcm_k);
+                                                                            s_cnt, flag_old, gcm_k, vis1);
                             if (cw.x) {
                                 any = 1;
                                 t_pairs += cw.x;
