@@ -262,7 +262,7 @@ struct BfsArgs {
     uint32_t* member;                 // n: 1 when the vertex lies in the probe source's component
     int64_t* part;                    // per-source mode: [grid][2][W] block partials
     int64_t* S;
-    uint32_t* S32;                    // n: this batch's distance sums (levels below kS32Levels), folded into S
+    uint32_t* S32;                    // n: distance sums since the last fold (levels below kS32Levels), folded into S
     int32_t* R;
     int32_t* H2;
     double* cc;
@@ -956,6 +956,12 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
     // start does not clear the visited bitset.  Vertices without arcs are
     // never read.
     const bool l1_vis = NW == 64 && !a.listed && (a.alpha == 0 || a.direction == 2);
+    // Per-vertex sums: a batch adds less than W * min(n, s32_levels) to a
+    // vertex's 32-bit sum (fewer than W new bits, at depths below both), so
+    // the 32-bit sums are folded into S only before a batch that could carry
+    // them past 2^32 - 1, and at the end.
+    const unsigned long long s32_cap = static_cast<unsigned long long>(W) * static_cast<unsigned long long>(min(n, a.s32_levels));
+    unsigned long long s32_pend = 0;                     // bound on every S32 entry
     for (int b = 0; b < n_batches; ++b) {
         const int src0 = b * W;
         const int cnt = min(W, n_src_eff - src0);
@@ -966,6 +972,8 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
         bool push;
         {
             const int par = phase & 1;
+            const bool fold = s32_pend + s32_cap > 0xFFFFFFFFull;
+            s32_pend = fold ? s32_cap : s32_pend + s32_cap;
             for (long long i = tid; i < n_seg; i += nthreads) a.segsat[i] = 0u;
             // Saturation is judged against the component C of a probe: the
             // first batch's source of highest degree (ties: the first), whose
@@ -977,6 +985,10 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                 bool in = false;
                 if (i < cnt) {
                     const int src = a.listed ? a.sources[a.perm[src0 + i]] : a.perm[src0 + i];
+                    // all sources: the source's own frontier bit (frontier
+                    // words are read only where the word mask has the bit, so
+                    // only the sources' own words are written)
+                    if (!PER_SOURCE && !a.listed) a.bufA[static_cast<size_t>(src) * NW + (i >> 6)] = 1ull << (i & 63);
                     if (b == 0) {
                         const unsigned long long deg = static_cast<unsigned long long>(a.row_ptr[src + 1] - a.row_ptr[src]);
                         __hip_atomic_fetch_max(&ctrl->probe_key, (deg << 32) | (0xffffffffull - static_cast<unsigned long long>(i)),
@@ -1004,25 +1016,24 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                     if (bit >= 0 && bit < cnt && (bit >> 6) == kk) w0 = 1ull << (bit & 63);
                     a.vis[i] = w0;
                 }
-                // frontier words are read only where the word mask has the bit,
-                // so only the sources' own words are written
-                for (long long i = tid; i < cnt; i += nthreads)
-                    a.bufA[static_cast<size_t>(a.perm[src0 + i]) * NW + (i >> 6)] = 1ull << (i & 63);
                 for (long long v = tid; v < n; v += nthreads) {
                     const int j = a.iperm[v] - src0;
                     static_cast<Mask*>(a.flagA)[v] =
                         (j >= 0 && j < cnt) ? static_cast<Mask>(static_cast<Mask>(1) << (j >> 6)) : Mask(0);
-                    // the previous batch's 32-bit sums into S
-                    const uint32_t x = a.S32[v];
-                    if (x) {
-                        a.S[v] += x;
-                        a.S32[v] = 0;
+                    // the earlier batches' 32-bit sums into S
+                    if (fold) {
+                        const uint32_t x = a.S32[v];
+                        if (x) {
+                            a.S[v] += x;
+                            a.S32[v] = 0;
+                        }
                     }
                 }
-                for (long long i = tid_x; i < cnt; i += nthreads) {
-                    const int3 sg = vertex_segments(a, a.perm[src0 + i]);
-                    if (lists && sg.y > 0) frontier_note(s_fr, par, sg.x, sg.y, sg.z);
-                }
+                if (lists)
+                    for (long long i = tid_x; i < cnt; i += nthreads) {
+                        const int3 sg = vertex_segments(a, a.perm[src0 + i]);
+                        if (sg.y > 0) frontier_note(s_fr, par, sg.x, sg.y, sg.z);
+                    }
             } else {
                 for (long long i = tid; i < static_cast<long long>(n) * NW; i += nthreads) a.vis[i] = 0;
                 // only the words the sources' bits go to are cleared
@@ -1030,8 +1041,8 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
                     a.bufA[static_cast<size_t>(a.sources[a.perm[src0 + i]]) * NW + (i >> 6)] = 0;
                 for (long long v = tid; v < n; v += nthreads) {
                     static_cast<Mask*>(a.flagA)[v] = 0;
-                    if (!PER_SOURCE) {
-                        // per-vertex sums: the previous batch's 32-bit sums into S
+                    if (!PER_SOURCE && fold) {
+                        // per-vertex sums: the earlier batches' 32-bit sums into S
                         const uint32_t x = a.S32[v];
                         if (x) {
                             a.S[v] += x;
