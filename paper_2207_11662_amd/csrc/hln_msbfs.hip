@@ -957,7 +957,7 @@ __device__ __forceinline__ bool closeness_run(const BfsArgs& a, Barrier& gb, con
     // never read.
     const bool l1_vis = NW == 64 && !a.listed && (a.alpha == 0 || a.direction == 2);
     // Per-vertex sums: a batch adds less than W * min(n, s32_levels) to a
-    // vertex's 32-bit sum (fewer than W new bits, at depths below both), so
+    // vertex's 32-bit sum (at most W new bits, at depths below both), so
     // the 32-bit sums are folded into S only before a batch that could carry
     // them past 2^32 - 1, and at the end.
     const unsigned long long s32_cap = static_cast<unsigned long long>(W) * static_cast<unsigned long long>(min(n, a.s32_levels));
